@@ -1,0 +1,193 @@
+/*
+ * mapper_gpu.h -- C ABI of the MI355X mapper library (libmapper_gpu.so).
+ *
+ * The library computes the mapper graph of Singh, Memoli and Carlsson as used
+ * by Zhou et al., "Mapper Interactive" (Background section): given a point
+ * cloud X in R^d, a filter (lens) f : X -> R or R^2, a cover of f(X) by n
+ * intervals per axis with fractional overlap p, and DBSCAN (Ester et al.)
+ * parameters eps and minPts, it clusters each pullback set f^{-1}(V_k) with
+ * the Euclidean metric and returns the 1-D nerve of the clusters: one node per
+ * cluster, one edge per pair of clusters that share a point.
+ *
+ * The parameter set mirrors the paper's command-line API (Implementation
+ * section: number of intervals, overlap, DBSCAN parameters); 2-D covers take
+ * per-axis (n, p) as in the breast-cancer use case.
+ *
+ * Conventions for every call:
+ *   - no C++ exception crosses this boundary; every fallible call returns a
+ *     mapper_status, and on failure mapper_last_error() describes it;
+ *   - pointers documented as "device" are HIP device pointers on the
+ *     context's device; "host" pointers are ordinary process memory;
+ *   - the caller keeps ownership of every buffer it passes in; the library
+ *     copies what it keeps (clouds, lens directions, lens values);
+ *   - all device memory the library uses comes from the caller's arena
+ *     (mapper_context_create); it never calls hipMalloc itself;
+ *   - all device work is issued on the caller's stream(s).
+ *
+ * Exactness: the returned graph is identical, bit for bit, to the one defined
+ * by the following readings (the paper leaves these points open):
+ *   lens        canonical FP64 values: column x_c; L-inf max|x_j|; L2 the
+ *               correctly rounded sqrt of sum_j x_j^2 accumulated in order in
+ *               FP64; projection sum_j x_j v_j accumulated in order in FP64;
+ *   cover       L = (M-m)/(n-(n-1)p), s = L(1-p), lo_k = m + k s,
+ *               hi_k = lo_k + L, hi_{n-1} = M, closed intervals, FP64;
+ *   distance    D(x,y) = fma chain over j of (x_j - y_j)^2 in FP64, in order;
+ *               neighbours iff D <= fl(eps*eps); a point neighbours itself;
+ *   DBSCAN      core iff #neighbours >= minPts; clusters = connected
+ *               components of core points; a non-core point with core
+ *               neighbours joins the lowest-numbered adjacent cluster, else it
+ *               is noise (dropped);
+ *   labelling   clusters of an element numbered by their smallest core index;
+ *               nodes ordered by (element, cluster); element id k1*n2 + k2 in
+ *               2-D; members ascending; edges (a<b) lexicographic; weight =
+ *               number of shared points.
+ * Distance tiles may run in BF16/FP16 on the matrix cores; every pair whose
+ * tile distance lies within a rigorous error band of eps^2 is re-decided with
+ * the FP64 distance above, so the precision never changes the graph.
+ */
+#ifndef MAPPER_GPU_H
+#define MAPPER_GPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MAPPER_OK = 0,
+    MAPPER_EINVAL = -1,     /* invalid argument; nothing was launched */
+    MAPPER_ENOMEM = -2,     /* the arena cannot hold the run's workspace */
+    MAPPER_EDEVICE = -3,    /* a HIP call failed */
+    MAPPER_EBUSY = -4,      /* object still in use (e.g. cloud with requests in flight) */
+    MAPPER_ETIMEDOUT = -5,  /* mapper_wait timed out; the request keeps running */
+    MAPPER_ENOTIMPL = -6
+} mapper_status;
+
+typedef enum {
+    MAPPER_LENS_COLUMN = 0,      /* f(x) = x_column */
+    MAPPER_LENS_L2 = 1,          /* f(x) = ||x||_2 */
+    MAPPER_LENS_LINF = 2,        /* f(x) = max_j |x_j| */
+    MAPPER_LENS_PROJECTION = 3,  /* f(x) = <x, direction> */
+    MAPPER_LENS_VALUES = 4       /* f given per point */
+} mapper_lens_kind;
+
+typedef enum {
+    MAPPER_PREC_FP32 = 0,    /* FP32 matrix-core tiles */
+    MAPPER_PREC_BF16 = 1,    /* one BF16 product per pair, FP32 accumulate */
+    MAPPER_PREC_BF16X3 = 2,  /* BF16 hi/lo split, three products */
+    MAPPER_PREC_FP16 = 3,    /* one FP16 product per pair */
+    MAPPER_PREC_FP16X3 = 4,  /* FP16 hi/lo split, three products */
+    MAPPER_PREC_AUTO = 5     /* chosen per run by the tile autotuner */
+} mapper_precision;
+
+/* One lens axis and its cover (Background section: filter f, number of
+ * intervals n, overlap p). */
+typedef struct {
+    int32_t kind;            /* mapper_lens_kind */
+    int32_t column;          /* COLUMN: 0 <= column < d */
+    const float *direction;  /* PROJECTION: d floats, host; copied */
+    const double *values;    /* VALUES: n doubles, host; copied; finite */
+    int32_t n_intervals;     /* >= 1 */
+    double overlap;          /* 0 <= overlap < 1 */
+} mapper_axis;
+
+typedef struct {
+    int32_t n_axes;          /* 1 (1-D mapper) or 2 (2-D mapper) */
+    mapper_axis axis[2];
+    double eps;              /* DBSCAN eps, finite, >= 0 */
+    int32_t min_pts;         /* DBSCAN minPts, >= 1 */
+    int32_t precision;       /* mapper_precision */
+    uint32_t flags;          /* MAPPER_FLAG_* */
+} mapper_params;
+
+#define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
+
+typedef struct mapper_context mapper_context;
+typedef struct mapper_cloud mapper_cloud;
+typedef struct mapper_graph mapper_graph;
+
+typedef struct {
+    double ms_total, ms_lens, ms_bin, ms_tiles, ms_recheck, ms_cc, ms_edges;
+    int64_t n_slots;         /* sum over elements of |f^{-1}(V_k)| */
+    int64_t pairs;           /* unordered in-element pairs, self included */
+    int64_t tiles;           /* tile pairs launched */
+    int64_t band_pairs;      /* pairs re-decided in FP64 */
+    int64_t bitmask_bytes;   /* adjacency bitmask written */
+    uint64_t arena_peak_bytes;
+    int32_t precision;       /* precision actually used */
+    int32_t tile_m, tile_n, split_terms;
+    int32_t tile_launches;   /* > 1 if the band list had to grow */
+    double band_halfwidth;   /* largest FP32 half-width of the eps^2 band */
+} mapper_run_stats;
+
+/* --- context ------------------------------------------------------------
+ * device: HIP device ordinal.  arena: device buffer of arena_bytes (256-byte
+ * aligned) that the library sub-allocates; it stays owned by the caller and
+ * must outlive the context.  stream: hipStream_t for all work (NULL = the
+ * null stream). */
+mapper_status mapper_context_create(int device, void *arena, uint64_t arena_bytes,
+                                    void *stream, mapper_context **out);
+/* Streams for concurrent requests (mapper_submit): count hipStream_t handles,
+ * owned by the caller.  Without this call requests use the context stream. */
+mapper_status mapper_context_set_streams(mapper_context *ctx, void *const *streams, int count);
+void mapper_context_destroy(mapper_context *ctx);
+/* Message for the last failure on this thread (never NULL). */
+const char *mapper_last_error(void);
+/* Bytes of arena currently in use and the high-water mark. */
+mapper_status mapper_context_memory(const mapper_context *ctx, uint64_t *in_use, uint64_t *peak);
+
+/* --- point clouds ---------------------------------------------------------
+ * points: n x d float32 row-major, host (points_on_device = 0) or device
+ * (= 1).  The cloud is copied into the arena and stays resident until
+ * mapper_cloud_destroy.  Non-finite coordinates -> MAPPER_EINVAL. */
+mapper_status mapper_cloud_create(mapper_context *ctx, const float *points, int64_t n,
+                                  int32_t d, int32_t points_on_device, mapper_cloud **out);
+mapper_status mapper_cloud_destroy(mapper_cloud *cloud);   /* MAPPER_EBUSY while in use */
+
+/* --- one mapper graph, synchronous ------------------------------------- */
+mapper_status mapper_run(mapper_context *ctx, const mapper_cloud *cloud,
+                         const mapper_params *params, mapper_graph **out);
+
+/* --- serving: continuous batching of requests ---------------------------
+ * submit returns at once with a ticket; requests are admitted while their
+ * workspace fits in the arena and a stream slot is free, and run
+ * concurrently.  wait blocks up to timeout_us (< 0: forever) and hands over
+ * the graph.  A request's graph never depends on what else runs. */
+mapper_status mapper_submit(mapper_context *ctx, const mapper_cloud *cloud,
+                            const mapper_params *params, uint64_t *ticket);
+mapper_status mapper_wait(mapper_context *ctx, uint64_t ticket, int64_t timeout_us,
+                          mapper_graph **out);
+
+/* --- graph (host memory owned by the graph) ---------------------------- */
+int64_t mapper_graph_num_nodes(const mapper_graph *g);
+int64_t mapper_graph_num_edges(const mapper_graph *g);
+const int32_t *mapper_graph_node_element(const mapper_graph *g);  /* N element ids */
+const int64_t *mapper_graph_node_offsets(const mapper_graph *g);  /* N+1 */
+const int32_t *mapper_graph_node_members(const mapper_graph *g);  /* ascending point ids */
+const int32_t *mapper_graph_edges(const mapper_graph *g);         /* 2E: (a,b), a<b, sorted */
+const int32_t *mapper_graph_edge_weights(const mapper_graph *g);  /* E shared-point counts */
+mapper_status mapper_graph_stats(const mapper_graph *g, mapper_run_stats *out);
+
+/* Per-stage arrays, present when MAPPER_FLAG_DEBUG_STAGES was set.
+ * name: "lens" (double, n*n_axes, axis-major), "lo", "hi" (double, endpoints
+ * of all axes concatenated), "elem_offsets" (int64, E+1), "elem_members"
+ * (int32), "slot_count" (int32), "slot_core" (uint8), "slot_node" (int32).
+ * Returns the host pointer and element count, or NULL if absent. */
+const void *mapper_graph_stage(const mapper_graph *g, const char *name, int64_t *count);
+void mapper_graph_destroy(mapper_graph *g);
+
+/* --- test hook -------------------------------------------------------------
+ * Gram values of the distance tiles: for the rows `rows` (host, nrows point
+ * ids of the cloud) runs the tile kernel of the given precision on them as one
+ * cover element and writes, host, out_d2[i*nrows + j] = the FP32 tile squared
+ * distance n_i + n_j - 2 g_ij rescaled to the cloud's units, and
+ * out_band[i*nrows+j] = the half-width of the certified band around it. */
+mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_cloud *cloud,
+                                   const int32_t *rows, int32_t nrows, int32_t precision,
+                                   double eps, double *out_d2, double *out_band);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAPPER_GPU_H */

@@ -1,0 +1,221 @@
+// bin.hip -- pullback sets of the cover and packed distance panels.
+//
+// Membership (Background section): point i lies in interval k of an axis iff
+// lo_k <= f_i <= hi_k.  The endpoint sequences are non-decreasing (lo_k by
+// construction, hi_k after clamping to the lens maximum, which no point
+// exceeds), so the intervals holding a point form one contiguous index range
+// per axis, found by two binary searches.  Each point emits its (element,
+// point) pairs in ascending element order; a stable radix sort by element then
+// lists every element's members in ascending point order.
+//
+// Packing copies each member row into a per-slot panel in the matrix-core
+// input format (FP32, or BF16/FP16 with an optional low part), scaled by a
+// power of two so that every FP32 intermediate stays far from overflow and
+// underflow, and computes the per-slot thresholds that let the tile epilogue
+// decide "certainly a neighbour" / "certainly not" with two adds and two
+// compares per pair.
+#include "internal.h"
+
+namespace mgpu {
+
+namespace {
+
+__device__ __forceinline__ int first_ge(const double *a, int n, double f) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] >= f) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int last_le(const double *a, int n, double f) {
+    int lo = 0, hi = n;           // count of entries <= f
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= f) lo = mid + 1; else hi = mid;
+    }
+    return lo - 1;
+}
+
+__global__ void k_member_count(const double *f0, const double *f1, int64_t n,
+                               const double *lo0, const double *hc0, int32_t n0,
+                               const double *lo1, const double *hc1, int32_t n1,
+                               int32_t *range4, int32_t *count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = f0[i];
+    const int kl0 = first_ge(hc0, n0, a), kh0 = last_le(lo0, n0, a);
+    int c = kh0 >= kl0 ? kh0 - kl0 + 1 : 0;
+    int kl1 = 0, kh1 = 0;
+    if (f1) {
+        const double b = f1[i];
+        kl1 = first_ge(hc1, n1, b);
+        kh1 = last_le(lo1, n1, b);
+        c *= kh1 >= kl1 ? kh1 - kl1 + 1 : 0;
+    }
+    range4[4 * i + 0] = kl0;
+    range4[4 * i + 1] = kh0;
+    range4[4 * i + 2] = kl1;
+    range4[4 * i + 3] = kh1;
+    count[i] = c;
+}
+
+__global__ void k_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
+                              int two_d, uint64_t *keys, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t p = pos[i];
+    const int kl0 = range4[4 * i], kh0 = range4[4 * i + 1];
+    const int kl1 = two_d ? range4[4 * i + 2] : 0, kh1 = two_d ? range4[4 * i + 3] : 0;
+    for (int k0 = kl0; k0 <= kh0; ++k0)
+        for (int k1 = kl1; k1 <= kh1; ++k1) {
+            keys[p] = (uint64_t)((int64_t)k0 * (two_d ? n1 : 1) + k1);
+            vals[p] = (uint32_t)i;
+            ++p;
+        }
+}
+
+// ------------------------------------------------------------------ packing
+
+// Round to nearest even BF16; results below the smallest normal are flushed
+// to zero so the matrix cores never see denormals.
+__device__ __forceinline__ float bf16_round(float x, uint16_t *bits) {
+    uint32_t u = __float_as_uint(x);
+    uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    if ((r & 0x7f800000u) == 0) r = 0;          // zero or denormal
+    *bits = (uint16_t)(r >> 16);
+    return __uint_as_float(r);
+}
+
+__device__ __forceinline__ float fp16_round(float x, uint16_t *bits) {
+    _Float16 h = (_Float16)x;                    // round to nearest even
+    float hv = (float)h;
+    if (fabsf(hv) < 6.103515625e-05f) { h = (_Float16)0.0f; hv = 0.0f; }
+    uint16_t b;
+    __builtin_memcpy(&b, &h, 2);
+    *bits = b;
+    return hv;
+}
+
+__device__ __forceinline__ double gam(double k) {
+    const double u = 0x1.0p-23;                 // covers RNE and truncating accumulators
+    return k * u / (1.0 - k * u);
+}
+
+// Next float towards +inf / -inf (finite inputs).
+__device__ __forceinline__ float next_up(float f) {
+    if (f == 0.0f) return __uint_as_float(1u);
+    const uint32_t b = __float_as_uint(f);
+    return __uint_as_float(f > 0.0f ? b + 1u : b - 1u);
+}
+
+__device__ __forceinline__ float next_down(float f) { return -next_up(-f); }
+
+__device__ __forceinline__ float round_up_f(double v) {
+    float f = (float)v;
+    if ((double)f < v) f = next_up(f);
+    return f;
+}
+
+__device__ __forceinline__ float round_dn_f(double v) {
+    float f = (float)v;
+    if ((double)f > v) f = next_down(f);
+    return f;
+}
+
+__global__ void __launch_bounds__(256) k_pack(PackArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (s >= a.n_slots) return;
+    const float *x = a.X + (int64_t)a.slot_point[s] * a.d;
+    const bool split = a.prec == P_BF16X3 || a.prec == P_FP16X3;
+    const bool bf = a.prec == P_BF16 || a.prec == P_BF16X3;
+    double nx = 0, hh = 0, ll = 0, xt = 0, rr = 0;
+    for (int j = lane; j < a.dp; j += WAVE) {
+        const float xs = j < a.d ? (float)((double)x[j] * a.scale) : 0.0f;   // exact power-of-two scaling
+        const double xd = (double)xs;
+        nx += xd * xd;
+        if (a.prec == P_FP32) {
+            ((float *)a.panel_hi)[s * a.dp + j] = xs;
+            continue;
+        }
+        uint16_t hb, lb = 0;
+        const float h = bf ? bf16_round(xs, &hb) : fp16_round(xs, &hb);
+        ((uint16_t *)a.panel_hi)[s * a.dp + j] = hb;
+        double lo = 0.0;
+        if (split) {
+            const float rem = xs - h;            // exact in FP32
+            lo = (double)(bf ? bf16_round(rem, &lb) : fp16_round(rem, &lb));
+            ((uint16_t *)a.panel_lo)[s * a.dp + j] = lb;
+        }
+        const double hd = (double)h, r = xd - hd - lo;   // exact in FP64
+        hh += hd * hd;
+        ll += lo * lo;
+        xt += (hd + lo) * (hd + lo);
+        rr += r * r;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nx += __shfl_xor(nx, o, WAVE);
+        hh += __shfl_xor(hh, o, WAVE);
+        ll += __shfl_xor(ll, o, WAVE);
+        xt += __shfl_xor(xt, o, WAVE);
+        rr += __shfl_xor(rr, o, WAVE);
+    }
+    if (lane != 0) return;
+    // Per-slot share e_s of the bound |g_ij - x_i.x_j| <= e_i + e_j on the tile's
+    // Gram value (every product bound made separable with a*b <= (l a^2 + b^2/l)/2).
+    const double K = (double)a.dp;
+    double e;
+    if (a.prec == P_FP32) {
+        e = gam(2 * K + 2) * nx * 0.5;                    // rounded products + sums
+    } else if (!split) {
+        const double rho = bf ? 0x1.0p-9 : 0x1.0p-12;     // nominal relative residual
+        e = gam(K + 2) * hh * 0.5                         // exact products, FP32 sums
+            + (rho * hh + rr / rho + rr) * 0.5;           // x.r_y + r_x.y + r_x.r_y
+    } else {
+        const double rho = bf ? 0x1.0p-17 : 0x1.0p-23;    // residual after hi + lo
+        const double rl = bf ? 0x1.0p-8 : 0x1.0p-11;      // |lo| / |hi|
+        e = gam(K + 2) * hh * 0.5                         // hi.hi accumulator
+            + gam(2 * K + 2) * (rl * hh + ll / rl) * 0.5  // cross accumulator
+            + 0x1.0p-23 * xt * 0.5                        // adding the two accumulators
+            + ll * 0.5                                    // dropped lo.lo
+            + (rho * xt + rr / rho + rr) * 0.5;           // residual beyond hi + lo
+    }
+    e += 0x1.0p-40 * nx + (3 * K + 8) * 0x1.0p-110;       // FP64 norm / distance rounding, underflow
+    const double Eh = a.E_scaled * 0.5;
+    const double A = (nx + 2 * e - Eh) * 0.5;               // g >= A_i + A_j  =>  D <= eps^2
+    const double B = (nx - 2 * e - Eh) * 0.5;               // g <  B_i + B_j  =>  D >  eps^2
+    a.thrA[s] = round_up_f(A + 0x1.0p-22 * fabs(A));
+    a.thrB[s] = round_dn_f(B - 0x1.0p-22 * fabs(B));
+    if (a.dbg_norm2) a.dbg_norm2[s] = nx;
+    if (a.dbg_e) a.dbg_e[s] = e;
+}
+
+}  // namespace
+
+hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
+                               const double *lo0, const double *hc0, int32_t n0,
+                               const double *lo1, const double *hc1, int32_t n1,
+                               int32_t *range4, int32_t *count, hipStream_t s) {
+    k_member_count<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
+        f0, f1, n, lo0, hc0, n0, lo1, hc1, n1, range4, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
+                              int two_d, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+    k_member_emit<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(range4, pos, n, n1, two_d,
+                                                                         keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
+    if (a.n_slots <= 0) return hipSuccess;
+    const int64_t blocks = (a.n_slots + 3) / 4;
+    k_pack<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace mgpu

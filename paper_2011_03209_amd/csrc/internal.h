@@ -1,0 +1,136 @@
+// internal.h -- declarations shared by the host runtime and the HIP kernels of
+// libmapper_gpu.  Not part of the public ABI (include/mapper_gpu.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace mgpu {
+
+// ---------------------------------------------------------------- tiling
+// Distance tiles are TILE x TILE blocks of one cover element's members.
+constexpr int TILE = 128;
+constexpr int TILE_WORDS = TILE * TILE / 32;      // uint32 words of one bitmask block
+constexpr int WAVE = 64;
+
+enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_BF16X3 = 2, P_FP16 = 3, P_FP16X3 = 4 };
+
+inline bool prec_is_split(int p) { return p == P_BF16X3 || p == P_FP16X3; }
+inline bool prec_is_16bit(int p) { return p != P_FP32; }
+inline bool prec_is_bf16(int p) { return p == P_BF16 || p == P_BF16X3; }
+
+// Work table of the distance-tile launch.  Items are the tile pairs (I <= J)
+// of all elements, grouped by element in the order `order` (largest first).
+struct TileTable {
+    const int64_t *item_off;   // [nord+1] first item of each ordered element
+    const int32_t *order;      // [nord] element id of each ordered entry
+    const int64_t *elem_off;   // [E+1] first slot of each element
+    const int64_t *blk_off;    // [E] first bitmask block of each element
+    int32_t nord;
+    int64_t n_items;
+};
+
+// One pair whose tile distance fell inside the certified band of eps^2.
+struct BandPair {
+    int32_t si, sj;            // slots (global member positions)
+    uint64_t bit;              // bit index in the bitmask
+};
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `s` and returns hipSuccess or the launch error.
+
+// lens.hip
+hipError_t launch_check_cloud(const float *X, int64_t count, uint32_t *flags_maxabs, hipStream_t s);
+hipError_t launch_lens(const float *X, int64_t n, int32_t d, int kind, int32_t column,
+                       const float *dir, const double *values, double *f, hipStream_t s);
+hipError_t launch_range(const double *f, int64_t n, unsigned long long *keys2, hipStream_t s);
+
+// prims.hip
+size_t scan_temp_bytes(int64_t n);
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total), int64.
+hipError_t launch_scan_i32(const int32_t *in, int64_t *out, int64_t n, void *temp, hipStream_t s);
+hipError_t launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, void *temp, hipStream_t s);
+hipError_t launch_scan_u8(const uint8_t *in, int64_t *out, int64_t n, void *temp, hipStream_t s);
+size_t sort_temp_bytes(int64_t n);
+// Stable LSD radix sort of (key, value) by the low key_bits of key.  Uses the
+// *_alt buffers as ping-pong space; returns in *result_in_alt whether the
+// sorted data ended in the alt buffers.
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
+                            uint32_t *vals_alt, int64_t n, int key_bits, void *temp,
+                            bool *result_in_alt, hipStream_t s);
+// out[v] = first index i in sorted keys[0..n) with keys[i] >= v, v in [0, nv].
+hipError_t launch_lower_bounds(const uint64_t *keys, int64_t n, int64_t nv, int64_t *out,
+                               hipStream_t s);
+
+// bin.hip
+hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
+                               const double *lo0, const double *hc0, int32_t n0,
+                               const double *lo1, const double *hc1, int32_t n1,
+                               int32_t *range4, int32_t *count, hipStream_t s);
+hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
+                              int two_d, uint64_t *keys, uint32_t *vals, hipStream_t s);
+struct PackArgs {
+    const float *X; int32_t d; int32_t dp;
+    const uint32_t *slot_point; int64_t n_slots;
+    int prec;
+    double scale;              // power of two applied to coordinates
+    double E_scaled;           // eps^2 * scale^2
+    void *panel_hi; void *panel_lo;
+    float *thrA; float *thrB;  // in-threshold / out-threshold of each slot
+    double *dbg_norm2;         // optional: |x_s|^2 (scaled)
+    double *dbg_e;             // optional: e_s, the slot's share of the Gram error bound (scaled)
+};
+hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+
+// tile.hip
+struct TileArgs {
+    TileTable tt;
+    const void *panel_hi; const void *panel_lo; int32_t dp;
+    const float *thrA; const float *thrB;
+    uint32_t *bitmask; int32_t *count;
+    BandPair *band; unsigned long long *band_n; int64_t band_cap;
+    float *debug_g;            // non-null: write raw Gram values (debug, one element)
+    int64_t debug_ld;
+    unsigned int *queue;       // work counters (persistent launch)
+    int grid;                  // number of workgroups launched
+};
+hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
+int tile_grid_size(int prec, int64_t n_items);
+hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
+                          const uint32_t *slot_point, double E, uint32_t *bitmask,
+                          int32_t *count, hipStream_t s);
+hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
+                            double *out, hipStream_t s);
+hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, const float *X,
+                           int32_t d, double *out, hipStream_t s);
+
+// graph.hip
+hipError_t launch_cc_init(int32_t *parent, int64_t n_slots, hipStream_t s);
+hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
+                           int32_t min_pts, int32_t *parent, hipStream_t s);
+hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
+                             uint8_t *isroot, int64_t n_slots, hipStream_t s);
+hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent,
+                           const int64_t *root_rank, const uint64_t *slot_elem,
+                           int32_t *node, int32_t *node_elem, int64_t n_slots, hipStream_t s);
+hipError_t launch_border(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
+                         int32_t min_pts, int32_t *node, hipStream_t s);
+hipError_t launch_member_pairs(const int32_t *node, const uint32_t *slot_point,
+                               const int64_t *pos, int64_t n_slots, uint64_t *keys,
+                               uint32_t *vals, hipStream_t s);
+hipError_t launch_flag_labelled(const int32_t *node, uint8_t *flag, int64_t n_slots, hipStream_t s);
+hipError_t launch_edge_counts(const uint64_t *pt_keys, int64_t m, int32_t *pairs_per_item,
+                              hipStream_t s);
+hipError_t launch_edge_emit(const uint64_t *pt_keys, const uint32_t *pt_nodes, int64_t m,
+                            const int64_t *pos, int64_t n_nodes, uint64_t *ekeys, hipStream_t s);
+hipError_t launch_run_starts(const uint64_t *keys, int64_t m, uint8_t *flag, hipStream_t s);
+hipError_t launch_edge_compact(const uint64_t *keys, int64_t m, const int64_t *rank,
+                               int64_t n_nodes, int32_t *edges, int32_t *weights, hipStream_t s);
+hipError_t launch_node_offsets_from_sorted(const uint64_t *keys, int64_t m, int64_t n_nodes,
+                                           int64_t *node_off, hipStream_t s);
+hipError_t launch_widen_u32(const uint32_t *in, uint64_t *out, int64_t n, hipStream_t s);
+hipError_t launch_narrow_u64(const uint64_t *in, uint32_t *out, int64_t n, hipStream_t s);
+hipError_t launch_u32_to_i32(const uint32_t *in, int32_t *out, int64_t n, hipStream_t s);
+
+}  // namespace mgpu

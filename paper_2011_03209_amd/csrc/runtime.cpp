@@ -1,0 +1,1139 @@
+// runtime.cpp -- host side of libmapper_gpu: the C ABI of include/mapper_gpu.h.
+//
+// One mapper_run is a fixed sequence of device stages on one stream (lens ->
+// range -> cover -> pullback sets -> panels -> distance tiles -> FP64 band
+// recheck -> components -> labels -> border -> nodes/edges).  The host reads
+// back only what sizes the next stage: the lens range (to place the interval
+// endpoints), the element sizes (to lay out tiles and the bitmask), the band
+// count and the node/edge counts, then the finished graph.
+//
+// Device memory is sub-allocated from the caller's arena (first fit, 256-byte
+// aligned).  Requests submitted for serving run on worker threads, one per
+// caller-provided stream; a request that cannot get its workspace releases
+// everything it holds and waits for memory to be returned, so admission never
+// deadlocks.
+#include "internal.h"
+#include "../../include/mapper_gpu.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace mgpu;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+mapper_status fail(mapper_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+struct DevError {
+    hipError_t e;
+    int line;
+};
+
+#define HIPCHK(x)                                                        \
+    do {                                                                 \
+        hipError_t _e = (x);                                             \
+        if (_e != hipSuccess) throw DevError{_e, __LINE__};              \
+    } while (0)
+
+struct NoMem {
+    uint64_t want;
+};
+
+// ------------------------------------------------------------------ arena
+class Arena {
+  public:
+    void init(char *base, uint64_t bytes) {
+        base_ = base;
+        size_ = bytes;
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+    }
+    // First fit; returns nullptr if no block fits.
+    void *alloc(uint64_t bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
+        return alloc_locked(bytes);
+    }
+    void release(void *p) {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            uint64_t off = (uint64_t)((char *)p - base_);
+            auto it = used_.find(off);
+            if (it == used_.end()) return;
+            uint64_t sz = it->second;
+            used_.erase(it);
+            in_use_ -= sz;
+            auto nx = free_.lower_bound(off);
+            if (nx != free_.end() && off + sz == nx->first) {
+                sz += nx->second;
+                nx = free_.erase(nx);
+            }
+            if (nx != free_.begin()) {
+                auto pv = std::prev(nx);
+                if (pv->first + pv->second == off) {
+                    pv->second += sz;
+                    ++epoch_;
+                    cv_.notify_all();
+                    return;
+                }
+            }
+            free_[off] = sz;
+            ++epoch_;
+        }
+        cv_.notify_all();
+    }
+    uint64_t in_use() const { return in_use_; }
+    uint64_t peak() const { return peak_; }
+    uint64_t epoch() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return epoch_;
+    }
+    // Wait until memory is returned after `seen` or the timeout passes.
+    void wait_release(uint64_t seen, int ms) {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait_for(lk, std::chrono::milliseconds(ms), [&] { return epoch_ != seen; });
+    }
+
+  private:
+    void *alloc_locked(uint64_t bytes) {
+        bytes = (bytes + 255) & ~(uint64_t)255;
+        if (bytes == 0) bytes = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const uint64_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_[off] = bytes;
+                in_use_ += bytes;
+                peak_ = std::max(peak_.load(), in_use_.load());
+                return base_ + off;
+            }
+        }
+        return nullptr;
+    }
+    char *base_ = nullptr;
+    uint64_t size_ = 0;
+    std::map<uint64_t, uint64_t> free_, used_;
+    std::atomic<uint64_t> in_use_{0}, peak_{0};
+    uint64_t epoch_ = 0;
+    std::mutex mu_;
+    std::condition_variable cv_;
+};
+
+// Allocations of one run, released together.
+class Scope {
+  public:
+    explicit Scope(Arena &a) : a_(a) {}
+    ~Scope() { release_all(); }
+    template <typename T>
+    T *get(uint64_t count) {
+        void *p = a_.alloc(count * sizeof(T) + 16);
+        if (!p) throw NoMem{count * sizeof(T)};
+        held_.push_back(p);
+        bytes_ += count * sizeof(T);
+        return (T *)p;
+    }
+    void release_all() {
+        for (void *p : held_) a_.release(p);
+        held_.clear();
+        bytes_ = 0;
+    }
+    uint64_t bytes() const { return bytes_; }
+
+  private:
+    Arena &a_;
+    std::vector<void *> held_;
+    uint64_t bytes_ = 0;
+};
+
+int bits_for(uint64_t maxval) {   // bits needed to hold values in [0, maxval]
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- objects
+
+struct ParamsCopy {
+    mapper_params p{};
+    std::vector<float> dir[2];
+    std::vector<double> val[2];
+};
+
+struct Request;
+
+struct mapper_context {
+    int device = 0;
+    Arena arena;
+    hipStream_t stream = nullptr;
+    std::vector<hipStream_t> slots;
+    // serving
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> pending;
+    std::unordered_map<uint64_t, Request *> tickets;
+    std::vector<std::thread> workers;
+    uint64_t next_ticket = 1;
+    int active = 0;
+    bool stop = false;
+    // autotuner cache: (d, eps bucket, norm bucket) -> precision
+    std::mutex tune_mu;
+    std::map<std::tuple<int, int, int>, int> tune;
+};
+
+struct mapper_cloud {
+    mapper_context *ctx = nullptr;
+    float *X = nullptr;
+    int64_t n = 0;
+    int32_t d = 0;
+    float maxabs = 0.f;
+    std::atomic<int> inflight{0};
+};
+
+struct mapper_graph {
+    std::vector<int32_t> node_element;
+    std::vector<int64_t> node_offsets;
+    std::vector<int32_t> node_members;
+    std::vector<int32_t> edges;
+    std::vector<int32_t> weights;
+    mapper_run_stats stats{};
+    std::map<std::string, std::pair<std::vector<char>, int64_t>> stages;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    const mapper_cloud *cloud = nullptr;
+    ParamsCopy params;
+    bool done = false;
+    mapper_status status = MAPPER_OK;
+    std::string err;
+    mapper_graph *graph = nullptr;
+};
+
+namespace {
+
+mapper_status validate(const mapper_cloud *c, const mapper_params *p) {
+    if (!c || !p) return fail(MAPPER_EINVAL, "null cloud or params");
+    if (p->n_axes < 1 || p->n_axes > 2) return fail(MAPPER_EINVAL, "n_axes must be 1 or 2");
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return fail(MAPPER_EINVAL, "eps must be finite and >= 0");
+    if (p->min_pts < 1) return fail(MAPPER_EINVAL, "min_pts must be >= 1");
+    if (p->precision < 0 || p->precision > MAPPER_PREC_AUTO) return fail(MAPPER_EINVAL, "bad precision");
+    int64_t ne = 1;
+    for (int a = 0; a < p->n_axes; ++a) {
+        const mapper_axis &ax = p->axis[a];
+        if (ax.n_intervals < 1) return fail(MAPPER_EINVAL, "n_intervals must be >= 1");
+        if (!(ax.overlap >= 0.0 && ax.overlap < 1.0)) return fail(MAPPER_EINVAL, "overlap must be in [0, 1)");
+        if (ax.kind < 0 || ax.kind > MAPPER_LENS_VALUES) return fail(MAPPER_EINVAL, "bad lens kind");
+        if (ax.kind == MAPPER_LENS_COLUMN && (ax.column < 0 || ax.column >= c->d))
+            return fail(MAPPER_EINVAL, "lens column out of range");
+        if (ax.kind == MAPPER_LENS_PROJECTION) {
+            if (!ax.direction) return fail(MAPPER_EINVAL, "projection lens needs a direction");
+            for (int j = 0; j < c->d; ++j)
+                if (!std::isfinite(ax.direction[j])) return fail(MAPPER_EINVAL, "non-finite direction");
+        }
+        if (ax.kind == MAPPER_LENS_VALUES) {
+            if (!ax.values) return fail(MAPPER_EINVAL, "values lens needs values");
+            for (int64_t i = 0; i < c->n; ++i)
+                if (!std::isfinite(ax.values[i])) return fail(MAPPER_EINVAL, "non-finite lens value");
+        }
+        ne *= ax.n_intervals;
+    }
+    if (ne > (1 << 24)) return fail(MAPPER_EINVAL, "more than 2^24 cover elements");
+    return MAPPER_OK;
+}
+
+void copy_params(const mapper_cloud *c, const mapper_params *p, ParamsCopy &out) {
+    out.p = *p;
+    for (int a = 0; a < p->n_axes; ++a) {
+        const mapper_axis &ax = p->axis[a];
+        if (ax.kind == MAPPER_LENS_PROJECTION) {
+            out.dir[a].assign(ax.direction, ax.direction + c->d);
+            out.p.axis[a].direction = out.dir[a].data();
+        } else {
+            out.p.axis[a].direction = nullptr;
+        }
+        if (ax.kind == MAPPER_LENS_VALUES) {
+            out.val[a].assign(ax.values, ax.values + c->n);
+            out.p.axis[a].values = out.val[a].data();
+        } else {
+            out.p.axis[a].values = nullptr;
+        }
+    }
+}
+
+// Interval endpoints (Background section: n intervals of one length with
+// fractional overlap p covering [m, M]); evaluated exactly as written, in
+// FP64, with contraction disabled for this translation unit.
+void cover_endpoints(double m, double M, int n, double p, std::vector<double> &lo,
+                     std::vector<double> &hi) {
+    lo.resize(n);
+    hi.resize(n);
+    const double L = (M - m) / ((double)n - (double)(n - 1) * p);
+    const double s = L * (1.0 - p);
+    for (int k = 0; k < n; ++k) {
+        lo[k] = m + (double)k * s;
+        hi[k] = (k == n - 1) ? M : lo[k] + L;
+    }
+}
+
+double key_to_double(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+}
+
+template <typename T>
+void d2h(std::vector<T> &dst, const T *src, int64_t count, hipStream_t s) {
+    dst.resize((size_t)std::max<int64_t>(count, 0));
+    if (count > 0) HIPCHK(hipMemcpyAsync(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+
+template <typename T>
+void h2d(T *dst, const T *src, int64_t count, hipStream_t s) {
+    if (count > 0) HIPCHK(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    hipStream_t s;
+    explicit Events(hipStream_t st) : s(st) {}
+    ~Events() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    void mark() {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventRecord(e, s));
+        ev.push_back(e);
+    }
+    double ms(size_t a, size_t b) {
+        if (b >= ev.size()) return 0.0;
+        float t = 0;
+        (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+};
+
+// ----------------------------------------------------------------- autotuner
+// Precision choice: predicted time = matrix-core time + (band fraction x FP64
+// recheck time).  The band fraction of each precision is measured on a
+// sample of in-element pairs (exact FP64 distances from the device) against
+// the nominal half-width of that precision's certified band.
+struct TuneSample {
+    std::vector<double> D, na, nb;
+};
+
+int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneSample &ts,
+                     double pairs) {
+    if (ts.D.empty()) return P_BF16X3;
+    std::vector<double> nn = ts.na;
+    nn.insert(nn.end(), ts.nb.begin(), ts.nb.end());
+    std::nth_element(nn.begin(), nn.begin() + nn.size() / 2, nn.end());
+    const double med = std::max(nn[nn.size() / 2], 1e-300);
+    const int eb = (int)std::floor(std::log2(std::max(E, 1e-300) / med) * 4.0);
+    const int nbk = (int)std::floor(std::log2(std::max((double)pairs, 1.0)));
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->tune.find({d, eb, nbk});
+        if (it != ctx->tune.end()) return it->second;
+    }
+    const double u = std::ldexp(1.0, -23);
+    auto gam = [&](double k) { return k * u / (1.0 - k * u); };
+    const double K16 = dp16, K32 = 32.0 * std::ceil(d / 32.0);
+    // nominal e_i / |x_i|^2 for each precision (same structure as the packing bound)
+    const double c[5] = {
+        gam(2 * K32 + 2) * 0.5,                                       // FP32
+        gam(K16 + 2) * 0.5 + std::ldexp(1.0, -9) * 0.67,              // BF16
+        gam(K16 + 2) * 0.5 + gam(2 * K16 + 2) * std::ldexp(1.0, -8) + std::ldexp(1.0, -24) * 3,  // BF16X3
+        gam(K16 + 2) * 0.5 + std::ldexp(1.0, -12) * 0.67,             // FP16
+        gam(K16 + 2) * 0.5 + gam(2 * K16 + 2) * std::ldexp(1.0, -11) + std::ldexp(1.0, -24) * 3, // FP16X3
+    };
+    // issued matrix-core seconds per pair (peak FLOP rates, 2 flops per MAC)
+    const double mfma[5] = {2 * K32 / 157e12, 2 * K16 / 2.5e15, 6 * K16 / 2.5e15,
+                            2 * K16 / 2.5e15, 6 * K16 / 2.5e15};
+    const double eff[5] = {0.7, 0.45, 0.5, 0.45, 0.5};
+    const double recheck = 2.0 * d * 4.0 / 1.5e12 + 2.0 * d / 20e12;   // gather two rows + FP64 chain
+    int best = P_FP32;
+    double tbest = 1e300;
+    for (int p = 0; p < 5; ++p) {
+        size_t inband = 0;
+        for (size_t k = 0; k < ts.D.size(); ++k) {
+            const double beta = 2.0 * c[p] * (ts.na[k] + ts.nb[k]) * 1.05;
+            if (std::fabs(ts.D[k] - E) <= beta) ++inband;
+        }
+        const double frac = (double)inband / (double)ts.D.size();
+        const double t = mfma[p] / eff[p] + frac * recheck;
+        if (t < tbest) { tbest = t; best = p; }
+    }
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->tune[{d, eb, nbk}] = best;
+    return best;
+}
+
+// ------------------------------------------------------------------ the run
+enum class Phase { Ok, Retry };
+
+struct RunOut {
+    mapper_graph *g = nullptr;
+};
+
+Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
+                   hipStream_t s, bool may_retry, RunOut &out) {
+    Scope mem(ctx->arena);
+    Events ev(s);
+    const int64_t n = cloud->n;
+    const int32_t d = cloud->d;
+    const int na = P->n_axes;
+    auto g = std::make_unique<mapper_graph>();
+    mapper_run_stats &st = g->stats;
+    const bool dbg = (P->flags & MAPPER_FLAG_DEBUG_STAGES) != 0;
+    std::vector<int> nint(2, 1);
+    for (int a = 0; a < na; ++a) nint[a] = P->axis[a].n_intervals;
+    const int64_t E_count = (int64_t)nint[0] * (na == 2 ? nint[1] : 1);
+    const double E = P->eps * P->eps;
+
+    ev.mark();                                                      // 0
+    // ---- lens and range
+    double *f[2] = {nullptr, nullptr};
+    unsigned long long *rk = mem.get<unsigned long long>(4);
+    {
+        const unsigned long long init[4] = {~0ull, 0ull, ~0ull, 0ull};
+        h2d(rk, init, 4, s);
+    }
+    for (int a = 0; a < na; ++a) {
+        const mapper_axis &ax = P->axis[a];
+        f[a] = mem.get<double>(n);
+        float *dir = nullptr;
+        double *vals = nullptr;
+        if (ax.kind == MAPPER_LENS_PROJECTION) {
+            dir = mem.get<float>(d);
+            h2d(dir, ax.direction, d, s);
+        }
+        if (ax.kind == MAPPER_LENS_VALUES) {
+            vals = mem.get<double>(n);
+            h2d(vals, ax.values, n, s);
+        }
+        HIPCHK(launch_lens(cloud->X, n, d, ax.kind, ax.column, dir, vals, f[a], s));
+        HIPCHK(launch_range(f[a], n, rk + 2 * a, s));
+    }
+    std::vector<unsigned long long> rkh;
+    d2h(rkh, rk, 4, s);
+    HIPCHK(hipStreamSynchronize(s));
+    ev.mark();                                                      // 1
+    std::vector<double> lo[2], hi[2], hc[2];
+    double* dlo[2] = {nullptr, nullptr};
+    double* dhc[2] = {nullptr, nullptr};
+    for (int a = 0; a < na; ++a) {
+        const double m = key_to_double(rkh[2 * a]), M = key_to_double(rkh[2 * a + 1]);
+        cover_endpoints(m, M, nint[a], P->axis[a].overlap, lo[a], hi[a]);
+        hc[a].resize(nint[a]);
+        for (int k = 0; k < nint[a]; ++k) {
+            if (!std::isfinite(lo[a][k]) || !std::isfinite(hi[a][k]))
+                throw std::runtime_error("lens range too wide for finite interval endpoints");
+            hc[a][k] = std::min(hi[a][k], M);
+        }
+        for (int k = 1; k < nint[a]; ++k)
+            if (lo[a][k] < lo[a][k - 1] || hc[a][k] < hc[a][k - 1])
+                throw std::runtime_error("interval endpoints not monotone");
+        dlo[a] = mem.get<double>(nint[a]);
+        dhc[a] = mem.get<double>(nint[a]);
+        h2d(dlo[a], lo[a].data(), nint[a], s);
+        h2d(dhc[a], hc[a].data(), nint[a], s);
+    }
+
+    // ---- pullback sets: (element, point) pairs sorted stably by element
+    int32_t *range4 = mem.get<int32_t>(4 * n);
+    int32_t *mcount = mem.get<int32_t>(n);
+    int64_t *mpos = mem.get<int64_t>(n + 1);
+    void *stmp = mem.get<char>(scan_temp_bytes(n));
+    HIPCHK(launch_member_count(f[0], na == 2 ? f[1] : nullptr, n, dlo[0], dhc[0], nint[0],
+                               na == 2 ? dlo[1] : nullptr, na == 2 ? dhc[1] : nullptr, nint[1],
+                               range4, mcount, s));
+    HIPCHK(launch_scan_i32(mcount, mpos, n, stmp, s));
+    int64_t S = 0;
+    HIPCHK(hipMemcpyAsync(&S, mpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (S > (int64_t)0x7fffffff) throw std::runtime_error("more than 2^31 memberships");
+    const int64_t Sa = std::max<int64_t>(S, 1);
+    uint64_t *skey = mem.get<uint64_t>(Sa), *skey2 = mem.get<uint64_t>(Sa);
+    uint32_t *sval = mem.get<uint32_t>(Sa), *sval2 = mem.get<uint32_t>(Sa);
+    void *sortmp = mem.get<char>(sort_temp_bytes(Sa));
+    HIPCHK(launch_member_emit(range4, mpos, n, nint[1], na == 2, skey, sval, s));
+    bool alt = false;
+    HIPCHK(radix_sort_pairs(skey, sval, skey2, sval2, S, bits_for((uint64_t)E_count), sortmp, &alt, s));
+    uint64_t *slot_elem = alt ? skey2 : skey;
+    uint32_t *slot_point = alt ? sval2 : sval;
+    int64_t *elem_off = mem.get<int64_t>(E_count + 1);
+    HIPCHK(launch_lower_bounds(slot_elem, S, E_count, elem_off, s));
+    std::vector<int64_t> eoff;
+    d2h(eoff, elem_off, E_count + 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    ev.mark();                                                      // 2
+
+    // ---- tiling (host): elements largest first
+    std::vector<int32_t> order;
+    std::vector<int64_t> T(E_count), P_e(E_count), blk_off(E_count);
+    int64_t nblocks = 0, pairs = 0;
+    for (int64_t e = 0; e < E_count; ++e) {
+        const int64_t ne = eoff[e + 1] - eoff[e];
+        T[e] = (ne + TILE - 1) / TILE;
+        P_e[e] = T[e] * (T[e] + 1) / 2;
+        blk_off[e] = nblocks;
+        nblocks += P_e[e];
+        pairs += ne * (ne + 1) / 2;
+        if (ne > 0) order.push_back((int32_t)e);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P_e[a] > P_e[b]; });
+    std::vector<int64_t> item_off(order.size() + 1, 0);
+    for (size_t k = 0; k < order.size(); ++k) item_off[k + 1] = item_off[k] + P_e[order[k]];
+    st.n_slots = S;
+    st.pairs = pairs;
+    st.tiles = nblocks;
+
+    // ---- precision
+    const float scale_src = cloud->maxabs;
+    double scale = 1.0;
+    if (scale_src > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)scale_src));
+    const int dp16 = 64 * ((d + 63) / 64);
+    int prec = P->precision;
+    if (prec == MAPPER_PREC_AUTO) {
+        TuneSample ts;
+        if (S > 1 && !order.empty()) {
+            // sample pairs of elements in proportion to their pair counts
+            const int NS = 4096;
+            std::vector<int32_t> pa(NS), pb(NS);
+            std::vector<uint32_t> pts;
+            d2h(pts, slot_point, S, s);
+            HIPCHK(hipStreamSynchronize(s));
+            uint64_t rs = 0x9E3779B97F4A7C15ull ^ (uint64_t)S;
+            auto rnd = [&]() { rs ^= rs << 13; rs ^= rs >> 7; rs ^= rs << 17; return rs; };
+            std::vector<double> cum(order.size());
+            double acc = 0;
+            for (size_t k = 0; k < order.size(); ++k) {
+                const double ne = (double)(eoff[order[k] + 1] - eoff[order[k]]);
+                acc += ne * ne;
+                cum[k] = acc;
+            }
+            for (int q = 0; q < NS; ++q) {
+                const double r = (double)(rnd() >> 11) * 0x1.0p-53 * acc;
+                const size_t k = std::min(order.size() - 1,
+                                          (size_t)(std::lower_bound(cum.begin(), cum.end(), r) - cum.begin()));
+                const int e = order[k];
+                const int64_t ne = eoff[e + 1] - eoff[e];
+                pa[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
+                pb[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
+            }
+            Scope tmp(ctx->arena);
+            int32_t *dpa = tmp.get<int32_t>(NS), *dpb = tmp.get<int32_t>(NS);
+            double *dD = tmp.get<double>(NS), *dna = tmp.get<double>(NS), *dnb = tmp.get<double>(NS);
+            h2d(dpa, pa.data(), NS, s);
+            h2d(dpb, pb.data(), NS, s);
+            HIPCHK(launch_pair_d64(dpa, dpb, NS, cloud->X, d, dD, s));
+            HIPCHK(launch_row_norm2(dpa, NS, cloud->X, d, dna, s));
+            HIPCHK(launch_row_norm2(dpb, NS, cloud->X, d, dnb, s));
+            d2h(ts.D, dD, NS, s);
+            d2h(ts.na, dna, NS, s);
+            d2h(ts.nb, dnb, NS, s);
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        prec = choose_precision(ctx, d, dp16, E, ts, (double)pairs);
+    }
+    st.precision = prec;
+    st.tile_m = st.tile_n = TILE;
+    st.split_terms = prec_is_split(prec) ? 3 : 1;
+
+    // ---- device tables, panels, thresholds
+    int64_t *d_item_off = mem.get<int64_t>(item_off.size());
+    int32_t *d_order = mem.get<int32_t>(std::max<size_t>(order.size(), 1));
+    int64_t *d_blk_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
+    h2d(d_item_off, item_off.data(), (int64_t)item_off.size(), s);
+    h2d(d_order, order.data(), (int64_t)order.size(), s);
+    h2d(d_blk_off, blk_off.data(), E_count, s);
+    TileTable tt;
+    tt.item_off = d_item_off;
+    tt.order = d_order;
+    tt.elem_off = elem_off;
+    tt.blk_off = d_blk_off;
+    tt.nord = (int32_t)order.size();
+    tt.n_items = nblocks;
+
+    const int dp = prec == P_FP32 ? 32 * ((d + 31) / 32) : dp16;
+    const int esz = prec == P_FP32 ? 4 : 2;
+    void *panel_hi = mem.get<char>((uint64_t)Sa * dp * esz);
+    void *panel_lo = prec_is_split(prec) ? mem.get<char>((uint64_t)Sa * dp * esz) : nullptr;
+    float *thrA = mem.get<float>(Sa), *thrB = mem.get<float>(Sa);
+    PackArgs pk;
+    pk.X = cloud->X;
+    pk.d = d;
+    pk.dp = dp;
+    pk.slot_point = slot_point;
+    pk.n_slots = S;
+    pk.prec = prec;
+    pk.scale = scale;
+    pk.E_scaled = E * scale * scale;
+    pk.panel_hi = panel_hi;
+    pk.panel_lo = panel_lo;
+    pk.thrA = thrA;
+    pk.thrB = thrB;
+    pk.dbg_norm2 = nullptr;
+    pk.dbg_e = nullptr;
+    HIPCHK(launch_pack(pk, s));
+
+    int32_t *count = mem.get<int32_t>(Sa);
+    uint32_t *bitmask = mem.get<uint32_t>((uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS);
+    st.bitmask_bytes = nblocks * TILE_WORDS * 4;
+    unsigned long long *band_n = mem.get<unsigned long long>(1);
+    int64_t band_cap = std::max<int64_t>(1 << 20, pairs / 256);
+    band_cap = std::min<int64_t>(band_cap, 1ll << 28);
+    BandPair *band = nullptr;
+    for (;;) {
+        try {
+            band = mem.get<BandPair>(band_cap);
+        } catch (NoMem &) {
+            band_cap /= 4;
+            if (band_cap < 4096) throw;
+            continue;
+        }
+        break;
+    }
+    ev.mark();                                                      // 3
+    int64_t nband = 0;
+    for (int launch = 0;; ++launch) {
+        HIPCHK(hipMemsetAsync(count, 0, (size_t)Sa * 4, s));
+        HIPCHK(hipMemsetAsync(band_n, 0, 8, s));
+        TileArgs ta{};
+        ta.tt = tt;
+        ta.panel_hi = panel_hi;
+        ta.panel_lo = panel_lo;
+        ta.dp = dp;
+        ta.thrA = thrA;
+        ta.thrB = thrB;
+        ta.bitmask = bitmask;
+        ta.count = count;
+        ta.band = band;
+        ta.band_n = band_n;
+        ta.band_cap = band_cap;
+        Events kt(s);
+        kt.mark();
+        HIPCHK(launch_tiles(prec, ta, s));
+        kt.mark();
+        unsigned long long nb = 0;
+        HIPCHK(hipMemcpyAsync(&nb, band_n, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        st.tile_launches = launch + 1;
+        st.ms_tiles = kt.ms(0, 1);
+        if ((int64_t)nb <= band_cap) {
+            nband = (int64_t)nb;
+            break;
+        }
+        band_cap = (int64_t)nb + (int64_t)nb / 8 + 1024;     // grow and redo the tiles
+        band = mem.get<BandPair>(band_cap);
+    }
+    st.band_pairs = nband;
+    ev.mark();                                                      // 4
+    HIPCHK(launch_recheck(band, nband, cloud->X, d, slot_point, E, bitmask, count, s));
+    ev.mark();                                                      // 5
+
+    // ---- clusters
+    int32_t *parent = mem.get<int32_t>(Sa);
+    uint8_t *isroot = mem.get<uint8_t>(Sa);
+    int64_t *rank = mem.get<int64_t>(Sa + 1);
+    int32_t *node = mem.get<int32_t>(Sa);
+    int32_t *node_elem = mem.get<int32_t>(Sa);
+    HIPCHK(launch_cc_init(parent, S, s));
+    HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
+    HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
+    void *stmp2 = mem.get<char>(scan_temp_bytes(Sa + 1));
+    HIPCHK(launch_scan_u8(isroot, rank, S, stmp2, s));
+    HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, slot_elem, node, node_elem, S, s));
+    HIPCHK(launch_border(tt, bitmask, count, P->min_pts, node, s));
+    int64_t N = 0;
+    HIPCHK(hipMemcpyAsync(&N, rank + S, 8, hipMemcpyDeviceToHost, s));
+    ev.mark();                                                      // 6
+
+    // ---- node CSR: (node, point) sorted stably by node
+    uint8_t *lab = isroot;       // reuse
+    HIPCHK(launch_flag_labelled(node, lab, S, s));
+    int64_t *mp = rank;          // reuse (roots already consumed by launch_node_ids)
+    HIPCHK(launch_scan_u8(lab, mp, S, stmp2, s));
+    int64_t M = 0;
+    HIPCHK(hipMemcpyAsync(&M, mp + S, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t Ma = std::max<int64_t>(M, 1);
+    uint64_t *k1 = mem.get<uint64_t>(Ma), *k2 = mem.get<uint64_t>(Ma);
+    uint32_t *v1 = mem.get<uint32_t>(Ma), *v2 = mem.get<uint32_t>(Ma);
+    void *sortmp2 = mem.get<char>(sort_temp_bytes(Ma));
+    HIPCHK(launch_member_pairs(node, slot_point, mp, S, k1, v1, s));
+    HIPCHK(radix_sort_pairs(k1, v1, k2, v2, M, bits_for((uint64_t)std::max<int64_t>(N - 1, 0)), sortmp2, &alt, s));
+    uint64_t *nk = alt ? k2 : k1;
+    uint32_t *nv = alt ? v2 : v1;
+    int64_t *node_off = mem.get<int64_t>(N + 1);
+    HIPCHK(launch_node_offsets_from_sorted(nk, M, N, node_off, s));
+    int32_t *members = mem.get<int32_t>(Ma);
+    HIPCHK(launch_u32_to_i32(nv, members, M, s));
+    // ---- edges: regroup (point, node) by point; stable, so nodes stay ascending
+    uint64_t *ptk = mem.get<uint64_t>(Ma), *ptk2 = mem.get<uint64_t>(Ma);
+    uint32_t *ptn = mem.get<uint32_t>(Ma), *ptn2 = mem.get<uint32_t>(Ma);
+    HIPCHK(launch_widen_u32(nv, ptk, M, s));
+    HIPCHK(launch_narrow_u64(nk, ptn, M, s));
+    HIPCHK(radix_sort_pairs(ptk, ptn, ptk2, ptn2, M, bits_for((uint64_t)std::max<int64_t>(n - 1, 0)), sortmp2, &alt, s));
+    uint64_t *sp_k = alt ? ptk2 : ptk;
+    uint32_t *sp_n = alt ? ptn2 : ptn;
+    int32_t *ecnt = mem.get<int32_t>(Ma);
+    int64_t *epos = mem.get<int64_t>(Ma + 1);
+    void *stmp3 = mem.get<char>(scan_temp_bytes(Ma + 1));
+    HIPCHK(launch_edge_counts(sp_k, M, ecnt, s));
+    HIPCHK(launch_scan_i32(ecnt, epos, M, stmp3, s));
+    int64_t EP = 0;
+    HIPCHK(hipMemcpyAsync(&EP, epos + M, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t EPa = std::max<int64_t>(EP, 1);
+    uint64_t *ek = mem.get<uint64_t>(EPa), *ek2 = mem.get<uint64_t>(EPa);
+    uint32_t *ev1 = mem.get<uint32_t>(EPa), *ev2 = mem.get<uint32_t>(EPa);
+    void *sortmp3 = mem.get<char>(sort_temp_bytes(EPa));
+    HIPCHK(launch_edge_emit(sp_k, sp_n, M, epos, N, ek, s));
+    HIPCHK(hipMemsetAsync(ev1, 0, (size_t)EPa * 4, s));
+    HIPCHK(radix_sort_pairs(ek, ev1, ek2, ev2, EP, bits_for((uint64_t)N * (uint64_t)N), sortmp3, &alt, s));
+    uint64_t *sek = alt ? ek2 : ek;
+    uint8_t *rs = mem.get<uint8_t>(EPa);
+    int64_t *rr = mem.get<int64_t>(EPa + 1);
+    void *stmp4 = mem.get<char>(scan_temp_bytes(EPa + 1));
+    HIPCHK(launch_run_starts(sek, EP, rs, s));
+    HIPCHK(launch_scan_u8(rs, rr, EP, stmp4, s));
+    int64_t NE = 0;
+    HIPCHK(hipMemcpyAsync(&NE, rr + EP, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t *edges = mem.get<int32_t>(2 * std::max<int64_t>(NE, 1));
+    int32_t *weights = mem.get<int32_t>(std::max<int64_t>(NE, 1));
+    HIPCHK(launch_edge_compact(sek, EP, rr, N, edges, weights, s));
+    ev.mark();                                                      // 7
+
+    // ---- graph to the host
+    d2h(g->node_element, node_elem, N, s);
+    d2h(g->node_offsets, node_off, N + 1, s);
+    d2h(g->node_members, members, M, s);
+    d2h(g->edges, edges, 2 * NE, s);
+    d2h(g->weights, weights, NE, s);
+    if (dbg) {
+        auto put = [&](const char *name, const void *src, int64_t cnt, size_t esz) {
+            auto &slot = g->stages[name];
+            slot.first.resize((size_t)std::max<int64_t>(cnt, 0) * esz + 1);
+            slot.second = cnt;
+            if (cnt > 0) HIPCHK(hipMemcpyAsync(slot.first.data(), src, (size_t)cnt * esz, hipMemcpyDeviceToHost, s));
+        };
+        std::vector<double> lensv;
+        for (int a = 0; a < na; ++a) {
+            std::vector<double> tmp;
+            d2h(tmp, f[a], n, s);
+            HIPCHK(hipStreamSynchronize(s));
+            lensv.insert(lensv.end(), tmp.begin(), tmp.end());
+        }
+        auto &ls = g->stages["lens"];
+        ls.first.assign((char *)lensv.data(), (char *)lensv.data() + lensv.size() * 8);
+        ls.second = (int64_t)lensv.size();
+        std::vector<double> lov, hiv;
+        for (int a = 0; a < na; ++a) {
+            lov.insert(lov.end(), lo[a].begin(), lo[a].end());
+            hiv.insert(hiv.end(), hi[a].begin(), hi[a].end());
+        }
+        g->stages["lo"] = {std::vector<char>((char *)lov.data(), (char *)lov.data() + lov.size() * 8), (int64_t)lov.size()};
+        g->stages["hi"] = {std::vector<char>((char *)hiv.data(), (char *)hiv.data() + hiv.size() * 8), (int64_t)hiv.size()};
+        g->stages["elem_offsets"] = {std::vector<char>((char *)eoff.data(), (char *)eoff.data() + eoff.size() * 8), (int64_t)eoff.size()};
+        put("elem_members", slot_point, S, 4);
+        put("slot_count", count, S, 4);
+        put("slot_node_raw", node, S, 4);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (dbg) {
+        auto &raw = g->stages["slot_node_raw"];
+        std::vector<int32_t> nodev((size_t)S);
+        if (S) std::memcpy(nodev.data(), raw.first.data(), (size_t)S * 4);
+        std::vector<uint8_t> corev((size_t)S);
+        const int32_t *cnt = (const int32_t *)g->stages["slot_count"].first.data();
+        for (int64_t i = 0; i < S; ++i) {
+            if (nodev[i] == 0x7fffffff) nodev[i] = -1;
+            corev[i] = cnt[i] >= P->min_pts;
+        }
+        g->stages["slot_node"] = {std::vector<char>((char *)nodev.data(), (char *)nodev.data() + S * 4 + 1), S};
+        g->stages["slot_core"] = {std::vector<char>((char *)corev.data(), (char *)corev.data() + S + 1), S};
+        g->stages.erase("slot_node_raw");
+    }
+    st.ms_lens = ev.ms(0, 1);
+    st.ms_bin = ev.ms(1, 2);
+    st.ms_recheck = ev.ms(4, 5);
+    st.ms_cc = ev.ms(5, 6);
+    st.ms_edges = ev.ms(6, 7);
+    st.ms_total = ev.ms(0, 7);
+    st.arena_peak_bytes = mem.bytes();
+    (void)may_retry;
+    out.g = g.release();
+    return Phase::Ok;
+}
+
+mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
+                          hipStream_t s, bool may_retry, mapper_graph **out, bool *retry) {
+    *retry = false;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        RunOut ro;
+        run_pipeline(ctx, cloud, P, s, may_retry, ro);
+        *out = ro.g;
+        return MAPPER_OK;
+    } catch (NoMem &nm) {
+        (void)hipStreamSynchronize(s);
+        if (may_retry) {
+            *retry = true;
+            return MAPPER_ENOMEM;
+        }
+        return fail(MAPPER_ENOMEM, "arena too small for this run (needed " + std::to_string(nm.want) +
+                                       " more bytes in one block)");
+    } catch (DevError &de) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e) + " (runtime.cpp:" +
+                                        std::to_string(de.line) + ")");
+    } catch (std::exception &ex) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EINVAL, ex.what());
+    }
+}
+
+void worker_main(mapper_context *ctx, hipStream_t s) {
+    (void)hipSetDevice(ctx->device);
+    while (true) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(ctx->mu);
+            ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
+            if (ctx->stop && ctx->pending.empty()) return;
+            r = ctx->pending.front();
+            ctx->pending.pop_front();
+            ++ctx->active;
+        }
+        mapper_graph *g = nullptr;
+        bool retry = false;
+        uint64_t seen = ctx->arena.epoch();
+        mapper_status st;
+        {
+            // only retry while another request holds memory that it will return
+            int others;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                others = ctx->active - 1;
+            }
+            st = run_guarded(ctx, r->cloud, &r->params.p, s, others > 0, &g, &retry);
+        }
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        --ctx->active;
+        if (retry) {
+            ctx->pending.push_front(r);
+            lk.unlock();
+            ctx->arena.wait_release(seen, 50);
+            ctx->cv.notify_all();
+            continue;
+        }
+        r->status = st;
+        r->err = st == MAPPER_OK ? "" : g_last_error;
+        r->graph = g;
+        r->done = true;
+        const_cast<mapper_cloud *>(r->cloud)->inflight--;
+        ctx->cv.notify_all();
+    }
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+const char *mapper_last_error(void) { return g_last_error.c_str(); }
+
+mapper_status mapper_context_create(int device, void *arena, uint64_t arena_bytes, void *stream,
+                                    mapper_context **out) {
+    if (!out) return fail(MAPPER_EINVAL, "out is null");
+    *out = nullptr;
+    if (!arena || arena_bytes < (1u << 20)) return fail(MAPPER_EINVAL, "arena must be at least 1 MiB");
+    if (((uintptr_t)arena & 255) != 0) return fail(MAPPER_EINVAL, "arena must be 256-byte aligned");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(MAPPER_EDEVICE, "no such HIP device");
+    auto *c = new mapper_context();
+    c->device = device;
+    c->arena.init((char *)arena, arena_bytes);
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return MAPPER_OK;
+}
+
+mapper_status mapper_context_set_streams(mapper_context *ctx, void *const *streams, int count) {
+    if (!ctx || count < 0 || (count > 0 && !streams)) return fail(MAPPER_EINVAL, "bad streams");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->workers.empty()) return fail(MAPPER_EBUSY, "streams already in use by the request loop");
+    ctx->slots.clear();
+    for (int i = 0; i < count; ++i) ctx->slots.push_back((hipStream_t)streams[i]);
+    return MAPPER_OK;
+}
+
+void mapper_context_destroy(mapper_context *ctx) {
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->stop = true;
+    }
+    ctx->cv.notify_all();
+    for (auto &t : ctx->workers) t.join();
+    for (auto &kv : ctx->tickets) {
+        if (kv.second->graph) mapper_graph_destroy(kv.second->graph);
+        delete kv.second;
+    }
+    delete ctx;
+}
+
+mapper_status mapper_context_memory(const mapper_context *ctx, uint64_t *in_use, uint64_t *peak) {
+    if (!ctx) return fail(MAPPER_EINVAL, "null context");
+    if (in_use) *in_use = ctx->arena.in_use();
+    if (peak) *peak = ctx->arena.peak();
+    return MAPPER_OK;
+}
+
+mapper_status mapper_cloud_create(mapper_context *ctx, const float *points, int64_t n, int32_t d,
+                                  int32_t on_device, mapper_cloud **out) {
+    if (!ctx || !points || !out) return fail(MAPPER_EINVAL, "null argument");
+    *out = nullptr;
+    if (n < 1 || n > 0x7fffffff || d < 1 || d > (1 << 16)) return fail(MAPPER_EINVAL, "need 1 <= n < 2^31, 1 <= d <= 65536");
+    const uint64_t bytes = (uint64_t)n * (uint64_t)d * 4;
+    float *X = (float *)ctx->arena.alloc(bytes);
+    uint32_t *flags = (uint32_t *)ctx->arena.alloc(256);
+    if (!X || !flags) {
+        ctx->arena.release(X);
+        ctx->arena.release(flags);
+        return fail(MAPPER_ENOMEM, "arena cannot hold the cloud");
+    }
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        hipStream_t s = ctx->stream;
+        HIPCHK(hipMemcpyAsync(X, points, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(flags, 0, 8, s));
+        HIPCHK(launch_check_cloud(X, (int64_t)n * d, flags, s));
+        uint32_t h[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->arena.release(flags);
+        if (h[0]) {
+            ctx->arena.release(X);
+            return fail(MAPPER_EINVAL, "cloud has non-finite coordinates");
+        }
+        auto *c = new mapper_cloud();
+        c->ctx = ctx;
+        c->X = X;
+        c->n = n;
+        c->d = d;
+        std::memcpy(&c->maxabs, &h[1], 4);
+        *out = c;
+        return MAPPER_OK;
+    } catch (DevError &de) {
+        ctx->arena.release(X);
+        ctx->arena.release(flags);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
+    }
+}
+
+mapper_status mapper_cloud_destroy(mapper_cloud *c) {
+    if (!c) return fail(MAPPER_EINVAL, "null cloud");
+    if (c->inflight.load() > 0) return fail(MAPPER_EBUSY, "cloud has requests in flight");
+    c->ctx->arena.release(c->X);
+    delete c;
+    return MAPPER_OK;
+}
+
+mapper_status mapper_run(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
+                         mapper_graph **out) {
+    if (!ctx || !out) return fail(MAPPER_EINVAL, "null argument");
+    *out = nullptr;
+    mapper_status v = validate(cloud, params);
+    if (v != MAPPER_OK) return v;
+    bool retry;
+    return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry);
+}
+
+mapper_status mapper_submit(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
+                            uint64_t *ticket) {
+    if (!ctx || !ticket) return fail(MAPPER_EINVAL, "null argument");
+    mapper_status v = validate(cloud, params);
+    if (v != MAPPER_OK) return v;
+    auto *r = new Request();
+    r->cloud = cloud;
+    copy_params(cloud, params, r->params);
+    const_cast<mapper_cloud *>(cloud)->inflight++;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->workers.empty()) {
+            std::vector<hipStream_t> ss = ctx->slots;
+            if (ss.empty()) ss.push_back(ctx->stream);
+            for (hipStream_t s : ss) ctx->workers.emplace_back(worker_main, ctx, s);
+        }
+        r->ticket = ctx->next_ticket++;
+        ctx->tickets[r->ticket] = r;
+        ctx->pending.push_back(r);
+        *ticket = r->ticket;
+    }
+    ctx->cv.notify_all();
+    return MAPPER_OK;
+}
+
+mapper_status mapper_wait(mapper_context *ctx, uint64_t ticket, int64_t timeout_us, mapper_graph **out) {
+    if (!ctx || !out) return fail(MAPPER_EINVAL, "null argument");
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return fail(MAPPER_EINVAL, "unknown ticket");
+    Request *r = it->second;
+    if (timeout_us < 0) {
+        ctx->cv.wait(lk, [&] { return r->done; });
+    } else if (!ctx->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->done; })) {
+        return fail(MAPPER_ETIMEDOUT, "request still running");
+    }
+    ctx->tickets.erase(it);
+    const mapper_status st = r->status;
+    if (st != MAPPER_OK) g_last_error = r->err;
+    *out = r->graph;
+    delete r;
+    return st;
+}
+
+int64_t mapper_graph_num_nodes(const mapper_graph *g) { return g ? (int64_t)g->node_element.size() : 0; }
+int64_t mapper_graph_num_edges(const mapper_graph *g) { return g ? (int64_t)g->weights.size() : 0; }
+const int32_t *mapper_graph_node_element(const mapper_graph *g) { return g ? g->node_element.data() : nullptr; }
+const int64_t *mapper_graph_node_offsets(const mapper_graph *g) { return g ? g->node_offsets.data() : nullptr; }
+const int32_t *mapper_graph_node_members(const mapper_graph *g) { return g ? g->node_members.data() : nullptr; }
+const int32_t *mapper_graph_edges(const mapper_graph *g) { return g ? g->edges.data() : nullptr; }
+const int32_t *mapper_graph_edge_weights(const mapper_graph *g) { return g ? g->weights.data() : nullptr; }
+
+mapper_status mapper_graph_stats(const mapper_graph *g, mapper_run_stats *out) {
+    if (!g || !out) return fail(MAPPER_EINVAL, "null argument");
+    *out = g->stats;
+    return MAPPER_OK;
+}
+
+const void *mapper_graph_stage(const mapper_graph *g, const char *name, int64_t *count) {
+    if (!g || !name) return nullptr;
+    auto it = g->stages.find(name);
+    if (it == g->stages.end()) return nullptr;
+    if (count) *count = it->second.second;
+    return it->second.first.data();
+}
+
+void mapper_graph_destroy(mapper_graph *g) { delete g; }
+
+}  // extern "C"
+
+extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_cloud *cloud,
+                                              const int32_t *rows, int32_t nrows, int32_t precision,
+                                              double eps, double *out_d2, double *out_band) {
+    if (!ctx || !cloud || !rows || !out_d2 || !out_band || nrows < 1)
+        return fail(MAPPER_EINVAL, "null argument or empty row set");
+    if (precision < 0 || precision > P_FP16X3) return fail(MAPPER_EINVAL, "precision must be explicit");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(MAPPER_EINVAL, "bad eps");
+    for (int32_t i = 0; i < nrows; ++i)
+        if (rows[i] < 0 || rows[i] >= cloud->n) return fail(MAPPER_EINVAL, "row id out of range");
+    hipStream_t s = ctx->stream;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        Scope mem(ctx->arena);
+        const int32_t d = cloud->d;
+        const int64_t T = (nrows + TILE - 1) / TILE, P = T * (T + 1) / 2;
+        uint32_t *slot_point = mem.get<uint32_t>(nrows);
+        h2d(slot_point, (const uint32_t *)rows, nrows, s);
+        const int64_t eo[2] = {0, nrows};
+        const int64_t io[2] = {0, P};
+        const int64_t bo[1] = {0};
+        const int32_t od[1] = {0};
+        int64_t *d_eo = mem.get<int64_t>(2), *d_io = mem.get<int64_t>(2), *d_bo = mem.get<int64_t>(1);
+        int32_t *d_od = mem.get<int32_t>(1);
+        h2d(d_eo, eo, 2, s);
+        h2d(d_io, io, 2, s);
+        h2d(d_bo, bo, 1, s);
+        h2d(d_od, od, 1, s);
+        double scale = 1.0;
+        if (cloud->maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)cloud->maxabs));
+        const int dp = precision == P_FP32 ? 32 * ((d + 31) / 32) : 64 * ((d + 63) / 64);
+        const int esz = precision == P_FP32 ? 4 : 2;
+        PackArgs pk{};
+        pk.X = cloud->X;
+        pk.d = d;
+        pk.dp = dp;
+        pk.slot_point = slot_point;
+        pk.n_slots = nrows;
+        pk.prec = precision;
+        pk.scale = scale;
+        pk.E_scaled = eps * eps * scale * scale;
+        pk.panel_hi = mem.get<char>((uint64_t)nrows * dp * esz);
+        pk.panel_lo = prec_is_split(precision) ? mem.get<char>((uint64_t)nrows * dp * esz) : nullptr;
+        pk.thrA = mem.get<float>(nrows);
+        pk.thrB = mem.get<float>(nrows);
+        pk.dbg_norm2 = mem.get<double>(nrows);
+        pk.dbg_e = mem.get<double>(nrows);
+        HIPCHK(launch_pack(pk, s));
+        TileArgs ta{};
+        ta.tt.item_off = d_io;
+        ta.tt.order = d_od;
+        ta.tt.elem_off = d_eo;
+        ta.tt.blk_off = d_bo;
+        ta.tt.nord = 1;
+        ta.tt.n_items = P;
+        ta.panel_hi = pk.panel_hi;
+        ta.panel_lo = pk.panel_lo;
+        ta.dp = dp;
+        ta.thrA = pk.thrA;
+        ta.thrB = pk.thrB;
+        ta.bitmask = mem.get<uint32_t>((uint64_t)P * TILE_WORDS);
+        ta.count = mem.get<int32_t>(nrows);
+        ta.band_cap = 0;
+        ta.band = nullptr;
+        ta.band_n = mem.get<unsigned long long>(1);
+        ta.debug_g = mem.get<float>((uint64_t)nrows * nrows);
+        ta.debug_ld = nrows;
+        HIPCHK(hipMemsetAsync(ta.count, 0, (size_t)nrows * 4, s));
+        HIPCHK(hipMemsetAsync(ta.band_n, 0, 8, s));
+        HIPCHK(launch_tiles(precision, ta, s));
+        std::vector<float> g;
+        std::vector<double> nn, ee;
+        d2h(g, ta.debug_g, (int64_t)nrows * nrows, s);
+        d2h(nn, pk.dbg_norm2, nrows, s);
+        d2h(ee, pk.dbg_e, nrows, s);
+        HIPCHK(hipStreamSynchronize(s));
+        const double inv = 1.0 / (scale * scale);
+        for (int64_t i = 0; i < nrows; ++i)
+            for (int64_t j = 0; j < nrows; ++j) {
+                out_d2[i * nrows + j] = (nn[i] + nn[j] - 2.0 * (double)g[i * nrows + j]) * inv;
+                out_band[i * nrows + j] = 2.0 * (ee[i] + ee[j]) * inv;
+            }
+        return MAPPER_OK;
+    } catch (NoMem &) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_ENOMEM, "arena too small for the debug tiles");
+    } catch (DevError &de) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
+    }
+}

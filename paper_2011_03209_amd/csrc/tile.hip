@@ -1,0 +1,450 @@
+// tile.hip -- eps-neighbourhood of every cover element by matrix-core Gram tiles.
+//
+// DBSCAN (Ester et al.) needs, inside each pullback set, every pair's
+// decision D(x, y) <= eps^2; the paper names this all-pairs query as the cost
+// centre of DBSCAN-based mapper (Scalability section) and precomputes
+// distance matrices per interval.  Here the per-interval matrix is never
+// stored: with D = |x|^2 + |y|^2 - 2 x.y the only dense contraction is the
+// Gram block X_I X_J^T, computed on the matrix cores one 128 x 128 tile pair
+// (I <= J) at a time, and each pair leaves one bit.
+//
+// Decisions are certified: the per-slot thresholds A_s, B_s (packing stage)
+// bound every rounding and representation error of the tile's Gram value g,
+// so g >= A_i + A_j proves D <= eps^2 and g < B_i + B_j proves D > eps^2.
+// Pairs in between (the band) are appended to a list and re-decided with the
+// canonical FP64 distance by k_recheck, so the bitmask is exact whatever the
+// tile precision.
+//
+// Layout: a workgroup of 4 waves owns one tile pair; wave (wm, wn) owns the
+// 64 x 64 quadrant as 2 x 2 blocks of 32 x 32 accumulators.  K runs over
+// double-buffered LDS slabs of 128 bytes (64 bytes per panel for hi/lo
+// splits) per row, rows padded by 16 bytes so 16-byte fragment reads from 8
+// consecutive rows hit distinct banks.  In a 32x32 accumulator lane l holds
+// column l%32 of rows 8(v/4) + 4(l/32) + v%4 (v = 0..15), so a ballot of
+// register v yields two 32-bit row words of the bitmask directly.
+//
+// Bitmask: one 128 x 128-bit block (128 rows x 4 words) per tile pair, in the
+// element's pair order p = J(J+1)/2 + I; bit (r, c) means pair
+// (I*128 + r, J*128 + c) are neighbours.  Diagonal blocks keep only r <= c,
+// so every unordered pair is stored once.
+#include "internal.h"
+
+namespace mgpu {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 256;              // threads per workgroup
+
+template <int PREC> struct Cfg;
+template <> struct Cfg<P_FP32>   { static constexpr int ESZ = 4, KC = 32, PANELS = 1; };
+template <> struct Cfg<P_BF16>   { static constexpr int ESZ = 2, KC = 64, PANELS = 1; };
+template <> struct Cfg<P_FP16>   { static constexpr int ESZ = 2, KC = 64, PANELS = 1; };
+template <> struct Cfg<P_BF16X3> { static constexpr int ESZ = 2, KC = 32, PANELS = 2; };
+template <> struct Cfg<P_FP16X3> { static constexpr int ESZ = 2, KC = 32, PANELS = 2; };
+
+template <int PREC> struct Lay {
+    static constexpr int RB = Cfg<PREC>::KC * Cfg<PREC>::ESZ;   // bytes of a row per slab
+    static constexpr int RS = RB + 16;                          // padded LDS row stride
+    static constexpr int PANEL_BYTES = TILE * RS;                // one operand panel
+    static constexpr int STAGE_BYTES = 2 * Cfg<PREC>::PANELS * PANEL_BYTES;   // A and B
+    static constexpr int CHUNKS = TILE * RB / 16;                // 16-byte chunks per panel
+    static constexpr int CPT = CHUNKS / NT;                      // per thread
+    static constexpr int NREG = 2 * Cfg<PREC>::PANELS * CPT;
+};
+
+struct Tile {
+    int e, I, J;
+    int64_t ne, slot0, blk;
+};
+
+__device__ __forceinline__ Tile decode(const TileTable &t, int64_t item) {
+    int lo = 0, hi = t.nord;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t.item_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    Tile r;
+    r.e = t.order[lo];
+    const int64_t p = item - t.item_off[lo];
+    int64_t J = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((J + 1) * (J + 2) / 2 <= p) ++J;
+    while (J * (J + 1) / 2 > p) --J;
+    r.J = (int)J;
+    r.I = (int)(p - J * (J + 1) / 2);
+    r.slot0 = t.elem_off[r.e];
+    r.ne = t.elem_off[r.e + 1] - r.slot0;
+    r.blk = t.blk_off[r.e] + p;
+    return r;
+}
+
+template <int PREC>
+__device__ __forceinline__ void gload(const TileArgs &a, const Tile &tl, int k0, u32x4 *reg) {
+    using L = Lay<PREC>;
+    constexpr int CPR = L::RB / 16;        // chunks per row
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int64_t rb = side == 0 ? (int64_t)tl.I * TILE : (int64_t)tl.J * TILE;
+#pragma unroll
+        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl) {
+            const char *base = (const char *)(pnl == 0 ? a.panel_hi : a.panel_lo);
+#pragma unroll
+            for (int q = 0; q < L::CPT; ++q) {
+                const int idx = q * NT + threadIdx.x;
+                const int r = idx / CPR, c = idx % CPR;
+                int64_t row = rb + r;
+                if (row >= tl.ne) row = tl.ne - 1;                   // clamp; masked later
+                const int64_t slot = tl.slot0 + row;
+                const char *src = base + (slot * a.dp + k0) * Cfg<PREC>::ESZ + c * 16;
+                reg[(side * Cfg<PREC>::PANELS + pnl) * L::CPT + q] = *(const u32x4 *)src;
+            }
+        }
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void lstore(char *stage, const u32x4 *reg) {
+    using L = Lay<PREC>;
+    constexpr int CPR = L::RB / 16;
+#pragma unroll
+    for (int sp = 0; sp < 2 * Cfg<PREC>::PANELS; ++sp) {
+#pragma unroll
+        for (int q = 0; q < L::CPT; ++q) {
+            const int idx = q * NT + threadIdx.x;
+            const int r = idx / CPR, c = idx % CPR;
+            *(u32x4 *)(stage + sp * L::PANEL_BYTES + r * L::RS + c * 16) = reg[sp * L::CPT + q];
+        }
+    }
+}
+
+template <int PREC> struct Acc {
+    f32x16 c[2][2];
+    f32x16 x[2][2];   // cross-term accumulator of hi/lo splits
+};
+
+template <int PREC>
+__device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc, int wm, int wn) {
+    using L = Lay<PREC>;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int li = lane & 31, lg = lane >> 5;
+    const char *Ah = stage;
+    const char *Bh = stage + Cfg<PREC>::PANELS * L::PANEL_BYTES;
+    if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int ss = 0; ss < Cfg<PREC>::KC / 8; ++ss) {
+            f32x4 av[2], bv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                av[b] = *(const f32x4 *)(Ah + (wm * 64 + b * 32 + li) * L::RS + (8 * ss + 4 * lg) * 4);
+                bv[b] = *(const f32x4 *)(Bh + (wn * 64 + b * 32 + li) * L::RS + (8 * ss + 4 * lg) * 4);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                    for (int bn = 0; bn < 2; ++bn)
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[bm][t], bv[bn][t],
+                                                                            acc.c[bm][bn], 0, 0, 0);
+        }
+    } else {
+        constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
+        const char *Al = Ah + L::PANEL_BYTES;
+        const char *Bl = Bh + L::PANEL_BYTES;
+#pragma unroll
+        for (int ks = 0; ks < Cfg<PREC>::KC / 16; ++ks) {
+            u32x4 ah[2], bh[2], al[2], bl[2];
+            const int koff = (16 * ks + 8 * lg) * 2;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                ah[b] = *(const u32x4 *)(Ah + (wm * 64 + b * 32 + li) * L::RS + koff);
+                bh[b] = *(const u32x4 *)(Bh + (wn * 64 + b * 32 + li) * L::RS + koff);
+                if constexpr (SPLIT) {
+                    al[b] = *(const u32x4 *)(Al + (wm * 64 + b * 32 + li) * L::RS + koff);
+                    bl[b] = *(const u32x4 *)(Bl + (wn * 64 + b * 32 + li) * L::RS + koff);
+                }
+            }
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    if constexpr (PREC == P_BF16 || PREC == P_BF16X3) {
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
+                            acc.c[bm][bn], 0, 0, 0);
+                        if constexpr (SPLIT) {
+                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bl[bn]),
+                                acc.x[bm][bn], 0, 0, 0);
+                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, al[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
+                                acc.x[bm][bn], 0, 0, 0);
+                        }
+                    } else {
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
+                            acc.c[bm][bn], 0, 0, 0);
+                        if constexpr (SPLIT) {
+                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bl[bn]),
+                                acc.x[bm][bn], 0, 0, 0);
+                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                                __builtin_bit_cast(f16x8, al[bm]), __builtin_bit_cast(f16x8, bh[bn]),
+                                acc.x[bm][bn], 0, 0, 0);
+                        }
+                    }
+                }
+        }
+    }
+}
+
+struct EpiShared {
+    float thrA[2 * TILE];
+    float thrB[2 * TILE];
+    uint32_t words[TILE * 4];
+    int32_t rowcnt[TILE];
+    int32_t colcnt[TILE];
+};
+
+template <int PREC>
+__device__ void process_tile(const TileArgs &a, const Tile &tl, char *stages, EpiShared &es) {
+    using L = Lay<PREC>;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int wm = w >> 1, wn = w & 1;
+    const bool diag = tl.I == tl.J;
+
+    // thresholds of the tile's rows and columns; zero the count scratch
+    {
+        const int t = threadIdx.x;
+        const int64_t rb = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
+        const int64_t slot = tl.slot0 + (rb < tl.ne ? rb : tl.ne - 1);
+        es.thrA[t] = a.thrA[slot];
+        es.thrB[t] = a.thrB[slot];
+        if (t < TILE) { es.rowcnt[t] = 0; es.colcnt[t] = 0; }
+    }
+
+    Acc<PREC> acc;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { acc.c[bm][bn][v] = 0.f; acc.x[bm][bn][v] = 0.f; }
+
+    const int nst = a.dp / Cfg<PREC>::KC;
+    u32x4 reg[L::NREG];
+    gload<PREC>(a, tl, 0, reg);
+    lstore<PREC>(stages, reg);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        char *cur = stages + (st & 1) * L::STAGE_BYTES;
+        if (st + 1 < nst) gload<PREC>(a, tl, (st + 1) * Cfg<PREC>::KC, reg);
+        compute_stage<PREC>(cur, acc, wm, wn);
+        if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, reg);
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    const int li = lane & 31, lg = lane >> 5;
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            const int cl = wn * 64 + bn * 32 + li;             // column within the tile
+            const int64_t gc = (int64_t)tl.J * TILE + cl;      // element-local column
+            const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
+            const int myv = 4 * (li >> 3) + (li & 3), myh = (li >> 2) & 1;
+            uint32_t word = 0;
+            int colc = 0, nb = 0;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int rl = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lg + (v & 3);
+                const int64_t gr = (int64_t)tl.I * TILE + rl;
+                float g = acc.c[bm][bn][v];
+                if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+                const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+                const bool self = diag && rl == cl;
+                const bool in = valid && (self || g >= es.thrA[rl] + Aj);
+                const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
+                const uint64_t ib = __ballot(in);
+                // lane li (< 32) keeps row li of this 32 x 32 block
+                if (v == myv) word = myh ? (uint32_t)(ib >> 32) : (uint32_t)ib;
+                nb += __popcll(__ballot(band));
+                colc += (in && !self) ? 1 : 0;
+                if (a.debug_g && gr < tl.ne && gc < tl.ne) {
+                    a.debug_g[gr * a.debug_ld + gc] = g;
+                    a.debug_g[gc * a.debug_ld + gr] = g;
+                }
+            }
+            colc += __shfl_xor(colc, 32, WAVE);
+            if (lane < 32) {
+                const int rl = wm * 64 + bm * 32 + li;
+                es.words[rl * 4 + wn * 2 + bn] = word;
+                atomicAdd(&es.rowcnt[rl], (int32_t)__popc(word));
+                atomicAdd(&es.colcnt[cl], colc);
+            }
+            // band pairs -> FP64 recheck list (rare: a second pass, wave-aggregated append)
+            if (nb) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(a.band_n, (unsigned long long)nb);
+                base = __shfl(base, 0, WAVE);
+                int before = 0;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int rl = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lg + (v & 3);
+                    const int64_t gr = (int64_t)tl.I * TILE + rl;
+                    float g = acc.c[bm][bn][v];
+                    if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+                    const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+                    const bool self = diag && rl == cl;
+                    const bool in = valid && (self || g >= es.thrA[rl] + Aj);
+                    const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
+                    const uint64_t bb = __ballot(band);
+                    if (band) {
+                        const int64_t idx = (int64_t)base + before + __popcll(bb & lt);
+                        if (idx < a.band_cap) {
+                            BandPair bp;
+                            bp.si = (int32_t)(tl.slot0 + gr);
+                            bp.sj = (int32_t)(tl.slot0 + gc);
+                            bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(rl * 4 + (cl >> 5))) * 32u
+                                     + (uint64_t)(cl & 31);
+                            a.band[idx] = bp;
+                        }
+                    }
+                    before += __popcll(bb);
+                }
+            }
+        }
+    __syncthreads();
+    // bitmask block (2 KB, coalesced) and neighbour counts
+    {
+        uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
+        const int t = threadIdx.x;
+        *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
+        if (t < TILE) {
+            const int64_t r = (int64_t)tl.I * TILE + t;
+            if (r < tl.ne && es.rowcnt[t]) atomicAdd(&a.count[tl.slot0 + r], es.rowcnt[t]);
+        } else {
+            const int c = t - TILE;
+            const int64_t gc = (int64_t)tl.J * TILE + c;
+            if (gc < tl.ne && es.colcnt[c]) atomicAdd(&a.count[tl.slot0 + gc], es.colcnt[c]);
+        }
+    }
+    __syncthreads();
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
+    __shared__ EpiShared es;
+    // XCD-aware order: the hardware deals workgroups round-robin to the 8
+    // XCDs, so consecutive tile pairs (which share row panels) are mapped to
+    // one XCD and its L2.
+    const int64_t G = gridDim.x;
+    const int64_t per = (G + 7) / 8;
+    const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (item >= a.tt.n_items) return;
+    const Tile tl = decode(a.tt, item);
+    process_tile<PREC>(a, tl, stages, es);
+}
+
+__global__ void __launch_bounds__(256) k_recheck(const BandPair *band, int64_t nband, const float *X,
+                                                 int32_t d, const uint32_t *slot_point, double E,
+                                                 uint32_t *bitmask, int32_t *count) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nband) return;
+    const BandPair bp = band[t];
+    const float *x = X + (int64_t)slot_point[bp.si] * d;
+    const float *y = X + (int64_t)slot_point[bp.sj] * d;
+    double D = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        const double u = (double)x[j] - (double)y[j];
+        D = __builtin_fma(u, u, D);
+    }
+    if (D <= E) {
+        atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
+        atomicAdd(&count[bp.si], 1);
+        atomicAdd(&count[bp.sj], 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np,
+                                                  const float *X, int32_t d, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np) return;
+    const float *x = X + (int64_t)pa[t] * d;
+    const float *y = X + (int64_t)pb[t] * d;
+    double D = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+        const double u = (double)x[j] - (double)y[j];
+        D = __builtin_fma(u, u, D);
+    }
+    out[t] = D;
+}
+
+__global__ void __launch_bounds__(256) k_row_norm2(const int32_t *rows, int64_t nr, const float *X,
+                                                   int32_t d, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nr) return;
+    const float *x = X + (int64_t)rows[t] * d;
+    double s = 0.0;
+    for (int32_t j = 0; j < d; ++j) s += (double)x[j] * (double)x[j];
+    out[t] = s;
+}
+
+template <int PREC>
+hipError_t launch_t(const TileArgs &a, hipStream_t s) {
+    if (a.tt.n_items <= 0) return hipSuccess;
+    const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
+    k_tiles<PREC><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int tile_grid_size(int prec, int64_t n_items) {
+    (void)prec;
+    return (int)(8 * ((n_items + 7) / 8));
+}
+
+hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
+    switch (prec) {
+    case P_FP32: return launch_t<P_FP32>(a, s);
+    case P_BF16: return launch_t<P_BF16>(a, s);
+    case P_BF16X3: return launch_t<P_BF16X3>(a, s);
+    case P_FP16: return launch_t<P_FP16>(a, s);
+    case P_FP16X3: return launch_t<P_FP16X3>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
+                          const uint32_t *slot_point, double E, uint32_t *bitmask,
+                          int32_t *count, hipStream_t s) {
+    if (nband <= 0) return hipSuccess;
+    k_recheck<<<dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s>>>(band, nband, X, d, slot_point,
+                                                                          E, bitmask, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
+                            double *out, hipStream_t s) {
+    if (nr <= 0) return hipSuccess;
+    k_row_norm2<<<dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s>>>(rows, nr, X, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, const float *X,
+                           int32_t d, double *out, hipStream_t s) {
+    if (np <= 0) return hipSuccess;
+    k_pair_d64<<<dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s>>>(pa, pb, np, X, d, out);
+    return hipGetLastError();
+}
+
+}  // namespace mgpu

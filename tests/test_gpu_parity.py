@@ -1,0 +1,347 @@
+"""GPU mapper vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+The graph (node elements, node CSR, edges, weights) must be bit-identical to
+the oracle's for every tile precision; with the debug flag the per-stage
+arrays (lens values, cover endpoints, pullback sets, neighbour counts, core
+flags, node labels) must be identical too.  Sizes are chosen so that the
+oracle finishes in seconds while cover elements still span several 128-row
+tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_03209_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3, synth.PREC_FP16,
+         synth.PREC_FP16X3, synth.PREC_AUTO]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2011_03209_amd import binding
+    c = binding.Context(arena_bytes=48 << 30)
+    yield c
+    c.close()
+
+
+def same_graph(g, ref):
+    assert g.n_nodes == ref.n_nodes, (g.n_nodes, ref.n_nodes)
+    assert np.array_equal(g.node_element, ref.node_element)
+    assert np.array_equal(g.node_offsets, ref.node_offsets)
+    assert np.array_equal(g.node_members, ref.node_members)
+    assert np.array_equal(g.edges, ref.edges)
+    assert np.array_equal(g.edge_weights, ref.edge_weights)
+
+
+def same_stages(g, ref, n_axes):
+    s = g.stages
+    assert s["lens"].view(np.uint64).tolist() == ref.lens.reshape(-1).view(np.uint64).tolist()
+    assert np.array_equal(s["lo"], np.concatenate(ref.lo))
+    assert np.array_equal(s["hi"], np.concatenate(ref.hi))
+    assert np.array_equal(s["elem_offsets"], ref.elem_offsets)
+    assert np.array_equal(s["elem_members"], ref.elem_members)
+    assert np.array_equal(s["slot_count"], ref.slot_count)
+    assert np.array_equal(s["slot_core"].astype(bool), ref.slot_core.astype(bool))
+    assert np.array_equal(s["slot_node"], ref.slot_node)
+
+
+_ORACLE = {}
+
+
+def oracle_graph(X, params):
+    """The oracle does not depend on the tile precision: cache it per input."""
+    key = (X.shape, float(np.float64(X).sum()), float(np.abs(np.float64(X)).sum()), params.eps,
+           params.min_pts, tuple((a.kind, a.column, a.n_intervals, a.overlap,
+                                  None if a.direction is None else a.direction.tobytes(),
+                                  None if a.values is None else a.values.tobytes()) for a in params.axes))
+    if key not in _ORACLE:
+        _ORACLE[key] = O.mapper(X, params)
+    return _ORACLE[key]
+
+
+def run_and_compare(ctx, X, params, stages=True):
+    print(f"[case] n={X.shape[0]} d={X.shape[1]} prec={params.precision}", flush=True)
+    cloud = ctx.cloud(X)
+    try:
+        g = cloud.run(params, debug=stages)
+    finally:
+        cloud.destroy()
+    ref = oracle_graph(X, params)
+    if stages:
+        same_stages(g, ref, len(params.axes))
+    same_graph(g, ref)
+    return g, ref
+
+
+def with_prec(params, prec):
+    import copy
+    p = copy.copy(params)
+    p.precision = prec
+    return p
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_circle(ctx, prec):
+    w = synth.circle_2k()
+    g, ref = run_and_compare(ctx, w.X, with_prec(w.params, prec))
+    assert g.n_nodes == 18 and g.n_edges == 18
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixture_d64(ctx, prec):
+    w = synth.mixture_100k_d64(scale=0.06)
+    g, _ = run_and_compare(ctx, w.X, with_prec(w.params, prec))
+    assert g.stats["band_pairs"] >= 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixture_d256(ctx, prec):
+    w = synth.mixture_1m_d256(scale=0.012)
+    g, _ = run_and_compare(ctx, w.X, with_prec(w.params, prec))
+    assert g.stats["pairs"] > 0
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_FP16X3, synth.PREC_BF16])
+def test_grid_2d(ctx, prec):
+    w = synth.mixture_500k_d128_2d(scale=0.012)
+    run_and_compare(ctx, w.X, with_prec(w.params, prec))
+
+
+def _cases():
+    rng = np.random.default_rng(77)
+    out = []
+    # one point
+    out.append(("one_point", np.array([[1.0, 2.0]], np.float32),
+                synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2, column=0)], 0.5, 1)))
+    # all points identical: degenerate lens range, every point in every interval
+    out.append(("identical", np.ones((300, 5), np.float32),
+                synth.Params([synth.Axis(synth.LENS_L2, 4, 0.25)], 0.0, 3)))
+    # eps = 0: only duplicates are neighbours
+    Xd = rng.integers(0, 3, size=(400, 2)).astype(np.float32)
+    out.append(("eps0_duplicates", Xd, synth.Params([synth.Axis(synth.LENS_COLUMN, 2, 0.5, column=0)], 0.0, 2)))
+    # minPts = 1, single interval, d = 1
+    X1 = np.sort(rng.uniform(0, 100, size=(700, 1)).astype(np.float32), axis=0)
+    out.append(("d1_minpts1", X1, synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0)], 0.3, 1)))
+    # ragged K (d = 300) with element sizes around tile boundaries
+    for n in (127, 128, 129, 255, 257):
+        X = rng.normal(size=(n, 300)).astype(np.float32)
+        out.append((f"d300_n{n}", X, synth.Params([synth.Axis(synth.LENS_LINF, 1, 0.0)], 24.4, 3)))
+    # empty intervals (a gap in the lens), values lens, many intervals
+    Xg = np.concatenate([rng.normal(0, 1, (300, 3)), rng.normal(40, 1, (300, 3))]).astype(np.float32)
+    out.append(("gap", Xg, synth.Params([synth.Axis(synth.LENS_COLUMN, 25, 0.3, column=0)], 1.2, 4)))
+    vals = rng.normal(size=500)
+    Xv = rng.normal(size=(500, 7)).astype(np.float32)
+    out.append(("values", Xv, synth.Params([synth.Axis(synth.LENS_VALUES, 6, 0.45, values=vals)], 3.0, 4)))
+    out.append(("many_intervals", Xv, synth.Params([synth.Axis(synth.LENS_VALUES, 300, 0.6, values=vals)], 3.0, 2)))
+    # overlap >= 1/2: non-adjacent intervals share points
+    out.append(("overlap_0.8", Xv, synth.Params([synth.Axis(synth.LENS_L2, 7, 0.8)], 2.5, 3)))
+    # huge offset: large norms, cancellation in the Gram form
+    Xo = (rng.normal(size=(600, 64)) + 1000.0).astype(np.float32)
+    out.append(("offset1000", Xo, synth.Params([synth.Axis(synth.LENS_L2, 5, 0.3)], 11.3, 5)))
+    # tiny magnitudes (power-of-two rescaling keeps FP32/FP16 tiles exact-safe)
+    Xs = (rng.normal(size=(500, 16)) * 1e-20).astype(np.float32)
+    out.append(("tiny", Xs, synth.Params([synth.Axis(synth.LENS_L2, 3, 0.3)], 5.5e-20, 4)))
+    # 2-D with one axis of one interval
+    out.append(("2d_1x9", Xv, synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0),
+                                             synth.Axis(synth.LENS_COLUMN, 9, 0.5, column=1)], 3.0, 3)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3, synth.PREC_FP16])
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_edge_cases(ctx, case, prec):
+    name, X, params = CASES[case]
+    run_and_compare(ctx, X, with_prec(params, prec))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dyadic_ties(ctx, seed):
+    """Exact ties D == eps^2 and f == endpoint (the oracle is pinned to exact
+    arithmetic on these inputs)."""
+    rng = np.random.default_rng(500 + seed)
+    X = synth.dyadic_cloud(rng, 900, 3, grid=4, span=12)
+    params = synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.5, column=0)], eps=0.75, min_pts=4,
+                          precision=[synth.PREC_FP32, synth.PREC_BF16, synth.PREC_FP16X3, synth.PREC_BF16X3][seed])
+    g, ref = run_and_compare(ctx, X, params)
+    assert g.stats["band_pairs"] > 0          # ties must have gone through the FP64 recheck
+
+
+def _d64(X, rows):
+    m = len(rows)
+    out = np.zeros((m, m))
+    for i in range(m):
+        for j in range(m):
+            out[i, j] = O.pair_d2(X[rows[i]], X[rows[j]])
+    return out
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
+                                  synth.PREC_FP16, synth.PREC_FP16X3])
+@pytest.mark.parametrize("data", ["mix256", "offset", "neardup"])
+def test_tile_distances(ctx, prec, data):
+    """FP32 tiles: |D_tile - D64| <= 1e-5 (|x|^2 + |y|^2).  Every precision:
+    |D_tile - D64| <= the certified band the tile uses for its decisions."""
+    rng = np.random.default_rng(9)
+    if data == "mix256":
+        X, _ = synth.gaussian_mixture(rng, 300, 256, 4)
+    elif data == "offset":
+        X = (rng.normal(size=(300, 96)) + 3000.0).astype(np.float32)
+    else:
+        base = rng.normal(size=(30, 128)).astype(np.float32)
+        X = np.repeat(base, 10, axis=0) + rng.normal(scale=1e-4, size=(300, 128)).astype(np.float32)
+        X = X.astype(np.float32)
+    cloud = ctx.cloud(X)
+    try:
+        rows = np.arange(X.shape[0], dtype=np.int32)
+        d2, band = cloud.tile_d2(rows, prec, eps=1.0)
+    finally:
+        cloud.destroy()
+    ref = _d64(X, rows)
+    nrm = (X.astype(np.float64) ** 2).sum(axis=1)
+    err = np.abs(d2 - ref)
+    assert np.all(err <= band), float((err - band).max())
+    if prec == synth.PREC_FP32:
+        assert np.all(err <= 1e-5 * (nrm[:, None] + nrm[None, :]))
+
+
+def test_determinism_and_permutation(ctx):
+    w = synth.mixture_1m_d256(scale=0.008, precision=synth.PREC_BF16X3)
+    cloud = ctx.cloud(w.X)
+    g1 = cloud.run(w.params)
+    g2 = cloud.run(w.params)
+    cloud.destroy()
+    same_graph(g1, g2)
+    perm = np.random.default_rng(3).permutation(w.X.shape[0])
+    cloud = ctx.cloud(w.X[perm])
+    gp = cloud.run(w.params)
+    cloud.destroy()
+    # same clusters as point sets after mapping indices back (ids are canonical per input order)
+    def sets(g, mapping):
+        o = g.node_offsets
+        return sorted((int(g.node_element[v]), tuple(sorted(mapping[g.node_members[o[v]:o[v + 1]]].tolist())))
+                      for v in range(g.n_nodes))
+    assert sets(g1, np.arange(w.X.shape[0])) == sets(gp, perm)
+
+
+def test_serving_alone_vs_mix():
+    """Requests submitted together (overlapping on several streams) give the
+    same graphs as each request alone."""
+    from paper_2011_03209_amd import binding
+    ctx = binding.Context(arena_bytes=8 << 30, serving_streams=3)
+    try:
+        clouds = [ctx.cloud(X) for X in synth.serving_clouds(scale=0.01)]
+        raw = synth.serving_clouds(scale=0.01)
+        reqs = synth.serving_requests(raw, 12, qps=0.0)
+        alone = [clouds[c].run(p) for (_, c, p) in reqs]
+        tickets = [clouds[c].submit(p) for (_, c, p) in reqs]
+        mixed = [binding.wait(ctx, t) for t in tickets]
+        for a, b in zip(alone, mixed):
+            same_graph(a, b)
+        # and the oracle agrees on a few of them
+        for k in (0, 5, 11):
+            _, c, p = reqs[k]
+            same_graph(mixed[k], O.mapper(raw[c], p))
+        for c in clouds:
+            c.destroy()
+    finally:
+        ctx.close()
+
+
+def test_errors(ctx):
+    from paper_2011_03209_amd import binding
+    X = np.random.default_rng(1).normal(size=(100, 4)).astype(np.float32)
+    cloud = ctx.cloud(X)
+    bad = [synth.Params([synth.Axis(synth.LENS_COLUMN, 0, 0.2)], 1.0, 2),
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 1.0)], 1.0, 2),
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2, column=4)], 1.0, 2),
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], -1.0, 2),
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], float("nan"), 2),
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], 1.0, 0)]
+    for p in bad:
+        with pytest.raises(binding.MapperError) as ei:
+            cloud.run(p)
+        assert ei.value.code == binding.MAPPER_EINVAL
+    Xn = X.copy()
+    Xn[5, 2] = np.nan
+    with pytest.raises(binding.MapperError) as ei:
+        ctx.cloud(Xn)
+    assert ei.value.code == binding.MAPPER_EINVAL
+    # busy cloud
+    t = cloud.submit(synth.Params([synth.Axis(synth.LENS_L2, 3, 0.2)], 1.0, 2))
+    try:
+        cloud.destroy()
+        destroyed_early = True
+    except binding.MapperError as e:
+        assert e.code == binding.MAPPER_EBUSY
+        destroyed_early = False
+    binding.wait(ctx, t)
+    if not destroyed_early:
+        cloud.destroy()
+    # a tiny arena: ENOMEM, then the context still works
+    small = binding.Context(arena_bytes=2 << 20)
+    try:
+        big = small.cloud(np.random.default_rng(2).normal(size=(4000, 64)).astype(np.float32))
+        with pytest.raises(binding.MapperError) as ei:
+            big.run(synth.Params([synth.Axis(synth.LENS_L2, 1, 0.0)], 100.0, 2))
+        assert ei.value.code == binding.MAPPER_ENOMEM
+        big.destroy()
+        ok = small.cloud(X)
+        ok.run(synth.Params([synth.Axis(synth.LENS_L2, 2, 0.2)], 2.0, 2))
+        ok.destroy()
+    finally:
+        small.close()
+
+
+def test_full_size_1m_d256(ctx):
+    """Paper-scale cloud (1,000,000 x 256) in the benchmark's launch
+    configuration: the BF16 split path and the FP32 path give the identical
+    graph; sampled lens values and whole small elements match the oracle; the
+    graph satisfies the nerve invariants."""
+    w = synth.mixture_1m_d256()
+    cloud = ctx.cloud(w.X)
+    try:
+        gb = cloud.run(with_prec(w.params, synth.PREC_BF16X3), debug=True)
+        gf = cloud.run(with_prec(w.params, synth.PREC_FP32))
+    finally:
+        cloud.destroy()
+    same_graph(gb, gf)
+    ax = w.params.axes[0]
+    rng = np.random.default_rng(4)
+    pick = rng.choice(w.X.shape[0], 2000, replace=False)
+    f_ref = O.lens(w.X[pick], ax)
+    assert np.array_equal(gb.stages["lens"][pick], f_ref)
+    lo, hi = O.cover(float(gb.stages["lens"].min()), float(gb.stages["lens"].max()), ax.n_intervals, ax.overlap)
+    assert np.array_equal(gb.stages["lo"], lo) and np.array_equal(gb.stages["hi"], hi)
+    eo = gb.stages["elem_offsets"]
+    sizes = np.diff(eo)
+    f = gb.stages["lens"]
+    for e in np.argsort(sizes)[:6]:
+        if sizes[e] == 0:
+            continue
+        mem = gb.stages["elem_members"][eo[e]:eo[e + 1]]
+        want = np.nonzero((lo[e] <= f) & (f <= hi[e]))[0]
+        assert np.array_equal(mem, want)
+        cnt, core, cid = O.dbscan(w.X, mem, w.params.eps, w.params.min_pts)
+        assert np.array_equal(gb.stages["slot_count"][eo[e]:eo[e + 1]], cnt)
+        node = gb.stages["slot_node"][eo[e]:eo[e + 1]]
+        first = node[node >= 0].min() if (node >= 0).any() else 0
+        assert np.array_equal(np.where(node >= 0, node - first, -1), cid)
+    # nerve invariants over the whole graph
+    o = gb.node_offsets
+    owner = {}
+    for v in range(gb.n_nodes):
+        for p in gb.node_members[o[v]:o[v + 1]].tolist():
+            owner.setdefault(p, []).append(v)
+    want = {}
+    for vs in owner.values():
+        for i in range(len(vs)):
+            for j in range(i + 1, len(vs)):
+                want[(vs[i], vs[j])] = want.get((vs[i], vs[j]), 0) + 1
+    got = {(int(a), int(b)): int(c) for (a, b), c in zip(gb.edges, gb.edge_weights)}
+    assert got == want
