@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--sweep", action="store_true", help="time every tile precision (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
@@ -136,6 +137,16 @@ def main():
     ctx = binding.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
     cloud = ctx.cloud(w.X)
     print(f"[bench] workload {w.name} n={w.X.shape[0]} d={w.X.shape[1]} uploaded", file=sys.stderr, flush=True)
+    if args.sweep:
+        import copy
+        for pv in (0, 1, 2, 3, 4):
+            pp = copy.copy(w.params)
+            pp.precision = pv
+            _, ts, ss = time_path(cloud, pp, 2, 1)
+            print(json.dumps({"sweep": PREC_NAME[pv], "s_per_graph": float(np.median(ts)),
+                              **{k: ss[-1][k] for k in ("ms_tiles", "ms_recheck", "ms_cc", "ms_edges",
+                                                        "ms_lens", "ms_bin", "band_pairs")}}),
+                  file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

@@ -65,21 +65,12 @@ __device__ __forceinline__ WaveTile wave_decode(const TileTable &t, int64_t item
     WaveTile r;
     r.ok = item < t.n_items;
     if (!r.ok) return r;
-    int lo = 0, hi = t.nord;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (t.item_off[mid] <= item) lo = mid; else hi = mid;
-    }
-    const int e = t.order[lo];
-    const int64_t p = item - t.item_off[lo];
-    int64_t J = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while ((J + 1) * (J + 2) / 2 <= p) ++J;
-    while (J * (J + 1) / 2 > p) --J;
-    r.J = (int)J;
-    r.I = (int)(p - J * (J + 1) / 2);
-    r.slot0 = t.elem_off[e];
-    r.ne = t.elem_off[e + 1] - r.slot0;
-    r.blk = t.blk_off[e] + p;
+    const TilePos p = tile_decode(t, item);
+    r.ne = p.ne;
+    r.slot0 = p.slot0;
+    r.blk = p.blk;
+    r.I = p.I;
+    r.J = p.J;
     return r;
 }
 
@@ -91,59 +82,99 @@ __device__ __forceinline__ int64_t wave_item(int w) {
     return b * 4 + w;
 }
 
+// One wave per bitmask block.  The block (512 words) is held in registers,
+// 8 words per lane (lane l holds words 8l..8l+7, i.e. rows 2l and 2l+1); each
+// lane also holds the labels of rows l, l+64 and columns l, l+64, taken from
+// the global union-find at the start.  Row r is broadcast with readlane.  When
+// a core row has core neighbours with other labels, all those labels are
+// merged into the smallest one in registers and the merges are queued in LDS;
+// the queue is applied to the global union-find by all lanes in parallel, so
+// the row loop itself never waits on global memory.
+constexpr int CC_QCAP = 256;
+
+__device__ void cc_flush(int32_t *parent, int2 *q, int &nq) {
+    for (int i = (threadIdx.x & (WAVE - 1)); i < nq; i += WAVE) uf_union(parent, q[i].x, q[i].y);
+    nq = 0;
+}
+
 __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *bitmask,
                                                   const int32_t *count, int32_t min_pts,
                                                   int32_t *parent) {
-    __shared__ uint32_t words[4][TILE_WORDS];
-    __shared__ int32_t lab[4][2 * TILE];
+    __shared__ int2 queue[4][CC_QCAP];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const WaveTile tl = wave_decode(tt, wave_item(w));
     if (!tl.ok) return;
-    uint32_t *W = words[w];
-    int32_t *L = lab[w];
-    {
-        const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS);
-        ((uint4 *)W)[lane] = src[lane];
-        ((uint4 *)W)[lane + 64] = src[lane + 64];
-    }
-    uint64_t coreI[2], coreJ[2];
+    int2 *Q = queue[w];
+    int nq = 0;
+    int32_t lab[4];                                // rows lane, lane+64; columns lane, lane+64
+    uint64_t core[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int t = lane + 64 * q;                   // 0..127 rows, 128..255 columns
-        const int64_t loc = (t < TILE ? (int64_t)tl.I * TILE + t : (int64_t)tl.J * TILE + (t - TILE));
-        const bool core = loc < tl.ne && count[tl.slot0 + loc] >= min_pts;
-        L[t] = core ? uf_find(parent, (int32_t)(tl.slot0 + loc)) : -1;
-        const uint64_t m = __ballot(core);
-        if (q < 2) coreI[q] = m; else coreJ[q - 2] = m;
+        const int t = lane + 64 * (q & 1);
+        const int64_t loc = (q < 2 ? (int64_t)tl.I : (int64_t)tl.J) * TILE + t;
+        const bool c = loc < tl.ne && count[tl.slot0 + loc] >= min_pts;
+        lab[q] = c ? uf_find(parent, (int32_t)(tl.slot0 + loc)) : -1;
+        core[q] = __ballot(c);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (!((coreI[0] | coreI[1]) && (coreJ[0] | coreJ[1]))) return;
-    const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
+    if (!((core[0] | core[1]) && (core[2] | core[3]))) return;
+    uint32_t wd[8];
+    {
+        const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS) + 2 * lane;
+        const uint4 u0 = src[0], u1 = src[1];
+        wd[0] = u0.x; wd[1] = u0.y; wd[2] = u0.z; wd[3] = u0.w;
+        wd[4] = u1.x; wd[5] = u1.y; wd[6] = u1.z; wd[7] = u1.w;
+    }
+    constexpr int32_t BIG = 0x7fffffff;
     for (int r = 0; r < TILE; ++r) {
-        if (!((coreI[r >> 6] >> (r & 63)) & 1ull)) continue;
-        const uint32_t wa = W[r * 4 + (lane >> 5)], wb = W[r * 4 + 2 + (lane >> 5)];
-        const bool b0 = ((wa >> (lane & 31)) & 1u) && ((coreJ[0] >> lane) & 1ull);
-        const bool b1 = ((wb >> (lane & 31)) & 1u) && ((coreJ[1] >> lane) & 1ull);
-        uint64_t m0 = __ballot(b0 && L[r] != L[TILE + lane]);
-        uint64_t m1 = __ballot(b1 && L[r] != L[TILE + 64 + lane]);
-        while (m0 | m1) {
-            const int c = m0 ? __ffsll((long long)m0) - 1 : 64 + __ffsll((long long)m1) - 1;
-            const int32_t o1 = L[r], o2 = L[TILE + c];
-            int32_t root = 0;
-            if (lane == 0) root = uf_union(parent, (int32_t)(tl.slot0 + (int64_t)tl.I * TILE + r),
-                                           (int32_t)(colbase + c));
-            root = __shfl(root, 0, WAVE);
+        if (!((core[r >> 6] >> (r & 63)) & 1ull)) continue;
+        const int src = r >> 1;
+        uint32_t x0, x1, x2, x3;
+        if (r & 1) {
+            x0 = __builtin_amdgcn_readlane(wd[4], src); x1 = __builtin_amdgcn_readlane(wd[5], src);
+            x2 = __builtin_amdgcn_readlane(wd[6], src); x3 = __builtin_amdgcn_readlane(wd[7], src);
+        } else {
+            x0 = __builtin_amdgcn_readlane(wd[0], src); x1 = __builtin_amdgcn_readlane(wd[1], src);
+            x2 = __builtin_amdgcn_readlane(wd[2], src); x3 = __builtin_amdgcn_readlane(wd[3], src);
+        }
+        const uint64_t m0 = (((uint64_t)x1 << 32) | x0) & core[2];
+        const uint64_t m1 = (((uint64_t)x3 << 32) | x2) & core[3];
+        if ((m0 | m1) == 0) continue;
+        const int32_t lr = __builtin_amdgcn_readlane(r < 64 ? lab[0] : lab[1], r & 63);
+        int32_t v0 = (((m0 >> lane) & 1ull) && lab[2] != lr) ? lab[2] : BIG;
+        int32_t v1 = (((m1 >> lane) & 1ull) && lab[3] != lr) ? lab[3] : BIG;
+        if (__ballot(v0 != BIG || v1 != BIG) == 0) continue;
+        int32_t mn = min(v0, v1);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = lane + 64 * q;
-                const int32_t v = L[t];
-                if (v >= 0 && (v == o1 || v == o2)) L[t] = root;
+        for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, WAVE));
+        mn = min(mn, lr);
+        // every distinct label of the row's neighbourhood joins mn
+        while (true) {
+            const int32_t cand = v0 != BIG ? v0 : v1;
+            const uint64_t act = __ballot(cand != BIG);
+            if (act == 0) break;
+            const int32_t o = __builtin_amdgcn_readlane(cand, __ffsll((long long)act) - 1);
+            if (o != mn) {
+                if (lane == 0) Q[nq] = make_int2(mn, o);
+                ++nq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lab[q] = lab[q] == o ? mn : lab[q];
             }
+            v0 = v0 == o ? BIG : v0;
+            v1 = v1 == o ? BIG : v1;
+        }
+        if (lr != mn) {
+            if (lane == 0) Q[nq] = make_int2(mn, lr);
+            ++nq;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lab[q] = lab[q] == lr ? mn : lab[q];
+        }
+        if (nq > CC_QCAP - 130) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            m0 = __ballot(b0 && L[r] != L[TILE + lane]);
-            m1 = __ballot(b1 && L[r] != L[TILE + 64 + lane]);
+            cc_flush(parent, Q, nq);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    cc_flush(parent, Q, nq);
 }
 
 __global__ void k_cc_init(int32_t *parent, int64_t n) {

@@ -22,14 +22,68 @@ inline bool prec_is_bf16(int p) { return p == P_BF16 || p == P_BF16X3; }
 
 // Work table of the distance-tile launch.  Items are the tile pairs (I <= J)
 // of all elements, grouped by element in the order `order` (largest first).
+// Inside an element the tile pairs are visited in supertiles of SUPER x SUPER
+// pairs (upper triangle only), supertile columns left to right, supertiles of a
+// column top to bottom, and inside a supertile row blocks fastest.  Workgroups
+// that run together on one XCD thus share a few row panels in its L2.
+constexpr int SUPER = 8;
+
 struct TileTable {
     const int64_t *item_off;   // [nord+1] first item of each ordered element
     const int32_t *order;      // [nord] element id of each ordered entry
     const int64_t *elem_off;   // [E+1] first slot of each element
     const int64_t *blk_off;    // [E] first bitmask block of each element
+    const int64_t *colpre;     // per element: items before each supertile column (Ts+1)
+    const int64_t *cp_off;     // [E] start of the element's colpre entries
     int32_t nord;
     int64_t n_items;
 };
+
+struct TilePos {
+    int e, I, J;
+    int64_t ne, slot0, blk;
+};
+
+// Item (global tile-pair index) -> element, row block I, column block J (I <= J)
+// and the bitmask block that stores it.
+__device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item) {
+    int lo = 0, hi = t.nord;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t.item_off[mid] <= item) lo = mid; else hi = mid;
+    }
+    TilePos r;
+    r.e = t.order[lo];
+    const int64_t p = item - t.item_off[lo];
+    r.slot0 = t.elem_off[r.e];
+    r.ne = t.elem_off[r.e + 1] - r.slot0;
+    r.blk = t.blk_off[r.e] + p;
+    const int64_t T = (r.ne + TILE - 1) / TILE;
+    const int64_t Ts = (T + SUPER - 1) / SUPER;
+    const int64_t *cp = t.colpre + t.cp_off[r.e];
+    int64_t a = 0, b = Ts;                         // largest SJ with cp[SJ] <= p
+    while (b - a > 1) {
+        const int64_t mid = (a + b) >> 1;
+        if (cp[mid] <= p) a = mid; else b = mid;
+    }
+    const int64_t SJ = a;
+    const int64_t q = p - cp[SJ];
+    const int64_t cols = (T - SJ * SUPER) < SUPER ? (T - SJ * SUPER) : SUPER;
+    const int64_t per = SUPER * cols;
+    if (q < SJ * per) {
+        const int64_t SI = q / per, loc = q - SI * per;
+        r.I = (int)(SI * SUPER + loc % SUPER);
+        r.J = (int)(SJ * SUPER + loc / SUPER);
+    } else {
+        const int64_t loc = q - SJ * per;
+        int64_t j = (int64_t)((sqrt(8.0 * (double)loc + 1.0) - 1.0) * 0.5);
+        while ((j + 1) * (j + 2) / 2 <= loc) ++j;
+        while (j * (j + 1) / 2 > loc) --j;
+        r.I = (int)(SJ * SUPER + (loc - j * (j + 1) / 2));
+        r.J = (int)(SJ * SUPER + j);
+    }
+    return r;
+}
 
 // One pair whose tile distance fell inside the certified band of eps^2.
 struct BandPair {

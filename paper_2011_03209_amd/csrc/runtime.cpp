@@ -334,6 +334,25 @@ struct Events {
     }
 };
 
+// Items before each supertile column of every element (see tile_decode).
+void build_supertile_columns(const std::vector<int64_t> &T, std::vector<int64_t> &colpre,
+                             std::vector<int64_t> &cp_off) {
+    colpre.clear();
+    for (size_t e = 0; e < T.size(); ++e) {
+        const int64_t Ts = (T[e] + SUPER - 1) / SUPER;
+        cp_off[e] = (int64_t)colpre.size();
+        int64_t acc = 0;
+        colpre.push_back(0);
+        for (int64_t SJ = 0; SJ < Ts; ++SJ) {
+            const int64_t cols = std::min<int64_t>(SUPER, T[e] - SJ * SUPER);
+            acc += SJ * SUPER * cols + cols * (cols + 1) / 2;
+            colpre.push_back(acc);
+        }
+        if (acc != T[e] * (T[e] + 1) / 2) throw std::runtime_error("supertile table mismatch");
+    }
+    if (colpre.empty()) colpre.push_back(0);
+}
+
 // ----------------------------------------------------------------- autotuner
 // Precision choice: predicted time = matrix-core time + (band fraction x FP64
 // recheck time).  The band fraction of each precision is measured on a
@@ -504,6 +523,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         if (ne > 0) order.push_back((int32_t)e);
     }
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P_e[a] > P_e[b]; });
+    std::vector<int64_t> colpre, cp_off(E_count);
+    build_supertile_columns(T, colpre, cp_off);
     std::vector<int64_t> item_off(order.size() + 1, 0);
     for (size_t k = 0; k < order.size(); ++k) item_off[k + 1] = item_off[k] + P_e[order[k]];
     st.n_slots = S;
@@ -574,6 +595,12 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     tt.order = d_order;
     tt.elem_off = elem_off;
     tt.blk_off = d_blk_off;
+    int64_t *d_colpre = mem.get<int64_t>(colpre.size());
+    int64_t *d_cp_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
+    h2d(d_colpre, colpre.data(), (int64_t)colpre.size(), s);
+    h2d(d_cp_off, cp_off.data(), E_count, s);
+    tt.colpre = d_colpre;
+    tt.cp_off = d_cp_off;
     tt.nord = (int32_t)order.size();
     tt.n_items = nblocks;
 
@@ -1099,6 +1126,13 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.tt.order = d_od;
         ta.tt.elem_off = d_eo;
         ta.tt.blk_off = d_bo;
+        std::vector<int64_t> colpre, cp_off(1);
+        build_supertile_columns(std::vector<int64_t>{T}, colpre, cp_off);
+        int64_t *d_cp = mem.get<int64_t>(colpre.size()), *d_cpo = mem.get<int64_t>(1);
+        h2d(d_cp, colpre.data(), (int64_t)colpre.size(), s);
+        h2d(d_cpo, cp_off.data(), 1, s);
+        ta.tt.colpre = d_cp;
+        ta.tt.cp_off = d_cpo;
         ta.tt.nord = 1;
         ta.tt.n_items = P;
         ta.panel_hi = pk.panel_hi;

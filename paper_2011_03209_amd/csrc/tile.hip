@@ -58,33 +58,8 @@ template <int PREC> struct Lay {
     static constexpr int NREG = 2 * Cfg<PREC>::PANELS * CPT;
 };
 
-struct Tile {
-    int e, I, J;
-    int64_t ne, slot0, blk;
-};
-
-__device__ __forceinline__ Tile decode(const TileTable &t, int64_t item) {
-    int lo = 0, hi = t.nord;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (t.item_off[mid] <= item) lo = mid; else hi = mid;
-    }
-    Tile r;
-    r.e = t.order[lo];
-    const int64_t p = item - t.item_off[lo];
-    int64_t J = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while ((J + 1) * (J + 2) / 2 <= p) ++J;
-    while (J * (J + 1) / 2 > p) --J;
-    r.J = (int)J;
-    r.I = (int)(p - J * (J + 1) / 2);
-    r.slot0 = t.elem_off[r.e];
-    r.ne = t.elem_off[r.e + 1] - r.slot0;
-    r.blk = t.blk_off[r.e] + p;
-    return r;
-}
-
 template <int PREC>
-__device__ __forceinline__ void gload(const TileArgs &a, const Tile &tl, int k0, u32x4 *reg) {
+__device__ __forceinline__ void gload(const TileArgs &a, const TilePos &tl, int k0, u32x4 *reg) {
     using L = Lay<PREC>;
     constexpr int CPR = L::RB / 16;        // chunks per row
 #pragma unroll
@@ -204,15 +179,107 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
 }
 
 struct EpiShared {
-    float thrA[2 * TILE];
-    float thrB[2 * TILE];
+    __attribute__((aligned(16))) float thrA[2 * TILE];
+    __attribute__((aligned(16))) float thrB[2 * TILE];
     uint32_t words[TILE * 4];
     int32_t rowcnt[TILE];
     int32_t colcnt[TILE];
 };
 
-template <int PREC>
-__device__ void process_tile(const TileArgs &a, const Tile &tl, char *stages, EpiShared &es) {
+// Decisions of one 32 x 32 accumulator block.  FULL: the block lies inside the
+// element and off the diagonal, so no bounds or triangle masks are needed.
+template <int PREC, bool FULL, bool DEBUG>
+__device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
+                                          const Acc<PREC> &acc, int bm, int bn, int wm, int wn) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int li = lane & 31, lg = lane >> 5;
+    const bool diag = tl.I == tl.J;
+    const int cl = wn * 64 + bn * 32 + li;                  // column within the tile
+    const int64_t gc = (int64_t)tl.J * TILE + cl;          // element-local column
+    const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
+    const int r0 = wm * 64 + bm * 32 + 4 * lg;             // register v holds row r0 + 8(v/4) + v%4
+    f32x4 TA[4], TB[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        TA[q] = *(const f32x4 *)&es.thrA[r0 + 8 * q];
+        TB[q] = *(const f32x4 *)&es.thrB[r0 + 8 * q];
+    }
+    const int myv = 4 * (li >> 3) + (li & 3);              // lane li (< 32) collects row li
+    uint64_t sel = 0;
+    int colc = 0, nb = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        float g = acc.c[bm][bn][v];
+        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+        bool in, band;
+        if constexpr (FULL) {
+            in = g >= TA[v >> 2][v & 3] + Aj;
+            band = !in && !(g < TB[v >> 2][v & 3] + Bj);
+            colc += in ? 1 : 0;
+        } else {
+            const int rl = r0 + 8 * (v >> 2) + (v & 3);
+            const int64_t gr = (int64_t)tl.I * TILE + rl;
+            const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+            const bool self = diag && rl == cl;
+            in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
+            band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
+            colc += (in && !self) ? 1 : 0;
+            if constexpr (DEBUG) {
+                if (gr < tl.ne && gc < tl.ne) {
+                    a.debug_g[gr * a.debug_ld + gc] = g;
+                    a.debug_g[gc * a.debug_ld + gr] = g;
+                }
+            }
+        }
+        const uint64_t ib = __ballot(in);
+        if (v == myv) sel = ib;
+        nb += __popcll(__ballot(band));
+    }
+    const uint32_t word = ((li >> 2) & 1) ? (uint32_t)(sel >> 32) : (uint32_t)sel;
+    colc += __shfl_xor(colc, 32, WAVE);
+    if (lane < 32) {
+        const int rl = wm * 64 + bm * 32 + li;
+        es.words[rl * 4 + wn * 2 + bn] = word;
+        atomicAdd(&es.rowcnt[rl], (int32_t)__popc(word));
+        atomicAdd(&es.colcnt[cl], colc);
+    }
+    if (nb == 0) return;
+    // band pairs -> FP64 recheck list (rare: second pass, wave-aggregated append)
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.band_n, (unsigned long long)nb);
+    base = __shfl(base, 0, WAVE);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int before = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int rl = r0 + 8 * (v >> 2) + (v & 3);
+        const int64_t gr = (int64_t)tl.I * TILE + rl;
+        float g = acc.c[bm][bn][v];
+        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+        // opaque copy: keeps the first pass's compare masks from living until here
+        asm volatile("" : "+v"(g));
+        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+        const bool self = diag && rl == cl;
+        const bool in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
+        const bool band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
+        const uint64_t bb = __ballot(band);
+        if (band) {
+            const int64_t idx = (int64_t)base + before + __popcll(bb & lt);
+            if (idx < a.band_cap) {
+                BandPair bp;
+                bp.si = (int32_t)(tl.slot0 + gr);
+                bp.sj = (int32_t)(tl.slot0 + gc);
+                bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(rl * 4 + (cl >> 5))) * 32u
+                         + (uint64_t)(cl & 31);
+                a.band[idx] = bp;
+            }
+        }
+        before += __popcll(bb);
+    }
+}
+
+template <int PREC, bool DEBUG>
+__device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared &es) {
     using L = Lay<PREC>;
     const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const int wm = w >> 1, wn = w & 1;
@@ -250,76 +317,13 @@ __device__ void process_tile(const TileArgs &a, const Tile &tl, char *stages, Ep
     }
 
     // ---------------------------------------------------------------- epilogue
-    const int li = lane & 31, lg = lane >> 5;
-    const uint64_t lt = (1ull << lane) - 1ull;
+    const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) {
-            const int cl = wn * 64 + bn * 32 + li;             // column within the tile
-            const int64_t gc = (int64_t)tl.J * TILE + cl;      // element-local column
-            const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
-            const int myv = 4 * (li >> 3) + (li & 3), myh = (li >> 2) & 1;
-            uint32_t word = 0;
-            int colc = 0, nb = 0;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int rl = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lg + (v & 3);
-                const int64_t gr = (int64_t)tl.I * TILE + rl;
-                float g = acc.c[bm][bn][v];
-                if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
-                const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
-                const bool self = diag && rl == cl;
-                const bool in = valid && (self || g >= es.thrA[rl] + Aj);
-                const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
-                const uint64_t ib = __ballot(in);
-                // lane li (< 32) keeps row li of this 32 x 32 block
-                if (v == myv) word = myh ? (uint32_t)(ib >> 32) : (uint32_t)ib;
-                nb += __popcll(__ballot(band));
-                colc += (in && !self) ? 1 : 0;
-                if (a.debug_g && gr < tl.ne && gc < tl.ne) {
-                    a.debug_g[gr * a.debug_ld + gc] = g;
-                    a.debug_g[gc * a.debug_ld + gr] = g;
-                }
-            }
-            colc += __shfl_xor(colc, 32, WAVE);
-            if (lane < 32) {
-                const int rl = wm * 64 + bm * 32 + li;
-                es.words[rl * 4 + wn * 2 + bn] = word;
-                atomicAdd(&es.rowcnt[rl], (int32_t)__popc(word));
-                atomicAdd(&es.colcnt[cl], colc);
-            }
-            // band pairs -> FP64 recheck list (rare: a second pass, wave-aggregated append)
-            if (nb) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(a.band_n, (unsigned long long)nb);
-                base = __shfl(base, 0, WAVE);
-                int before = 0;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int rl = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * lg + (v & 3);
-                    const int64_t gr = (int64_t)tl.I * TILE + rl;
-                    float g = acc.c[bm][bn][v];
-                    if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
-                    const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
-                    const bool self = diag && rl == cl;
-                    const bool in = valid && (self || g >= es.thrA[rl] + Aj);
-                    const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
-                    const uint64_t bb = __ballot(band);
-                    if (band) {
-                        const int64_t idx = (int64_t)base + before + __popcll(bb & lt);
-                        if (idx < a.band_cap) {
-                            BandPair bp;
-                            bp.si = (int32_t)(tl.slot0 + gr);
-                            bp.sj = (int32_t)(tl.slot0 + gc);
-                            bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(rl * 4 + (cl >> 5))) * 32u
-                                     + (uint64_t)(cl & 31);
-                            a.band[idx] = bp;
-                        }
-                    }
-                    before += __popcll(bb);
-                }
-            }
+            if (!DEBUG && full) epi_block<PREC, true, false>(a, tl, es, acc, bm, bn, wm, wn);
+            else epi_block<PREC, false, DEBUG>(a, tl, es, acc, bm, bn, wm, wn);
         }
     __syncthreads();
     // bitmask block (2 KB, coalesced) and neighbour counts
@@ -339,7 +343,7 @@ __device__ void process_tile(const TileArgs &a, const Tile &tl, char *stages, Ep
     __syncthreads();
 }
 
-template <int PREC>
+template <int PREC, bool DEBUG>
 __global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
     __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
     __shared__ EpiShared es;
@@ -350,27 +354,53 @@ __global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
     const int64_t per = (G + 7) / 8;
     const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (item >= a.tt.n_items) return;
-    const Tile tl = decode(a.tt, item);
-    process_tile<PREC>(a, tl, stages, es);
+    const TilePos tl = tile_decode(a.tt, item);
+    process_tile<PREC, DEBUG>(a, tl, stages, es);
 }
 
+// FP64 re-decision of band pairs, one pair per wave at a time.  The lanes
+// read the two rows with coalesced loads and sum (x_j - y_j)^2 in FP64 as a
+// tree; that value is within 2 gamma_{d+4} D of the canonical sequential
+// chain, so only pairs closer than that to eps^2 (ties, in practice) need
+// the canonical chain itself, which lane 0 then evaluates in order.
 __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, int64_t nband, const float *X,
                                                  int32_t d, const uint32_t *slot_point, double E,
                                                  uint32_t *bitmask, int32_t *count) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nband) return;
-    const BandPair bp = band[t];
-    const float *x = X + (int64_t)slot_point[bp.si] * d;
-    const float *y = X + (int64_t)slot_point[bp.sj] * d;
-    double D = 0.0;
-    for (int32_t j = 0; j < d; ++j) {
-        const double u = (double)x[j] - (double)y[j];
-        D = __builtin_fma(u, u, D);
-    }
-    if (D <= E) {
-        atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
-        atomicAdd(&count[bp.si], 1);
-        atomicAdd(&count[bp.sj], 1);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const double u = 0x1.0p-53;
+    const double gd = (d + 4) * u / (1.0 - (d + 4) * u);
+    const double cf = 4.0 * gd / (1.0 - gd);              // twice the certified gap, for margin
+    for (int64_t b = wid; b < nband; b += nw) {
+        const BandPair bp = band[b];
+        const float *x = X + (int64_t)slot_point[bp.si] * d;
+        const float *y = X + (int64_t)slot_point[bp.sj] * d;
+        double part = 0.0;
+        for (int32_t j = lane; j < d; j += WAVE) {
+            const double t = (double)x[j] - (double)y[j];
+            part = __builtin_fma(t, t, part);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
+        bool in;
+        if (fabs(part - E) > cf * part) {
+            in = part <= E;
+        } else {
+            double D = 0.0;                                 // canonical chain, in order
+            if (lane == 0)
+                for (int32_t j = 0; j < d; ++j) {
+                    const double t = (double)x[j] - (double)y[j];
+                    D = __builtin_fma(t, t, D);
+                }
+            D = __shfl(D, 0, WAVE);
+            in = D <= E;
+        }
+        if (in && lane == 0) {
+            atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
+            atomicAdd(&count[bp.si], 1);
+            atomicAdd(&count[bp.sj], 1);
+        }
     }
 }
 
@@ -402,7 +432,8 @@ template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
-    k_tiles<PREC><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
+    if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
+    else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -428,8 +459,9 @@ hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, i
                           const uint32_t *slot_point, double E, uint32_t *bitmask,
                           int32_t *count, hipStream_t s) {
     if (nband <= 0) return hipSuccess;
-    k_recheck<<<dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s>>>(band, nband, X, d, slot_point,
-                                                                          E, bitmask, count);
+    int64_t blocks = (nband + 3) / 4;
+    if (blocks > 32768) blocks = 32768;
+    k_recheck<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(band, nband, X, d, slot_point, E, bitmask, count);
     return hipGetLastError();
 }
 
