@@ -44,15 +44,15 @@ def workload(name: str, precision: int):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_path(cloud, params, steps: int, warmup: int):
+def time_path(cloud, params, steps: int, warmup: int, flags: int = 0):
     import torch
     for _ in range(warmup):
-        g = cloud.run(params)
+        g = cloud.run(params, flags=flags)
     torch.cuda.synchronize()
     times, stats = [], []
     for _ in range(steps):
         t0 = time.perf_counter()
-        g = cloud.run(params)
+        g = cloud.run(params, flags=flags)
         times.append(time.perf_counter() - t0)
         stats.append(g.stats)
     torch.cuda.synchronize()
@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--sweep", action="store_true", help="time every tile precision (stderr)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a plain copy kernel of known "
+                         "size, used to scale FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
@@ -133,6 +136,12 @@ def main():
     import torch
     from paper_2011_03209_amd import binding
     prec = {"fp32": 0, "bf16": 1, "bf16x3": 2, "fp16": 3, "fp16x3": 4, "auto": 5}[args.precision]
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workload(args.workload, prec)
     ctx = binding.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
     cloud = ctx.cloud(w.X)
@@ -147,6 +156,9 @@ def main():
                               **{k: ss[-1][k] for k in ("ms_tiles", "ms_recheck", "ms_cc", "ms_edges",
                                                         "ms_lens", "ms_bin", "band_pairs")}}),
                   file=sys.stderr, flush=True)
+        _, ts, ss = time_path(cloud, w.params, 2, 1, flags=binding.FLAG_GRID_LAUNCH)
+        print(json.dumps({"sweep": "grid-launch " + args.precision, "s_per_graph": float(np.median(ts)),
+                          "ms_tiles": ss[-1]["ms_tiles"]}), file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

@@ -102,6 +102,8 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
+#define MAPPER_FLAG_GRID_LAUNCH 2u    /* one workgroup per tile pair instead of the
+                                         persistent launch (for comparison) */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmapper_gpu.so")
 MAPPER_OK, MAPPER_EINVAL, MAPPER_ENOMEM, MAPPER_EDEVICE = 0, -1, -2, -3
 MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
+FLAG_GRID_LAUNCH = 2
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
 
@@ -272,9 +273,9 @@ class Cloud:
             _check(self.ctx.L.mapper_cloud_destroy(self.h))
             self.h = None
 
-    def run(self, params, debug: bool = False) -> Graph:
+    def run(self, params, debug: bool = False, flags: int = 0) -> Graph:
         keep: list = []
-        p = make_params(params, FLAG_DEBUG_STAGES if debug else 0, keep)
+        p = make_params(params, flags | (FLAG_DEBUG_STAGES if debug else 0), keep)
         g = _vp()
         _check(self.ctx.L.mapper_run(self.ctx.h, self.h, ctypes.byref(p), ctypes.byref(g)))
         return _take_graph(g)

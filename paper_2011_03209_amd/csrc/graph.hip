@@ -1,14 +1,12 @@
 // graph.hip -- DBSCAN clusters from the adjacency bitmask, and the mapper graph.
 //
 // Clusters (DBSCAN, Ester et al.): connected components of the core points
-// under the eps-neighbour relation.  One wave takes one bitmask block (128 x
-// 128 bits): it caches the block and a label per row and column in LDS, and
-// for every core row tests 64 columns per step with the lanes as bit
-// positions.  Only pairs whose cached labels differ reach the global
-// union-find (lock-free, hooking the larger root under the smaller, so every
-// root ends as its component's smallest slot); after each union the cached
-// labels of both merged sets are rewritten, so a dense cluster costs a few
-// unions per block instead of one per edge.
+// under the eps-neighbour relation, computed with a lock-free union-find whose
+// roots are the smallest slot of each component (hooking always attaches the
+// larger root under the smaller).  One wave checks one bitmask block (128 x
+// 128 bits) against the current labels with ballots and only queues merges
+// for rows that join different labels; the queued merges are applied by all
+// lanes at once (see k_cc_tiles).
 //
 // Border points: a non-core point with core neighbours joins the lowest node
 // id among them (atomicMin over the same blocks).  Nodes are numbered by a
@@ -40,6 +38,18 @@ __device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x) {
         __hip_atomic_store(&P[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = gp;
     }
+}
+
+// An ancestor of x, following parents with ordinary (cacheable) loads and no
+// writes.  A stale parent is still an ancestor, so the result is always a
+// member of x's set; it serves as a label, never as a hook target.
+__device__ __forceinline__ int32_t uf_label(const int32_t *P, int32_t x) {
+    int32_t p = P[x];
+    while (p != x) {
+        x = p;
+        p = P[x];
+    }
+    return x;
 }
 
 // Merge the sets of a and b; returns a representative of the merged set.
@@ -82,17 +92,30 @@ __device__ __forceinline__ int64_t wave_item(int w) {
     return b * 4 + w;
 }
 
-// One wave per bitmask block.  The block (512 words) is held in registers,
-// 8 words per lane (lane l holds words 8l..8l+7, i.e. rows 2l and 2l+1); each
-// lane also holds the labels of rows l, l+64 and columns l, l+64, taken from
-// the global union-find at the start.  Row r is broadcast with readlane.  When
-// a core row has core neighbours with other labels, all those labels are
-// merged into the smallest one in registers and the merges are queued in LDS;
-// the queue is applied to the global union-find by all lanes in parallel, so
-// the row loop itself never waits on global memory.
+// One wave per bitmask block; lane l holds the block's rows 2l and 2l+1 (8
+// words), their labels, and the labels of columns l and l+64.  Labels come
+// from the global union-find at the start (any ancestor will do).
+//
+// A block is consistent when every core-core bit joins two equal labels.  For
+// each distinct column label L the wave builds the 128-bit mask of columns
+// labelled L with two ballots; each lane then checks its two rows against the
+// mask of its own row label, all lanes at once.  Only rows that fail go
+// through the merge step: the row's label and every differing neighbour label
+// are merged into the smallest one in registers, and the merges are queued in
+// LDS and applied to the global union-find by all lanes in parallel.  Rounds
+// repeat until the block is consistent (each failing round merges labels).
 constexpr int CC_QCAP = 256;
 
+// The 64-bit value v held by lane `src` (readlane returns a signed 32-bit
+// int, so each half is widened as unsigned).
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ void cc_flush(int32_t *parent, int2 *q, int &nq) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     for (int i = (threadIdx.x & (WAVE - 1)); i < nq; i += WAVE) uf_union(parent, q[i].x, q[i].y);
     nq = 0;
 }
@@ -106,17 +129,21 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
     if (!tl.ok) return;
     int2 *Q = queue[w];
     int nq = 0;
-    int32_t lab[4];                                // rows lane, lane+64; columns lane, lane+64
-    uint64_t core[4];
+    constexpr int32_t BIG = 0x7fffffff;
+    const int64_t rowbase = tl.slot0 + (int64_t)tl.I * TILE;
+    const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
+    // labels: lab[0], lab[1] = rows 2l, 2l+1; lab[2], lab[3] = columns l, l+64
+    int32_t lab[4];
+    bool cr[2];
+    uint64_t cc[2];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int t = lane + 64 * (q & 1);
-        const int64_t loc = (q < 2 ? (int64_t)tl.I : (int64_t)tl.J) * TILE + t;
+        const int64_t loc = q < 2 ? (int64_t)tl.I * TILE + 2 * lane + q : (int64_t)tl.J * TILE + lane + 64 * (q - 2);
         const bool c = loc < tl.ne && count[tl.slot0 + loc] >= min_pts;
-        lab[q] = c ? uf_find(parent, (int32_t)(tl.slot0 + loc)) : -1;
-        core[q] = __ballot(c);
+        lab[q] = c ? uf_label(parent, (int32_t)(tl.slot0 + loc)) : -1;
+        if (q < 2) cr[q] = c; else cc[q - 2] = __ballot(c);
     }
-    if (!((core[0] | core[1]) && (core[2] | core[3]))) return;
+    if (__ballot(cr[0] || cr[1]) == 0 || (cc[0] | cc[1]) == 0) return;
     uint32_t wd[8];
     {
         const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS) + 2 * lane;
@@ -124,57 +151,71 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
         wd[0] = u0.x; wd[1] = u0.y; wd[2] = u0.z; wd[3] = u0.w;
         wd[4] = u1.x; wd[5] = u1.y; wd[6] = u1.z; wd[7] = u1.w;
     }
-    constexpr int32_t BIG = 0x7fffffff;
-    for (int r = 0; r < TILE; ++r) {
-        if (!((core[r >> 6] >> (r & 63)) & 1ull)) continue;
-        const int src = r >> 1;
-        uint32_t x0, x1, x2, x3;
-        if (r & 1) {
-            x0 = __builtin_amdgcn_readlane(wd[4], src); x1 = __builtin_amdgcn_readlane(wd[5], src);
-            x2 = __builtin_amdgcn_readlane(wd[6], src); x3 = __builtin_amdgcn_readlane(wd[7], src);
-        } else {
-            x0 = __builtin_amdgcn_readlane(wd[0], src); x1 = __builtin_amdgcn_readlane(wd[1], src);
-            x2 = __builtin_amdgcn_readlane(wd[2], src); x3 = __builtin_amdgcn_readlane(wd[3], src);
+    // core-core bits of my two rows (columns 0..63 and 64..127)
+    const uint64_t b00 = cr[0] ? ((((uint64_t)wd[1] << 32) | wd[0]) & cc[0]) : 0;
+    const uint64_t b01 = cr[0] ? ((((uint64_t)wd[3] << 32) | wd[2]) & cc[1]) : 0;
+    const uint64_t b10 = cr[1] ? ((((uint64_t)wd[5] << 32) | wd[4]) & cc[0]) : 0;
+    const uint64_t b11 = cr[1] ? ((((uint64_t)wd[7] << 32) | wd[6]) & cc[1]) : 0;
+    for (int round = 0;; ++round) {
+        // masks of the columns that carry each of my row labels
+        uint64_t m00 = 0, m01 = 0, m10 = 0, m11 = 0;
+        uint64_t p0 = cc[0], p1 = cc[1];
+        while (p0 | p1) {
+            const int32_t L = p0 ? __builtin_amdgcn_readlane(lab[2], __ffsll((long long)p0) - 1)
+                                 : __builtin_amdgcn_readlane(lab[3], __ffsll((long long)p1) - 1);
+            const uint64_t e0 = __ballot(lab[2] == L) & cc[0], e1 = __ballot(lab[3] == L) & cc[1];
+            if (lab[0] == L) { m00 = e0; m01 = e1; }
+            if (lab[1] == L) { m10 = e0; m11 = e1; }
+            p0 &= ~e0;
+            p1 &= ~e1;
         }
-        const uint64_t m0 = (((uint64_t)x1 << 32) | x0) & core[2];
-        const uint64_t m1 = (((uint64_t)x3 << 32) | x2) & core[3];
-        if ((m0 | m1) == 0) continue;
-        const int32_t lr = __builtin_amdgcn_readlane(r < 64 ? lab[0] : lab[1], r & 63);
-        int32_t v0 = (((m0 >> lane) & 1ull) && lab[2] != lr) ? lab[2] : BIG;
-        int32_t v1 = (((m1 >> lane) & 1ull) && lab[3] != lr) ? lab[3] : BIG;
-        if (__ballot(v0 != BIG || v1 != BIG) == 0) continue;
-        int32_t mn = min(v0, v1);
+        const uint64_t v0 = __ballot(((b00 & ~m00) | (b01 & ~m01)) != 0);   // row 2l fails
+        const uint64_t v1 = __ballot(((b10 & ~m10) | (b11 & ~m11)) != 0);   // row 2l+1 fails
+        if ((v0 | v1) == 0) break;
+        // merge step for every failing row
+        uint64_t todo0 = v0, todo1 = v1;
+        while (todo0 | todo1) {
+            int src, half;
+            if (todo0) { src = __ffsll((long long)todo0) - 1; half = 0; todo0 &= todo0 - 1; }
+            else { src = __ffsll((long long)todo1) - 1; half = 1; todo1 &= todo1 - 1; }
+            const int r = 2 * src + half;
+            const uint64_t r0 = half ? lane_u64(b10, src) : lane_u64(b00, src);
+            const uint64_t r1 = half ? lane_u64(b11, src) : lane_u64(b01, src);
+            const int32_t lr = __builtin_amdgcn_readlane(half ? lab[1] : lab[0], src);
+            int32_t c0 = (((r0 >> lane) & 1ull) && lab[2] != lr) ? lab[2] : BIG;
+            int32_t c1 = (((r1 >> lane) & 1ull) && lab[3] != lr) ? lab[3] : BIG;
+            if (__ballot(c0 != BIG || c1 != BIG) == 0) continue;
+            int32_t mn = min(c0, c1);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, WAVE));
-        mn = min(mn, lr);
-        // every distinct label of the row's neighbourhood joins mn
-        while (true) {
-            const int32_t cand = v0 != BIG ? v0 : v1;
-            const uint64_t act = __ballot(cand != BIG);
-            if (act == 0) break;
-            const int32_t o = __builtin_amdgcn_readlane(cand, __ffsll((long long)act) - 1);
-            if (o != mn) {
-                if (lane == 0) Q[nq] = make_int2(mn, o);
+            for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, WAVE));
+            mn = min(mn, lr);
+            while (true) {
+                const int32_t cand = c0 != BIG ? c0 : c1;
+                const uint64_t act = __ballot(cand != BIG);
+                if (act == 0) break;
+                const int32_t o = __builtin_amdgcn_readlane(cand, __ffsll((long long)act) - 1);
+                if (o != mn) {
+                    if (lane == 0) Q[nq] = make_int2(mn, o);
+                    ++nq;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) lab[q] = lab[q] == o ? mn : lab[q];
+                }
+                c0 = c0 == o ? BIG : c0;
+                c1 = c1 == o ? BIG : c1;
+            }
+            if (lr != mn) {
+                if (lane == 0) Q[nq] = make_int2(mn, lr);
                 ++nq;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) lab[q] = lab[q] == o ? mn : lab[q];
+                for (int q = 0; q < 4; ++q) lab[q] = lab[q] == lr ? mn : lab[q];
             }
-            v0 = v0 == o ? BIG : v0;
-            v1 = v1 == o ? BIG : v1;
-        }
-        if (lr != mn) {
-            if (lane == 0) Q[nq] = make_int2(mn, lr);
-            ++nq;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) lab[q] = lab[q] == lr ? mn : lab[q];
-        }
-        if (nq > CC_QCAP - 130) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            cc_flush(parent, Q, nq);
+            if (nq > CC_QCAP - 130) cc_flush(parent, Q, nq);
+            (void)r;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     cc_flush(parent, Q, nq);
+    (void)rowbase;
+    (void)colbase;
 }
 
 __global__ void k_cc_init(int32_t *parent, int64_t n) {

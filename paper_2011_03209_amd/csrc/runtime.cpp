@@ -183,6 +183,7 @@ struct Request;
 
 struct mapper_context {
     int device = 0;
+    int cus = 256;
     Arena arena;
     hipStream_t stream = nullptr;
     std::vector<hipStream_t> slots;
@@ -630,6 +631,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     uint32_t *bitmask = mem.get<uint32_t>((uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS);
     st.bitmask_bytes = nblocks * TILE_WORDS * 4;
     unsigned long long *band_n = mem.get<unsigned long long>(1);
+    unsigned int *queue = mem.get<unsigned int>(8);
+    const bool persistent = (P->flags & MAPPER_FLAG_GRID_LAUNCH) == 0;
     int64_t band_cap = std::max<int64_t>(1 << 20, pairs / 256);
     band_cap = std::min<int64_t>(band_cap, 1ll << 28);
     BandPair *band = nullptr;
@@ -648,7 +651,10 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     for (int launch = 0;; ++launch) {
         HIPCHK(hipMemsetAsync(count, 0, (size_t)Sa * 4, s));
         HIPCHK(hipMemsetAsync(band_n, 0, 8, s));
+        HIPCHK(hipMemsetAsync(queue, 0, 8 * sizeof(unsigned int), s));
         TileArgs ta{};
+        ta.queue = queue;
+        ta.grid = persistent ? 2 * ctx->cus : 0;
         ta.tt = tt;
         ta.panel_hi = panel_hi;
         ta.panel_lo = panel_lo;
@@ -906,6 +912,8 @@ mapper_status mapper_context_create(int device, void *arena, uint64_t arena_byte
         return fail(MAPPER_EDEVICE, "no such HIP device");
     auto *c = new mapper_context();
     c->device = device;
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus < 1)
+        c->cus = 256;
     c->arena.init((char *)arena, arena_bytes);
     c->stream = (hipStream_t)stream;
     *out = c;

@@ -50,18 +50,36 @@ template <> struct Cfg<P_FP16X3> { static constexpr int ESZ = 2, KC = 32, PANELS
 
 template <int PREC> struct Lay {
     static constexpr int RB = Cfg<PREC>::KC * Cfg<PREC>::ESZ;   // bytes of a row per slab
-    static constexpr int RS = RB + 16;                          // padded LDS row stride
-    static constexpr int PANEL_BYTES = TILE * RS;                // one operand panel
+    static constexpr int CPR = RB / 16;                         // 16-byte chunks per row
+    static constexpr int PANEL_BYTES = TILE * RB;                // one operand panel
     static constexpr int STAGE_BYTES = 2 * Cfg<PREC>::PANELS * PANEL_BYTES;   // A and B
-    static constexpr int CHUNKS = TILE * RB / 16;                // 16-byte chunks per panel
-    static constexpr int CPT = CHUNKS / NT;                      // per thread
+    static constexpr int CPT = TILE * CPR / NT;                  // chunks per thread per panel
     static constexpr int NREG = 2 * Cfg<PREC>::PANELS * CPT;
 };
 
+// LDS rows are unpadded; the 16-byte chunks of row r are permuted by an XOR
+// with swz(r).  16-byte reads of one chunk column by 8 (32-bank) or 16
+// (64-bank) consecutive rows, and writes of consecutive chunks of consecutive
+// rows, then all fall in distinct banks.
+template <int CPR> __device__ __forceinline__ int swz(int r) {
+    if constexpr (CPR == 8) return (r + (r >> 3)) & 7;
+    else return ((r >> 1) ^ (r >> 3)) & 3;
+}
+
+template <int CPR> __device__ __forceinline__ int loff(int r, int c) {
+    return (r * CPR + (c ^ swz<CPR>(r))) * 16;
+}
+
+// Per-thread copy plan of one tile: the global address (at k = 0) and the LDS
+// offset of each 16-byte chunk this thread moves per slab.
+template <int PREC> struct Feed {
+    const char *src[Lay<PREC>::NREG];
+    int dst[Lay<PREC>::NREG];
+};
+
 template <int PREC>
-__device__ __forceinline__ void gload(const TileArgs &a, const TilePos &tl, int k0, u32x4 *reg) {
+__device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl, Feed<PREC> &f) {
     using L = Lay<PREC>;
-    constexpr int CPR = L::RB / 16;        // chunks per row
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int64_t rb = side == 0 ? (int64_t)tl.I * TILE : (int64_t)tl.J * TILE;
@@ -71,30 +89,27 @@ __device__ __forceinline__ void gload(const TileArgs &a, const TilePos &tl, int 
 #pragma unroll
             for (int q = 0; q < L::CPT; ++q) {
                 const int idx = q * NT + threadIdx.x;
-                const int r = idx / CPR, c = idx % CPR;
+                const int r = idx / L::CPR, c = idx % L::CPR;
                 int64_t row = rb + r;
                 if (row >= tl.ne) row = tl.ne - 1;                   // clamp; masked later
-                const int64_t slot = tl.slot0 + row;
-                const char *src = base + (slot * a.dp + k0) * Cfg<PREC>::ESZ + c * 16;
-                reg[(side * Cfg<PREC>::PANELS + pnl) * L::CPT + q] = *(const u32x4 *)src;
+                const int i = (side * Cfg<PREC>::PANELS + pnl) * L::CPT + q;
+                f.src[i] = base + (tl.slot0 + row) * (int64_t)a.dp * Cfg<PREC>::ESZ + c * 16;
+                f.dst[i] = (side * Cfg<PREC>::PANELS + pnl) * L::PANEL_BYTES + loff<L::CPR>(r, c);
             }
         }
     }
 }
 
 template <int PREC>
-__device__ __forceinline__ void lstore(char *stage, const u32x4 *reg) {
-    using L = Lay<PREC>;
-    constexpr int CPR = L::RB / 16;
+__device__ __forceinline__ void gload(const Feed<PREC> &f, int koff, u32x4 *reg) {
 #pragma unroll
-    for (int sp = 0; sp < 2 * Cfg<PREC>::PANELS; ++sp) {
+    for (int i = 0; i < Lay<PREC>::NREG; ++i) reg[i] = *(const u32x4 *)(f.src[i] + koff);
+}
+
+template <int PREC>
+__device__ __forceinline__ void lstore(char *stage, const Feed<PREC> &f, const u32x4 *reg) {
 #pragma unroll
-        for (int q = 0; q < L::CPT; ++q) {
-            const int idx = q * NT + threadIdx.x;
-            const int r = idx / CPR, c = idx % CPR;
-            *(u32x4 *)(stage + sp * L::PANEL_BYTES + r * L::RS + c * 16) = reg[sp * L::CPT + q];
-        }
-    }
+    for (int i = 0; i < Lay<PREC>::NREG; ++i) *(u32x4 *)(stage + f.dst[i]) = reg[i];
 }
 
 template <int PREC> struct Acc {
@@ -105,18 +120,21 @@ template <int PREC> struct Acc {
 template <int PREC>
 __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc, int wm, int wn) {
     using L = Lay<PREC>;
+    constexpr int CPR = L::CPR;
     const int lane = threadIdx.x & (WAVE - 1);
     const int li = lane & 31, lg = lane >> 5;
     const char *Ah = stage;
     const char *Bh = stage + Cfg<PREC>::PANELS * L::PANEL_BYTES;
     if constexpr (PREC == P_FP32) {
+        // 16 bytes = 4 k values per lane; MFMA t of a step takes element t, so
+        // lane group g supplies k = 8 ss + 4 g + t for both operands
 #pragma unroll
         for (int ss = 0; ss < Cfg<PREC>::KC / 8; ++ss) {
             f32x4 av[2], bv[2];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                av[b] = *(const f32x4 *)(Ah + (wm * 64 + b * 32 + li) * L::RS + (8 * ss + 4 * lg) * 4);
-                bv[b] = *(const f32x4 *)(Bh + (wn * 64 + b * 32 + li) * L::RS + (8 * ss + 4 * lg) * 4);
+                av[b] = *(const f32x4 *)(Ah + loff<CPR>(wm * 64 + b * 32 + li, 2 * ss + lg));
+                bv[b] = *(const f32x4 *)(Bh + loff<CPR>(wn * 64 + b * 32 + li, 2 * ss + lg));
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
@@ -134,14 +152,15 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
 #pragma unroll
         for (int ks = 0; ks < Cfg<PREC>::KC / 16; ++ks) {
             u32x4 ah[2], bh[2], al[2], bl[2];
-            const int koff = (16 * ks + 8 * lg) * 2;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                ah[b] = *(const u32x4 *)(Ah + (wm * 64 + b * 32 + li) * L::RS + koff);
-                bh[b] = *(const u32x4 *)(Bh + (wn * 64 + b * 32 + li) * L::RS + koff);
+                const int oa = loff<CPR>(wm * 64 + b * 32 + li, 2 * ks + lg);
+                const int ob = loff<CPR>(wn * 64 + b * 32 + li, 2 * ks + lg);
+                ah[b] = *(const u32x4 *)(Ah + oa);
+                bh[b] = *(const u32x4 *)(Bh + ob);
                 if constexpr (SPLIT) {
-                    al[b] = *(const u32x4 *)(Al + (wm * 64 + b * 32 + li) * L::RS + koff);
-                    bl[b] = *(const u32x4 *)(Bl + (wn * 64 + b * 32 + li) * L::RS + koff);
+                    al[b] = *(const u32x4 *)(Al + oa);
+                    bl[b] = *(const u32x4 *)(Bl + ob);
                 }
             }
 #pragma unroll
@@ -304,15 +323,17 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
             for (int v = 0; v < 16; ++v) { acc.c[bm][bn][v] = 0.f; acc.x[bm][bn][v] = 0.f; }
 
     const int nst = a.dp / Cfg<PREC>::KC;
+    Feed<PREC> feed;
+    feed_setup<PREC>(a, tl, feed);
     u32x4 reg[L::NREG];
-    gload<PREC>(a, tl, 0, reg);
-    lstore<PREC>(stages, reg);
+    gload<PREC>(feed, 0, reg);
+    lstore<PREC>(stages, feed, reg);
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
         char *cur = stages + (st & 1) * L::STAGE_BYTES;
-        if (st + 1 < nst) gload<PREC>(a, tl, (st + 1) * Cfg<PREC>::KC, reg);
+        if (st + 1 < nst) gload<PREC>(feed, (st + 1) * L::RB, reg);
         compute_stage<PREC>(cur, acc, wm, wn);
-        if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, reg);
+        if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, feed, reg);
         __syncthreads();
     }
 
@@ -363,6 +384,35 @@ __global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
 // tree; that value is within 2 gamma_{d+4} D of the canonical sequential
 // chain, so only pairs closer than that to eps^2 (ties, in practice) need
 // the canonical chain itself, which lane 0 then evaluates in order.
+// Persistent form: a fixed grid (a few workgroups per CU) drains the tile
+// pairs through eight atomic counters, one per XCD slice of the item order
+// (largest elements first).  A workgroup starts on the slice of the XCD it
+// was dealt to and then helps the others; it leaves when every slice is
+// exhausted, so the grid always drains.
+template <int PREC>
+__global__ void __launch_bounds__(NT, 2) k_tiles_persistent(TileArgs a) {
+    __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
+    __shared__ EpiShared es;
+    __shared__ int64_t next;
+    const int64_t n = a.tt.n_items;
+    const int64_t per = (n + 7) / 8;
+    const int x0 = blockIdx.x % 8;
+    for (int k = 0; k < 8; ++k) {
+        const int x = (x0 + k) % 8;
+        const int64_t lo = (int64_t)x * per;
+        const int64_t hi = lo + per < n ? lo + per : n;
+        while (true) {
+            if (threadIdx.x == 0) next = lo + (int64_t)atomicAdd(&a.queue[x], 1u);
+            __syncthreads();
+            const int64_t item = next;
+            __syncthreads();
+            if (item >= hi) break;
+            const TilePos tl = tile_decode(a.tt, item);
+            process_tile<PREC, false>(a, tl, stages, es);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, int64_t nband, const float *X,
                                                  int32_t d, const uint32_t *slot_point, double E,
                                                  uint32_t *bitmask, int32_t *count) {
@@ -431,6 +481,10 @@ __global__ void __launch_bounds__(256) k_row_norm2(const int32_t *rows, int64_t 
 template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
+    if (a.grid > 0 && !a.debug_g) {
+        k_tiles_persistent<PREC><<<dim3((unsigned)a.grid), dim3(NT), 0, s>>>(a);
+        return hipGetLastError();
+    }
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
     if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
     else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);

@@ -210,6 +210,22 @@ def test_tile_distances(ctx, prec, data):
         assert np.all(err <= 1e-5 * (nrm[:, None] + nrm[None, :]))
 
 
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3])
+def test_grid_launch_matches_persistent(ctx, prec):
+    """The one-workgroup-per-tile launch and the persistent launch give the
+    same graph (and the oracle's)."""
+    from paper_2011_03209_amd import binding
+    w = synth.mixture_500k_d128_2d(scale=0.01, precision=prec)
+    cloud = ctx.cloud(w.X)
+    try:
+        gp = cloud.run(w.params)
+        gg = cloud.run(w.params, flags=binding.FLAG_GRID_LAUNCH)
+    finally:
+        cloud.destroy()
+    same_graph(gp, gg)
+    same_graph(gp, oracle_graph(w.X, w.params))
+
+
 def test_determinism_and_permutation(ctx):
     w = synth.mixture_1m_d256(scale=0.008, precision=synth.PREC_BF16X3)
     cloud = ctx.cloud(w.X)
