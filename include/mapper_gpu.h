@@ -102,8 +102,8 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
-#define MAPPER_FLAG_GRID_LAUNCH 2u    /* one workgroup per tile pair instead of the
-                                         persistent launch (for comparison) */
+#define MAPPER_FLAG_PERSISTENT 2u     /* tile pairs drained by a fixed persistent grid
+                                         instead of one workgroup per tile pair */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

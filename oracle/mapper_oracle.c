@@ -360,6 +360,8 @@ int orc_mapper(const float *X, int64_t n, int32_t d, int32_t n_axes,
         lo[a] = g->lo + ioff;
         hi[a] = g->hi + ioff;
         orc_cover(m, M, nint[a], axes[a].overlap, lo[a], hi[a]);
+        for (int32_t k = 0; k < nint[a]; ++k)        /* a range too wide for FP64 endpoints */
+            if (!isfinite(lo[a][k]) || !isfinite(hi[a][k])) { orc_graph_free(g); return ORC_EINVAL; }
         ioff += nint[a];
     }
 

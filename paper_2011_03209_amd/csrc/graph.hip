@@ -67,7 +67,7 @@ __device__ int32_t uf_union(int32_t *P, int32_t a, int32_t b) {
 
 struct WaveTile {
     int64_t ne, slot0, blk;
-    int I, J;
+    int e, I, J;
     bool ok;
 };
 
@@ -79,6 +79,7 @@ __device__ __forceinline__ WaveTile wave_decode(const TileTable &t, int64_t item
     r.ne = p.ne;
     r.slot0 = p.slot0;
     r.blk = p.blk;
+    r.e = p.e;
     r.I = p.I;
     r.J = p.J;
     return r;
@@ -120,14 +121,9 @@ __device__ void cc_flush(int32_t *parent, int2 *q, int &nq) {
     nq = 0;
 }
 
-__global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *bitmask,
-                                                  const int32_t *count, int32_t min_pts,
-                                                  int32_t *parent) {
-    __shared__ int2 queue[4][CC_QCAP];
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const WaveTile tl = wave_decode(tt, wave_item(w));
-    if (!tl.ok) return;
-    int2 *Q = queue[w];
+__device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int32_t *count,
+                         int32_t min_pts, int32_t *parent, int2 *Q) {
+    const int lane = threadIdx.x & (WAVE - 1);
     int nq = 0;
     constexpr int32_t BIG = 0x7fffffff;
     const int64_t rowbase = tl.slot0 + (int64_t)tl.I * TILE;
@@ -218,6 +214,89 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
     (void)colbase;
 }
 
+__global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *bitmask,
+                                                  const int32_t *count, int32_t min_pts,
+                                                  int32_t *parent) {
+    __shared__ int2 queue[4][CC_QCAP];
+    const int w = threadIdx.x / WAVE;
+    const WaveTile tl = wave_decode(tt, wave_item(w));
+    if (!tl.ok) return;
+    cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
+}
+
+// Hooking pass before k_cc_tiles (the sampling idea of Afforest, Sutton et al.):
+// for every element, each core point of column block J is hung under its
+// first core neighbour in row block 0 (block (0, J)), and block (0, 0) is
+// merged completely.  Dense clusters then reach k_cc_tiles as single trees,
+// so nearly every block there passes its label check without merges.  One
+// wave per (element, J); `rb_off` numbers the column blocks of all elements.
+__global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb_off, int64_t n_rb,
+                                                 int32_t n_elem, const uint32_t *bitmask,
+                                                 const int32_t *count, int32_t min_pts,
+                                                 int32_t *parent) {
+    __shared__ int2 queue[4][CC_QCAP];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int64_t k = (int64_t)blockIdx.x * 4 + w;
+    if (k >= n_rb) return;
+    int lo = 0, hi = n_elem;                          // element with rb_off[e] <= k < rb_off[e+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rb_off[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int e = lo;
+    WaveTile tl;
+    tl.ok = true;
+    tl.e = e;
+    tl.I = 0;
+    tl.J = (int)(k - rb_off[e]);
+    tl.slot0 = tt.elem_off[e];
+    tl.ne = tt.elem_off[e + 1] - tl.slot0;
+    const int64_t T = (tl.ne + TILE - 1) / TILE;
+    if (tl.ne <= 0 || tl.J >= T) return;
+    tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, 0, tl.J);
+    if (tl.J == 0) {
+        cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
+        return;
+    }
+    // block (0, J): lane holds rows 2l, 2l+1 (words) and columns l, l+64
+    uint32_t wd[8];
+    {
+        const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS) + 2 * lane;
+        const uint4 u0 = src[0], u1 = src[1];
+        wd[0] = u0.x; wd[1] = u0.y; wd[2] = u0.z; wd[3] = u0.w;
+        wd[4] = u1.x; wd[5] = u1.y; wd[6] = u1.z; wd[7] = u1.w;
+    }
+    bool rc[2], ccore[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t r = 2 * lane + q;
+        rc[q] = r < tl.ne && count[tl.slot0 + r] >= min_pts;
+        const int64_t c = (int64_t)tl.J * TILE + lane + 64 * q;
+        ccore[q] = c < tl.ne && count[tl.slot0 + c] >= min_pts;
+    }
+    const uint64_t rc0 = __ballot(rc[0]), rc1 = __ballot(rc[1]);   // rows 2l and 2l+1
+    int32_t first0 = -1, first1 = -1;                             // first core row per column
+    for (int r = 0; r < TILE; ++r) {
+        const int src = r >> 1;
+        if (!((((r & 1) ? rc1 : rc0) >> src) & 1ull)) continue;
+        uint32_t x0, x1, x2, x3;
+        if (r & 1) {
+            x0 = __builtin_amdgcn_readlane(wd[4], src); x1 = __builtin_amdgcn_readlane(wd[5], src);
+            x2 = __builtin_amdgcn_readlane(wd[6], src); x3 = __builtin_amdgcn_readlane(wd[7], src);
+        } else {
+            x0 = __builtin_amdgcn_readlane(wd[0], src); x1 = __builtin_amdgcn_readlane(wd[1], src);
+            x2 = __builtin_amdgcn_readlane(wd[2], src); x3 = __builtin_amdgcn_readlane(wd[3], src);
+        }
+        const uint32_t lw = lane < 32 ? x0 : x1, hw = lane < 32 ? x2 : x3;
+        if (first0 < 0 && ((lw >> (lane & 31)) & 1u)) first0 = r;
+        if (first1 < 0 && ((hw >> (lane & 31)) & 1u)) first1 = r;
+        if (__ballot((ccore[0] && first0 < 0) || (ccore[1] && first1 < 0)) == 0) break;
+    }
+    const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
+    if (ccore[0] && first0 >= 0) uf_union(parent, (int32_t)(tl.slot0 + first0), (int32_t)(colbase + lane));
+    if (ccore[1] && first1 >= 0) uf_union(parent, (int32_t)(tl.slot0 + first1), (int32_t)(colbase + lane + 64));
+}
+
 __global__ void k_cc_init(int32_t *parent, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) parent[i] = (int32_t)i;
@@ -250,14 +329,27 @@ __global__ void k_node_ids(const int32_t *count, int32_t min_pts, const int32_t 
     }
 }
 
+// flag[rb] = 1 if the 128-slot row block rb (row blocks numbered per element,
+// rb_off[e] + local / 128) holds a non-core member
+__global__ void k_noncore_flags(const int32_t *count, int32_t min_pts, const uint64_t *slot_elem,
+                                const int64_t *elem_off, const int64_t *rb_off, uint8_t *flag,
+                                int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n || count[s] >= min_pts) return;
+    const int64_t e = (int64_t)slot_elem[s];
+    flag[rb_off[e] + (s - elem_off[e]) / TILE] = 1;
+}
+
 __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bitmask,
                                                 const int32_t *count, int32_t min_pts,
+                                                const uint8_t *ncflag, const int64_t *rb_off,
                                                 int32_t *node) {
     __shared__ uint32_t words[4][TILE_WORDS];
     __shared__ int32_t nid[4][2 * TILE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     const WaveTile tl = wave_decode(tt, wave_item(w));
     if (!tl.ok) return;
+    if (!ncflag[rb_off[tl.e] + tl.I] && !ncflag[rb_off[tl.e] + tl.J]) return;   // all core
     uint64_t coreI[2], coreJ[2], ncI[2], ncJ[2];
     int32_t *N = nid[w];
 #pragma unroll
@@ -407,6 +499,15 @@ hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const i
     return hipGetLastError();
 }
 
+hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
+                          const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
+                          int32_t *parent, hipStream_t s) {
+    if (n_rb <= 0) return hipSuccess;
+    k_cc_hook<<<dim3((unsigned)((n_rb + 3) / 4)), 256, 0, s>>>(tt, rb_off, n_rb, n_elem, bitmask, count,
+                                                               min_pts, parent);
+    return hipGetLastError();
+}
+
 hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
                              uint8_t *isroot, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -422,10 +523,19 @@ hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t 
     return hipGetLastError();
 }
 
+hipError_t launch_noncore_flags(const int32_t *count, int32_t min_pts, const uint64_t *slot_elem,
+                                const int64_t *elem_off, const int64_t *rb_off, uint8_t *flag,
+                                int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_noncore_flags<<<nblk(n), 256, 0, s>>>(count, min_pts, slot_elem, elem_off, rb_off, flag, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_border(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
-                         int32_t min_pts, int32_t *node, hipStream_t s) {
+                         int32_t min_pts, const uint8_t *ncflag, const int64_t *rb_off,
+                         int32_t *node, hipStream_t s) {
     if (tt.n_items <= 0) return hipSuccess;
-    k_border<<<wave_blocks(tt.n_items), 256, 0, s>>>(tt, bitmask, count, min_pts, node);
+    k_border<<<wave_blocks(tt.n_items), 256, 0, s>>>(tt, bitmask, count, min_pts, ncflag, rb_off, node);
     return hipGetLastError();
 }
 

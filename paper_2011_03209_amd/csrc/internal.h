@@ -85,6 +85,17 @@ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item)
     return r;
 }
 
+// Inverse of tile_decode inside one element: the position p of tile pair
+// (I, J), I <= J < T, in the element's supertile order (cp = its colpre).
+__device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T, int64_t I, int64_t J) {
+    const int64_t SI = I / SUPER, SJ = J / SUPER;
+    const int64_t cols = (T - SJ * SUPER) < SUPER ? (T - SJ * SUPER) : SUPER;
+    const int64_t per = SUPER * cols;
+    if (SI < SJ) return cp[SJ] + SI * per + (I % SUPER) + SUPER * (J % SUPER);
+    const int64_t i = I % SUPER, j = J % SUPER;
+    return cp[SJ] + SJ * per + j * (j + 1) / 2 + i;
+}
+
 // One pair whose tile distance fell inside the certified band of eps^2.
 struct BandPair {
     int32_t si, sj;            // slots (global member positions)
@@ -163,13 +174,20 @@ hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, con
 hipError_t launch_cc_init(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
                            int32_t min_pts, int32_t *parent, hipStream_t s);
+hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
+                          const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
+                          int32_t *parent, hipStream_t s);
 hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
                              uint8_t *isroot, int64_t n_slots, hipStream_t s);
 hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent,
                            const int64_t *root_rank, const uint64_t *slot_elem,
                            int32_t *node, int32_t *node_elem, int64_t n_slots, hipStream_t s);
+hipError_t launch_noncore_flags(const int32_t *count, int32_t min_pts, const uint64_t *slot_elem,
+                                const int64_t *elem_off, const int64_t *rb_off, uint8_t *flag,
+                                int64_t n, hipStream_t s);
 hipError_t launch_border(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
-                         int32_t min_pts, int32_t *node, hipStream_t s);
+                         int32_t min_pts, const uint8_t *ncflag, const int64_t *rb_off,
+                         int32_t *node, hipStream_t s);
 hipError_t launch_member_pairs(const int32_t *node, const uint32_t *slot_point,
                                const int64_t *pos, int64_t n_slots, uint64_t *keys,
                                uint32_t *vals, hipStream_t s);

@@ -45,14 +45,29 @@ __global__ void __launch_bounds__(LB) k_lens_rows(const float *__restrict__ X, i
     double acc = 0.0;
     for (int32_t c0 = 0; c0 < d; c0 += LC) {
         const int cw = (d - c0) < LC ? (d - c0) : LC;
-        // coalesced load: 32 consecutive floats of a row per 32 threads
-        for (int q = 0; q < LB * LC / 256; ++q) {
-            const int idx = q * 256 + threadIdx.x;
-            const int r = idx / LC, j = idx % LC;
-            const int64_t gr = row0 + r;
-            float v = 0.f;
-            if (gr < n && j < cw) v = X[gr * d + c0 + j];
-            tile[r][j] = v;
+        if ((d & 3) == 0 && cw == LC) {
+            // 16-byte loads: 8 threads cover the slab's 128 bytes of a row
+            for (int q = 0; q < LB * LC / 4 / 256; ++q) {
+                const int idx = q * 256 + threadIdx.x;
+                const int r = idx / (LC / 4), j = 4 * (idx % (LC / 4));
+                const int64_t gr = row0 + r;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gr < n) v = *(const float4 *)(X + gr * d + c0 + j);
+                tile[r][j] = v.x;
+                tile[r][j + 1] = v.y;
+                tile[r][j + 2] = v.z;
+                tile[r][j + 3] = v.w;
+            }
+        } else {
+            // coalesced load: 32 consecutive floats of a row per 32 threads
+            for (int q = 0; q < LB * LC / 256; ++q) {
+                const int idx = q * 256 + threadIdx.x;
+                const int r = idx / LC, j = idx % LC;
+                const int64_t gr = row0 + r;
+                float v = 0.f;
+                if (gr < n && j < cw) v = X[gr * d + c0 + j];
+                tile[r][j] = v;
+            }
         }
         if (kind == 3 && threadIdx.x < LC) vdir[threadIdx.x] = threadIdx.x < cw ? (double)dir[c0 + threadIdx.x] : 0.0;
         __syncthreads();

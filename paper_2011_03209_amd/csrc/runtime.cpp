@@ -632,7 +632,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     st.bitmask_bytes = nblocks * TILE_WORDS * 4;
     unsigned long long *band_n = mem.get<unsigned long long>(1);
     unsigned int *queue = mem.get<unsigned int>(8);
-    const bool persistent = (P->flags & MAPPER_FLAG_GRID_LAUNCH) == 0;
+    const bool persistent = (P->flags & MAPPER_FLAG_PERSISTENT) != 0;
     int64_t band_cap = std::max<int64_t>(1 << 20, pairs / 256);
     band_cap = std::min<int64_t>(band_cap, 1ll << 28);
     BandPair *band = nullptr;
@@ -693,13 +693,25 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int64_t *rank = mem.get<int64_t>(Sa + 1);
     int32_t *node = mem.get<int32_t>(Sa);
     int32_t *node_elem = mem.get<int32_t>(Sa);
+    // row blocks of all elements, numbered element by element
+    std::vector<int64_t> rb_off(std::max<int64_t>(E_count, 1), 0);
+    int64_t nrb = 0;
+    for (int64_t e = 0; e < E_count; ++e) { rb_off[e] = nrb; nrb += T[e]; }
+    int64_t *d_rb_off = mem.get<int64_t>(rb_off.size());
+    h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
     HIPCHK(launch_cc_init(parent, S, s));
+    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
     void *stmp2 = mem.get<char>(scan_temp_bytes(Sa + 1));
     HIPCHK(launch_scan_u8(isroot, rank, S, stmp2, s));
     HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, slot_elem, node, node_elem, S, s));
-    HIPCHK(launch_border(tt, bitmask, count, P->min_pts, node, s));
+    {
+        uint8_t *ncflag = mem.get<uint8_t>(std::max<int64_t>(nrb, 1));
+        HIPCHK(hipMemsetAsync(ncflag, 0, (size_t)std::max<int64_t>(nrb, 1), s));
+        HIPCHK(launch_noncore_flags(count, P->min_pts, slot_elem, elem_off, d_rb_off, ncflag, S, s));
+        HIPCHK(launch_border(tt, bitmask, count, P->min_pts, ncflag, d_rb_off, node, s));
+    }
     int64_t N = 0;
     HIPCHK(hipMemcpyAsync(&N, rank + S, 8, hipMemcpyDeviceToHost, s));
     ev.mark();                                                      // 6

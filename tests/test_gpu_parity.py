@@ -211,7 +211,7 @@ def test_tile_distances(ctx, prec, data):
 
 
 @pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3])
-def test_grid_launch_matches_persistent(ctx, prec):
+def test_persistent_matches_grid_launch(ctx, prec):
     """The one-workgroup-per-tile launch and the persistent launch give the
     same graph (and the oracle's)."""
     from paper_2011_03209_amd import binding
@@ -219,7 +219,7 @@ def test_grid_launch_matches_persistent(ctx, prec):
     cloud = ctx.cloud(w.X)
     try:
         gp = cloud.run(w.params)
-        gg = cloud.run(w.params, flags=binding.FLAG_GRID_LAUNCH)
+        gg = cloud.run(w.params, flags=binding.FLAG_PERSISTENT)
     finally:
         cloud.destroy()
     same_graph(gp, gg)
@@ -278,7 +278,9 @@ def test_errors(ctx):
            synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2, column=4)], 1.0, 2),
            synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], -1.0, 2),
            synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], float("nan"), 2),
-           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], 1.0, 0)]
+           synth.Params([synth.Axis(synth.LENS_COLUMN, 3, 0.2)], 1.0, 0),
+           synth.Params([synth.Axis(synth.LENS_VALUES, 3, 0.2,
+                                    values=np.r_[-1.5e308, 1.5e308, np.zeros(98)])], 1.0, 2)]
     for p in bad:
         with pytest.raises(binding.MapperError) as ei:
             cloud.run(p)

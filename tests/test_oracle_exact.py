@@ -169,7 +169,8 @@ def test_cover_closed_forms():
         assert np.all(np.diff(lo) >= 0)
 
 
-@pytest.mark.parametrize("bad", ["nint0", "ov1", "ovneg", "epsneg", "epsnan", "minpts0", "nan", "inf", "col"])
+@pytest.mark.parametrize("bad", ["nint0", "ov1", "ovneg", "epsneg", "epsnan", "minpts0", "nan", "inf", "col",
+                                 "range_overflow"])
 def test_invalid_params(bad):
     X = np.zeros((10, 3), np.float32)
     X[:, 0] = np.arange(10)
@@ -193,6 +194,10 @@ def test_invalid_params(bad):
         X[4, 2] = np.inf
     elif bad == "col":
         ax.column = 3
+    elif bad == "range_overflow":           # M - m overflows FP64: no finite endpoints
+        vals = np.zeros(10)
+        vals[0], vals[1] = -1.5e308, 1.5e308
+        ax = synth.Axis(synth.LENS_VALUES, 3, 0.2, values=vals)
     with pytest.raises(O.OracleError):
         O.mapper(X, synth.Params([ax], eps=eps, min_pts=mp))
 
