@@ -75,7 +75,7 @@ __device__ __forceinline__ WaveTile wave_decode(const TileTable &t, int64_t item
     WaveTile r;
     r.ok = item < t.n_items;
     if (!r.ok) return r;
-    const TilePos p = tile_decode(t, item);
+    const TilePos p = tile_lookup(t, item);
     r.ne = p.ne;
     r.slot0 = p.slot0;
     r.blk = p.blk;
@@ -152,7 +152,7 @@ __device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int3
     const uint64_t b01 = cr[0] ? ((((uint64_t)wd[3] << 32) | wd[2]) & cc[1]) : 0;
     const uint64_t b10 = cr[1] ? ((((uint64_t)wd[5] << 32) | wd[4]) & cc[0]) : 0;
     const uint64_t b11 = cr[1] ? ((((uint64_t)wd[7] << 32) | wd[6]) & cc[1]) : 0;
-    for (int round = 0;; ++round) {
+    for (;;) {
         // masks of the columns that carry each of my row labels
         uint64_t m00 = 0, m01 = 0, m10 = 0, m11 = 0;
         uint64_t p0 = cc[0], p1 = cc[1];

@@ -28,6 +28,12 @@ inline bool prec_is_bf16(int p) { return p == P_BF16 || p == P_BF16X3; }
 // that run together on one XCD thus share a few row panels in its L2.
 constexpr int SUPER = 8;
 
+// One tile pair, decoded (32 bytes: one scalar load per workgroup or wave).
+struct __attribute__((aligned(32))) TileItem {
+    int32_t e, I, J, ne;       // element, row block, column block, element size
+    int64_t slot0, blk;        // first slot of the element, bitmask block
+};
+
 struct TileTable {
     const int64_t *item_off;   // [nord+1] first item of each ordered element
     const int32_t *order;      // [nord] element id of each ordered entry
@@ -35,6 +41,7 @@ struct TileTable {
     const int64_t *blk_off;    // [E] first bitmask block of each element
     const int64_t *colpre;     // per element: items before each supertile column (Ts+1)
     const int64_t *cp_off;     // [E] start of the element's colpre entries
+    const struct TileItem *items;   // decoded items, built by launch_build_items
     int32_t nord;
     int64_t n_items;
 };
@@ -82,6 +89,19 @@ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item)
         r.I = (int)(SJ * SUPER + (loc - j * (j + 1) / 2));
         r.J = (int)(SJ * SUPER + j);
     }
+    return r;
+}
+
+// The decoded item from the table (one scalar load instead of the searches).
+__device__ __forceinline__ TilePos tile_lookup(const TileTable &t, int64_t item) {
+    const TileItem q = t.items[item];
+    TilePos r;
+    r.e = q.e;
+    r.I = q.I;
+    r.J = q.J;
+    r.ne = q.ne;
+    r.slot0 = q.slot0;
+    r.blk = q.blk;
     return r;
 }
 
@@ -161,6 +181,8 @@ struct TileArgs {
     int grid;                  // number of workgroups launched
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
+// items[i] = decoded tile pair i of the table (one thread per item).
+hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
 int tile_grid_size(int prec, int64_t n_items);
 hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
                           const uint32_t *slot_point, double E, uint32_t *bitmask,

@@ -604,6 +604,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     tt.cp_off = d_cp_off;
     tt.nord = (int32_t)order.size();
     tt.n_items = nblocks;
+    TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));
+    HIPCHK(launch_build_items(tt, d_items, s));
+    tt.items = d_items;
 
     const int dp = prec == P_FP32 ? 32 * ((d + 31) / 32) : dp16;
     const int esz = prec == P_FP32 ? 4 : 2;
@@ -1155,6 +1158,9 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.tt.cp_off = d_cpo;
         ta.tt.nord = 1;
         ta.tt.n_items = P;
+        TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(P, 1));
+        HIPCHK(launch_build_items(ta.tt, d_items, s));
+        ta.tt.items = d_items;
         ta.panel_hi = pk.panel_hi;
         ta.panel_lo = pk.panel_lo;
         ta.dp = dp;

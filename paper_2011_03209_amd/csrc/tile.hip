@@ -29,6 +29,9 @@
 // so every unordered pair is stored once.
 #include "internal.h"
 
+// v_writelane_b32: set lane `lane` of `old` to the wave-uniform `val`.
+extern "C" __device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace mgpu {
 
 namespace {
@@ -70,46 +73,66 @@ template <int CPR> __device__ __forceinline__ int loff(int r, int c) {
     return (r * CPR + (c ^ swz<CPR>(r))) * 16;
 }
 
-// Per-thread copy plan of one tile: the global address (at k = 0) and the LDS
-// offset of each 16-byte chunk this thread moves per slab.
+// Per-thread copy plan of one tile.  The row panels of the two sides (and of
+// the hi/lo halves of a split) start at wave-uniform addresses; a thread
+// moves chunk c of rows r_q (q < CPT) of each, found at a 32-bit offset from
+// that start.  Rows past the element are clamped to its last row (masked in
+// the epilogue).
 template <int PREC> struct Feed {
-    const char *src[Lay<PREC>::NREG];
-    int dst[Lay<PREC>::NREG];
+    const char *base[2 * Cfg<PREC>::PANELS];
+    uint32_t voff[2][Lay<PREC>::CPT];
+    int dst[Lay<PREC>::CPT];
 };
 
 template <int PREC>
 __device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl, Feed<PREC> &f) {
     using L = Lay<PREC>;
+    const uint32_t rowb = (uint32_t)a.dp * Cfg<PREC>::ESZ;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const int64_t rb = side == 0 ? (int64_t)tl.I * TILE : (int64_t)tl.J * TILE;
+        const int64_t r0 = (int64_t)(side == 0 ? tl.I : tl.J) * TILE;
+        const int64_t nrow = tl.ne - r0;
 #pragma unroll
-        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl) {
-            const char *base = (const char *)(pnl == 0 ? a.panel_hi : a.panel_lo);
+        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl)
+            f.base[side * Cfg<PREC>::PANELS + pnl] =
+                (const char *)(pnl == 0 ? a.panel_hi : a.panel_lo) + (tl.slot0 + r0) * (int64_t)rowb;
 #pragma unroll
-            for (int q = 0; q < L::CPT; ++q) {
-                const int idx = q * NT + threadIdx.x;
-                const int r = idx / L::CPR, c = idx % L::CPR;
-                int64_t row = rb + r;
-                if (row >= tl.ne) row = tl.ne - 1;                   // clamp; masked later
-                const int i = (side * Cfg<PREC>::PANELS + pnl) * L::CPT + q;
-                f.src[i] = base + (tl.slot0 + row) * (int64_t)a.dp * Cfg<PREC>::ESZ + c * 16;
-                f.dst[i] = (side * Cfg<PREC>::PANELS + pnl) * L::PANEL_BYTES + loff<L::CPR>(r, c);
-            }
+        for (int q = 0; q < L::CPT; ++q) {
+            const int idx = q * NT + threadIdx.x;
+            const int r = idx / L::CPR, c = idx % L::CPR;
+            const int rr = r < nrow ? r : (int)(nrow - 1);
+            f.voff[side][q] = (uint32_t)rr * rowb + (uint32_t)(c * 16);
         }
+    }
+#pragma unroll
+    for (int q = 0; q < L::CPT; ++q) {
+        const int idx = q * NT + threadIdx.x;
+        f.dst[q] = loff<L::CPR>(idx / L::CPR, idx % L::CPR);
     }
 }
 
 template <int PREC>
-__device__ __forceinline__ void gload(const Feed<PREC> &f, int koff, u32x4 *reg) {
+__device__ __forceinline__ void gload(const Feed<PREC> &f, uint32_t koff, u32x4 *reg) {
+    using L = Lay<PREC>;
 #pragma unroll
-    for (int i = 0; i < Lay<PREC>::NREG; ++i) reg[i] = *(const u32x4 *)(f.src[i] + koff);
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl) {
+            const char *bk = f.base[side * Cfg<PREC>::PANELS + pnl] + koff;
+#pragma unroll
+            for (int q = 0; q < L::CPT; ++q)
+                reg[(side * Cfg<PREC>::PANELS + pnl) * L::CPT + q] = *(const u32x4 *)(bk + f.voff[side][q]);
+        }
 }
 
 template <int PREC>
 __device__ __forceinline__ void lstore(char *stage, const Feed<PREC> &f, const u32x4 *reg) {
+    using L = Lay<PREC>;
 #pragma unroll
-    for (int i = 0; i < Lay<PREC>::NREG; ++i) *(u32x4 *)(stage + f.dst[i]) = reg[i];
+    for (int sp = 0; sp < 2 * Cfg<PREC>::PANELS; ++sp)
+#pragma unroll
+        for (int q = 0; q < L::CPT; ++q)
+            *(u32x4 *)(stage + sp * L::PANEL_BYTES + f.dst[q]) = reg[sp * L::CPT + q];
 }
 
 template <int PREC> struct Acc {
@@ -117,9 +140,12 @@ template <int PREC> struct Acc {
     f32x16 x[2][2];   // cross-term accumulator of hi/lo splits
 };
 
-template <int PREC>
+// FIRST: the first slab, whose products start the accumulators (MFMA with a
+// zero addend, so the accumulators need no clearing).
+template <int PREC, bool FIRST>
 __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc, int wm, int wn) {
     using L = Lay<PREC>;
+    const f32x16 zero = {};
     constexpr int CPR = L::CPR;
     const int lane = threadIdx.x & (WAVE - 1);
     const int li = lane & 31, lg = lane >> 5;
@@ -142,8 +168,8 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
                 for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
                     for (int bn = 0; bn < 2; ++bn)
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[bm][t], bv[bn][t],
-                                                                            acc.c[bm][bn], 0, 0, 0);
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            av[bm][t], bv[bn][t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][bn], 0, 0, 0);
         }
     } else {
         constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
@@ -163,6 +189,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
                     bl[b] = *(const u32x4 *)(Bl + ob);
                 }
             }
+            const bool z0 = FIRST && ks == 0;
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -170,11 +197,11 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
                     if constexpr (PREC == P_BF16 || PREC == P_BF16X3) {
                         acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                            acc.c[bm][bn], 0, 0, 0);
+                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
                         if constexpr (SPLIT) {
                             acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                                 __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bl[bn]),
-                                acc.x[bm][bn], 0, 0, 0);
+                                z0 ? zero : acc.x[bm][bn], 0, 0, 0);
                             acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                                 __builtin_bit_cast(bf16x8, al[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
                                 acc.x[bm][bn], 0, 0, 0);
@@ -182,11 +209,11 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
                     } else {
                         acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                             __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                            acc.c[bm][bn], 0, 0, 0);
+                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
                         if constexpr (SPLIT) {
                             acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                                 __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bl[bn]),
-                                acc.x[bm][bn], 0, 0, 0);
+                                z0 ? zero : acc.x[bm][bn], 0, 0, 0);
                             acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                                 __builtin_bit_cast(f16x8, al[bm]), __builtin_bit_cast(f16x8, bh[bn]),
                                 acc.x[bm][bn], 0, 0, 0);
@@ -200,16 +227,17 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
 struct EpiShared {
     __attribute__((aligned(16))) float thrA[2 * TILE];
     __attribute__((aligned(16))) float thrB[2 * TILE];
-    uint32_t words[TILE * 4];
-    int32_t rowcnt[TILE];
-    int32_t colcnt[TILE];
+    __attribute__((aligned(16))) uint32_t words[TILE * 4];
+    int32_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes
 };
 
-// Decisions of one 32 x 32 accumulator block.  FULL: the block lies inside the
-// element and off the diagonal, so no bounds or triangle masks are needed.
+// Decisions of one 32 x 32 accumulator block: the row words of its bitmask
+// go to LDS, the lane's column count is added to colc, and the result says
+// whether the block has band pairs.  FULL: the block lies inside the element
+// and off the diagonal, so no bounds or triangle masks are needed.
 template <int PREC, bool FULL, bool DEBUG>
-__device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
-                                          const Acc<PREC> &acc, int bm, int bn, int wm, int wn) {
+__device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
+                                          const Acc<PREC> &acc, int bm, int bn, int wm, int wn, int &colc) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
@@ -223,9 +251,8 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         TA[q] = *(const f32x4 *)&es.thrA[r0 + 8 * q];
         TB[q] = *(const f32x4 *)&es.thrB[r0 + 8 * q];
     }
-    const int myv = 4 * (li >> 3) + (li & 3);              // lane li (< 32) collects row li
-    uint64_t sel = 0;
-    int colc = 0, nb = 0;
+    int word = 0;                                          // lane li (< 32): row li of the block
+    uint64_t anyband = 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         float g = acc.c[bm][bn][v];
@@ -233,7 +260,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         bool in, band;
         if constexpr (FULL) {
             in = g >= TA[v >> 2][v & 3] + Aj;
-            band = !in && !(g < TB[v >> 2][v & 3] + Bj);
+            band = !(g < TB[v >> 2][v & 3] + Bj);           // band once the "in" pairs are removed
             colc += in ? 1 : 0;
         } else {
             const int rl = r0 + 8 * (v >> 2) + (v & 3);
@@ -251,19 +278,43 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
             }
         }
         const uint64_t ib = __ballot(in);
-        if (v == myv) sel = ib;
-        nb += __popcll(__ballot(band));
+        // the low half of the ballot is row 8(v/4) + v%4, the high half the row 4 below
+        word = lane_write((int)(uint32_t)ib, 8 * (v >> 2) + (v & 3), word);
+        word = lane_write((int)(uint32_t)(ib >> 32), 8 * (v >> 2) + 4 + (v & 3), word);
+        anyband |= __ballot(band) & ~ib;
+        asm volatile("" : "+s"(anyband));                 // fold now: keeps no masks live
     }
-    const uint32_t word = ((li >> 2) & 1) ? (uint32_t)(sel >> 32) : (uint32_t)sel;
-    colc += __shfl_xor(colc, 32, WAVE);
-    if (lane < 32) {
-        const int rl = wm * 64 + bm * 32 + li;
-        es.words[rl * 4 + wn * 2 + bn] = word;
-        atomicAdd(&es.rowcnt[rl], (int32_t)__popc(word));
-        atomicAdd(&es.colcnt[cl], colc);
-    }
-    if (nb == 0) return;
-    // band pairs -> FP64 recheck list (rare: second pass, wave-aggregated append)
+    if (lane < 32) es.words[(wm * 64 + bm * 32 + li) * 4 + wn * 2 + bn] = (uint32_t)word;
+    return anyband != 0;
+}
+
+// Band pairs of one block -> FP64 recheck list (rare; wave-aggregated append).
+template <int PREC>
+__device__ __forceinline__ void epi_band(const TileArgs &a, const TilePos &tl, const EpiShared &es,
+                                      const Acc<PREC> &acc, int bm, int bn, int wm, int wn) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int li = lane & 31, lg = lane >> 5;
+    const bool diag = tl.I == tl.J;
+    const int cl = wn * 64 + bn * 32 + li;
+    const int64_t gc = (int64_t)tl.J * TILE + cl;
+    const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
+    const int r0 = wm * 64 + bm * 32 + 4 * lg;
+    // the decisions are recomputed in each pass rather than kept (keeps the
+    // common path free of their registers)
+    auto band_at = [&](int v) -> bool {
+        const int rl = r0 + 8 * (v >> 2) + (v & 3);
+        const int64_t gr = (int64_t)tl.I * TILE + rl;
+        float g = acc.c[bm][bn][v];
+        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+        asm volatile("" : "+v"(g));
+        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+        const bool self = diag && rl == cl;
+        const bool in = valid && (self || g >= es.thrA[rl] + Aj);
+        return valid && !in && !(g < es.thrB[rl] + Bj);
+    };
+    int nb = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) nb += __popcll(__ballot(band_at(v)));
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(a.band_n, (unsigned long long)nb);
     base = __shfl(base, 0, WAVE);
@@ -273,14 +324,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
     for (int v = 0; v < 16; ++v) {
         const int rl = r0 + 8 * (v >> 2) + (v & 3);
         const int64_t gr = (int64_t)tl.I * TILE + rl;
-        float g = acc.c[bm][bn][v];
-        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
-        // opaque copy: keeps the first pass's compare masks from living until here
-        asm volatile("" : "+v"(g));
-        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
-        const bool self = diag && rl == cl;
-        const bool in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
-        const bool band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
+        const bool band = band_at(v);
         const uint64_t bb = __ballot(band);
         if (band) {
             const int64_t idx = (int64_t)base + before + __popcll(bb & lt);
@@ -300,65 +344,79 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
 template <int PREC, bool DEBUG>
 __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared &es) {
     using L = Lay<PREC>;
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
     const int wm = w >> 1, wn = w & 1;
     const bool diag = tl.I == tl.J;
 
-    // thresholds of the tile's rows and columns; zero the count scratch
-    {
-        const int t = threadIdx.x;
-        const int64_t rb = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
-        const int64_t slot = tl.slot0 + (rb < tl.ne ? rb : tl.ne - 1);
-        es.thrA[t] = a.thrA[slot];
-        es.thrB[t] = a.thrB[slot];
-        if (t < TILE) { es.rowcnt[t] = 0; es.colcnt[t] = 0; }
-    }
-
-    Acc<PREC> acc;
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) { acc.c[bm][bn][v] = 0.f; acc.x[bm][bn][v] = 0.f; }
-
+    // K loop: double-buffered LDS slabs, the next slab's global loads in
+    // flight while the current one feeds the matrix cores
     const int nst = a.dp / Cfg<PREC>::KC;
     Feed<PREC> feed;
     feed_setup<PREC>(a, tl, feed);
     u32x4 reg[L::NREG];
     gload<PREC>(feed, 0, reg);
+    // thresholds of the tile's rows and columns (read in the epilogue)
+    {
+        const int t = threadIdx.x;
+        const int64_t rb = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
+        const int64_t slot = tl.slot0 + (rb < tl.ne ? rb : tl.ne - 1);
+        const float ta = a.thrA[slot], tb = a.thrB[slot];
+        es.thrA[t] = ta;
+        es.thrB[t] = tb;
+    }
     lstore<PREC>(stages, feed, reg);
     __syncthreads();
-    for (int st = 0; st < nst; ++st) {
+    Acc<PREC> acc;
+    if (nst > 1) gload<PREC>(feed, L::RB, reg);
+    compute_stage<PREC, true>(stages, acc, wm, wn);
+    if (nst > 1) lstore<PREC>(stages + L::STAGE_BYTES, feed, reg);
+    __syncthreads();
+    for (int st = 1; st < nst; ++st) {
         char *cur = stages + (st & 1) * L::STAGE_BYTES;
-        if (st + 1 < nst) gload<PREC>(feed, (st + 1) * L::RB, reg);
-        compute_stage<PREC>(cur, acc, wm, wn);
+        if (st + 1 < nst) gload<PREC>(feed, (uint32_t)(st + 1) * L::RB, reg);
+        compute_stage<PREC, false>(cur, acc, wm, wn);
         if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, feed, reg);
         __syncthreads();
     }
 
     // ---------------------------------------------------------------- epilogue
     const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
+    bool hb[2][2];
+    int colc[2] = {0, 0};
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) {
-            if (!DEBUG && full) epi_block<PREC, true, false>(a, tl, es, acc, bm, bn, wm, wn);
-            else epi_block<PREC, false, DEBUG>(a, tl, es, acc, bm, bn, wm, wn);
+            if (!DEBUG && full) hb[bm][bn] = epi_block<PREC, true, false>(a, tl, es, acc, bm, bn, wm, wn, colc[bn]);
+            else hb[bm][bn] = epi_block<PREC, false, DEBUG>(a, tl, es, acc, bm, bn, wm, wn, colc[bn]);
         }
+    {
+        const int lane = threadIdx.x & (WAVE - 1);
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = colc[0];
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = colc[1];
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+            if (hb[bm][bn]) epi_band<PREC>(a, tl, es, acc, bm, bn, wm, wn);
     __syncthreads();
-    // bitmask block (2 KB, coalesced) and neighbour counts
+    // bitmask block (2 KB, coalesced) and neighbour counts: a row's count is
+    // the popcount of its four words, a column's the sum of its partials
     {
         uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
         const int t = threadIdx.x;
         *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
         if (t < TILE) {
             const int64_t r = (int64_t)tl.I * TILE + t;
-            if (r < tl.ne && es.rowcnt[t]) atomicAdd(&a.count[tl.slot0 + r], es.rowcnt[t]);
+            const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
+            const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
+            if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
         } else {
-            const int c = t - TILE;
-            const int64_t gc = (int64_t)tl.J * TILE + c;
-            if (gc < tl.ne && es.colcnt[c]) atomicAdd(&a.count[tl.slot0 + gc], es.colcnt[c]);
+            const int cc = t - TILE;
+            const int64_t gc = (int64_t)tl.J * TILE + cc;
+            const int c = es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
+            if (gc < tl.ne && c) atomicAdd(&a.count[tl.slot0 + gc], c);
         }
     }
     __syncthreads();
@@ -375,7 +433,7 @@ __global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
     const int64_t per = (G + 7) / 8;
     const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (item >= a.tt.n_items) return;
-    const TilePos tl = tile_decode(a.tt, item);
+    const TilePos tl = tile_lookup(a.tt, item);
     process_tile<PREC, DEBUG>(a, tl, stages, es);
 }
 
@@ -407,7 +465,7 @@ __global__ void __launch_bounds__(NT, 2) k_tiles_persistent(TileArgs a) {
             const int64_t item = next;
             __syncthreads();
             if (item >= hi) break;
-            const TilePos tl = tile_decode(a.tt, item);
+            const TilePos tl = tile_lookup(a.tt, item);
             process_tile<PREC, false>(a, tl, stages, es);
         }
     }
@@ -478,6 +536,20 @@ __global__ void __launch_bounds__(256) k_row_norm2(const int32_t *rows, int64_t 
     out[t] = s;
 }
 
+__global__ void k_build_items(TileTable tt, TileItem *items) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tt.n_items) return;
+    const TilePos p = tile_decode(tt, i);
+    TileItem q;
+    q.e = p.e;
+    q.I = p.I;
+    q.J = p.J;
+    q.ne = (int32_t)p.ne;
+    q.slot0 = p.slot0;
+    q.blk = p.blk;
+    items[i] = q;
+}
+
 template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
@@ -507,6 +579,12 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
     case P_FP16X3: return launch_t<P_FP16X3>(a, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s) {
+    if (tt.n_items <= 0) return hipSuccess;
+    k_build_items<<<dim3((unsigned)((tt.n_items + 255) / 256)), dim3(256), 0, s>>>(tt, items);
+    return hipGetLastError();
 }
 
 hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
