@@ -59,6 +59,30 @@ def time_path(cloud, params, steps: int, warmup: int, flags: int = 0):
     return g, times, stats
 
 
+def recorded_traffic(precision: str):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3
+    counter record (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the record is missing or was taken from
+    another version of the kernel source."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", f"mapper_mix1m_d256_{precision}.txt")
+    src = os.path.join(ROOT, "paper_2011_03209_amd", "csrc", "tile.hip")
+    if not (os.path.exists(rec) and os.path.exists(src)):
+        return None
+    kv = {}
+    for line in open(rec):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("tile_source_sha256_16") != sha:
+        return None
+    try:
+        return float(kv["traffic_fetch_bytes"]) + float(kv["traffic_write_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, target_s: float = 15.0):
     """The FP64 oracle on a bounded sample: whole cover elements drawn at
     random until about target_s of oracle work, scaled to the full graph by
@@ -156,8 +180,8 @@ def main():
                               **{k: ss[-1][k] for k in ("ms_tiles", "ms_recheck", "ms_cc", "ms_edges",
                                                         "ms_lens", "ms_bin", "band_pairs")}}),
                   file=sys.stderr, flush=True)
-        _, ts, ss = time_path(cloud, w.params, 2, 1, flags=binding.FLAG_PERSISTENT)
-        print(json.dumps({"sweep": "persistent " + args.precision, "s_per_graph": float(np.median(ts)),
+        _, ts, ss = time_path(cloud, w.params, 2, 1, flags=binding.FLAG_TILE_PER_WORKGROUP)
+        print(json.dumps({"sweep": "tile-per-workgroup " + args.precision, "s_per_graph": float(np.median(ts)),
                           "ms_tiles": ss[-1]["ms_tiles"]}), file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
@@ -200,7 +224,7 @@ def main():
                    "overlap": [a.overlap for a in w.params.axes], "eps": w.params.eps,
                    "min_pts": w.params.min_pts, "precision": used},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[used] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[used], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[used], "traffic": recorded_traffic(used),
                      "kernel": f"k_tiles<{used}>", "ms_per_launch": ms_tiles,
                      "algorithmic_flop": flops,
                      "issued_flop": flops * (3 if used.endswith("x3") else 1)},

@@ -102,8 +102,9 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
-#define MAPPER_FLAG_PERSISTENT 2u     /* tile pairs drained by a fixed persistent grid
-                                         instead of one workgroup per tile pair */
+#define MAPPER_FLAG_TILE_PER_WORKGROUP 2u  /* distance tiles launched one workgroup per tile
+                                             pair instead of the default persistent grid
+                                             (same graph; for comparison and debugging) */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

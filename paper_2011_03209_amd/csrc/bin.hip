@@ -137,17 +137,20 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
         const double xd = (double)xs;
         nx += xd * xd;
         if (a.prec == P_FP32) {
-            ((float *)a.panel_hi)[s * a.dp + j] = xs;
+            ((float *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp)))[j] = xs;
             continue;
         }
         uint16_t hb, lb = 0;
         const float h = bf ? bf16_round(xs, &hb) : fp16_round(xs, &hb);
-        ((uint16_t *)a.panel_hi)[s * a.dp + j] = hb;
+        // split rows interleave 16 hi and 16 lo values per group of 16 coordinates
+        uint16_t *row16 = (uint16_t *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp));
+        const int64_t at = split ? (int64_t)(j >> 4) * 32 + (j & 15) : j;
+        row16[at] = hb;
         double lo = 0.0;
         if (split) {
             const float rem = xs - h;            // exact in FP32
             lo = (double)(bf ? bf16_round(rem, &lb) : fp16_round(rem, &lb));
-            ((uint16_t *)a.panel_lo)[s * a.dp + j] = lb;
+            row16[at + 16] = lb;
         }
         const double hd = (double)h, r = xd - hd - lo;   // exact in FP64
         hh += hd * hd;

@@ -155,13 +155,33 @@ hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
                                int32_t *range4, int32_t *count, hipStream_t s);
 hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
                               int two_d, uint64_t *keys, uint32_t *vals, hipStream_t s);
+// Packed panel rows.  A row holds dp coordinates: FP32 values (4 bytes), one
+// 16-bit value each (BF16, FP16), or for the hi/lo splits groups of 16 hi
+// values followed by their 16 lo values (4 bytes per coordinate).  dp is d
+// rounded up so that a row is a whole number of 64-byte slabs, at least four.
+__host__ __device__ inline int panel_dp(int prec, int d) {
+    if (prec == P_FP32) return d <= 64 ? 64 : 32 * ((d + 31) / 32);
+    if (prec == P_BF16X3 || prec == P_FP16X3) return 64 * ((d + 63) / 64);
+    return d <= 128 ? 128 : 64 * ((d + 63) / 64);
+}
+__host__ __device__ inline int64_t panel_row_bytes(int prec, int dp) {
+    return (int64_t)dp * ((prec == P_BF16 || prec == P_FP16) ? 2 : 4);
+}
+// Distance between consecutive rows: the row bytes padded to an odd number of
+// 128-byte lines, so that the same slab of many rows spreads over all L2
+// channels (a power-of-two row stride would put it on a few of them).
+__host__ __device__ inline int64_t panel_row_stride(int prec, int dp) {
+    const int64_t b = panel_row_bytes(prec, dp);
+    return ((b >> 7) & 1) ? b : b + 128;
+}
+
 struct PackArgs {
     const float *X; int32_t d; int32_t dp;
     const uint32_t *slot_point; int64_t n_slots;
     int prec;
     double scale;              // power of two applied to coordinates
     double E_scaled;           // eps^2 * scale^2
-    void *panel_hi; void *panel_lo;
+    void *panel;               // packed rows (panel_row_bytes each, panel_row_stride apart)
     float *thrA; float *thrB;  // in-threshold / out-threshold of each slot
     double *dbg_norm2;         // optional: |x_s|^2 (scaled)
     double *dbg_e;             // optional: e_s, the slot's share of the Gram error bound (scaled)
@@ -171,22 +191,24 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 // tile.hip
 struct TileArgs {
     TileTable tt;
-    const void *panel_hi; const void *panel_lo; int32_t dp;
+    const void *panel; int32_t dp;
     const float *thrA; const float *thrB;
     uint32_t *bitmask; int32_t *count;
-    BandPair *band; unsigned long long *band_n; int64_t band_cap;
+    // band pairs: nseg segments of band_cap entries; band_n[g] counts the pairs
+    // of segment g (past band_cap they are counted but not stored)
+    BandPair *band; unsigned long long *band_n; int64_t band_cap; int32_t nseg;
     float *debug_g;            // non-null: write raw Gram values (debug, one element)
     int64_t debug_ld;
-    unsigned int *queue;       // work counters (persistent launch)
-    int grid;                  // number of workgroups launched
+    int grid;                  // > 0: persistent launch of this many workgroups (a multiple of 8)
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
 int tile_grid_size(int prec, int64_t n_items);
-hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
-                          const uint32_t *slot_point, double E, uint32_t *bitmask,
-                          int32_t *count, hipStream_t s);
+// seg_start[g] = pairs in segments before g (nseg + 1 entries, the last is the total).
+hipError_t launch_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg, int64_t band_cap,
+                          int64_t nband, const float *X, int32_t d, const uint32_t *slot_point, double E,
+                          uint32_t *bitmask, int32_t *count, hipStream_t s);
 hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
                             double *out, hipStream_t s);
 hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, const float *X,

@@ -608,10 +608,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     HIPCHK(launch_build_items(tt, d_items, s));
     tt.items = d_items;
 
-    const int dp = prec == P_FP32 ? 32 * ((d + 31) / 32) : dp16;
-    const int esz = prec == P_FP32 ? 4 : 2;
-    void *panel_hi = mem.get<char>((uint64_t)Sa * dp * esz);
-    void *panel_lo = prec_is_split(prec) ? mem.get<char>((uint64_t)Sa * dp * esz) : nullptr;
+    const int dp = panel_dp(prec, d);
+    void *panel = mem.get<char>((uint64_t)Sa * (uint64_t)panel_row_stride(prec, dp));
     float *thrA = mem.get<float>(Sa), *thrB = mem.get<float>(Sa);
     PackArgs pk;
     pk.X = cloud->X;
@@ -622,8 +620,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     pk.prec = prec;
     pk.scale = scale;
     pk.E_scaled = E * scale * scale;
-    pk.panel_hi = panel_hi;
-    pk.panel_lo = panel_lo;
+    pk.panel = panel;
     pk.thrA = thrA;
     pk.thrB = thrB;
     pk.dbg_norm2 = nullptr;
@@ -633,34 +630,34 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int32_t *count = mem.get<int32_t>(Sa);
     uint32_t *bitmask = mem.get<uint32_t>((uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS);
     st.bitmask_bytes = nblocks * TILE_WORDS * 4;
-    unsigned long long *band_n = mem.get<unsigned long long>(1);
-    unsigned int *queue = mem.get<unsigned int>(8);
-    const bool persistent = (P->flags & MAPPER_FLAG_PERSISTENT) != 0;
-    int64_t band_cap = std::max<int64_t>(1 << 20, pairs / 256);
-    band_cap = std::min<int64_t>(band_cap, 1ll << 28);
+    // band list: one segment per persistent workgroup (the one-workgroup-per-
+    // tile launch shares the same segments), grown and the tiles redone if
+    // a segment overflows
+    const bool per_tile = (P->flags & MAPPER_FLAG_TILE_PER_WORKGROUP) != 0;
+    const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two workgroups per CU, a multiple of the 8 XCDs
+    unsigned long long *band_n = mem.get<unsigned long long>(nseg);
+    int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
+    band_cap = std::max<int64_t>(band_cap, 1024);
     BandPair *band = nullptr;
     for (;;) {
         try {
-            band = mem.get<BandPair>(band_cap);
+            band = mem.get<BandPair>((uint64_t)nseg * band_cap);
         } catch (NoMem &) {
-            band_cap /= 4;
-            if (band_cap < 4096) throw;
+            if (band_cap <= 8) throw;                       // small arenas: a small list, grown on demand
+            band_cap = std::max<int64_t>(band_cap / 4, 8);
             continue;
         }
         break;
     }
     ev.mark();                                                      // 3
-    int64_t nband = 0;
+    std::vector<unsigned long long> segn(nseg);
     for (int launch = 0;; ++launch) {
         HIPCHK(hipMemsetAsync(count, 0, (size_t)Sa * 4, s));
-        HIPCHK(hipMemsetAsync(band_n, 0, 8, s));
-        HIPCHK(hipMemsetAsync(queue, 0, 8 * sizeof(unsigned int), s));
+        HIPCHK(hipMemsetAsync(band_n, 0, (size_t)nseg * 8, s));
         TileArgs ta{};
-        ta.queue = queue;
-        ta.grid = persistent ? 2 * ctx->cus : 0;
+        ta.grid = per_tile ? 0 : nseg;
         ta.tt = tt;
-        ta.panel_hi = panel_hi;
-        ta.panel_lo = panel_lo;
+        ta.panel = panel;
         ta.dp = dp;
         ta.thrA = thrA;
         ta.thrB = thrB;
@@ -669,25 +666,28 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         ta.band = band;
         ta.band_n = band_n;
         ta.band_cap = band_cap;
+        ta.nseg = nseg;
         Events kt(s);
         kt.mark();
         HIPCHK(launch_tiles(prec, ta, s));
         kt.mark();
-        unsigned long long nb = 0;
-        HIPCHK(hipMemcpyAsync(&nb, band_n, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(segn.data(), band_n, (size_t)nseg * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         st.tile_launches = launch + 1;
         st.ms_tiles = kt.ms(0, 1);
-        if ((int64_t)nb <= band_cap) {
-            nband = (int64_t)nb;
-            break;
-        }
-        band_cap = (int64_t)nb + (int64_t)nb / 8 + 1024;     // grow and redo the tiles
-        band = mem.get<BandPair>(band_cap);
+        const int64_t most = (int64_t)*std::max_element(segn.begin(), segn.end());
+        if (most <= band_cap) break;
+        band_cap = most + most / 8 + 256;                   // grow and redo the tiles
+        band = mem.get<BandPair>((uint64_t)nseg * band_cap);
     }
+    std::vector<int64_t> seg_start(nseg + 1, 0);
+    for (int g = 0; g < nseg; ++g) seg_start[g + 1] = seg_start[g] + (int64_t)segn[g];
+    const int64_t nband = seg_start[nseg];
+    int64_t *d_seg_start = mem.get<int64_t>(nseg + 1);
+    h2d(d_seg_start, seg_start.data(), nseg + 1, s);
     st.band_pairs = nband;
     ev.mark();                                                      // 4
-    HIPCHK(launch_recheck(band, nband, cloud->X, d, slot_point, E, bitmask, count, s));
+    HIPCHK(launch_recheck(band, d_seg_start, nseg, band_cap, nband, cloud->X, d, slot_point, E, bitmask, count, s));
     ev.mark();                                                      // 5
 
     // ---- clusters
@@ -1126,8 +1126,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         h2d(d_od, od, 1, s);
         double scale = 1.0;
         if (cloud->maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)cloud->maxabs));
-        const int dp = precision == P_FP32 ? 32 * ((d + 31) / 32) : 64 * ((d + 63) / 64);
-        const int esz = precision == P_FP32 ? 4 : 2;
+        const int dp = panel_dp(precision, d);
         PackArgs pk{};
         pk.X = cloud->X;
         pk.d = d;
@@ -1137,8 +1136,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         pk.prec = precision;
         pk.scale = scale;
         pk.E_scaled = eps * eps * scale * scale;
-        pk.panel_hi = mem.get<char>((uint64_t)nrows * dp * esz);
-        pk.panel_lo = prec_is_split(precision) ? mem.get<char>((uint64_t)nrows * dp * esz) : nullptr;
+        pk.panel = mem.get<char>((uint64_t)nrows * (uint64_t)panel_row_stride(precision, dp));
         pk.thrA = mem.get<float>(nrows);
         pk.thrB = mem.get<float>(nrows);
         pk.dbg_norm2 = mem.get<double>(nrows);
@@ -1161,8 +1159,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(P, 1));
         HIPCHK(launch_build_items(ta.tt, d_items, s));
         ta.tt.items = d_items;
-        ta.panel_hi = pk.panel_hi;
-        ta.panel_lo = pk.panel_lo;
+        ta.panel = pk.panel;
         ta.dp = dp;
         ta.thrA = pk.thrA;
         ta.thrB = pk.thrB;
@@ -1171,6 +1168,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.band_cap = 0;
         ta.band = nullptr;
         ta.band_n = mem.get<unsigned long long>(1);
+        ta.nseg = 1;
         ta.debug_g = mem.get<float>((uint64_t)nrows * nrows);
         ta.debug_ld = nrows;
         HIPCHK(hipMemsetAsync(ta.count, 0, (size_t)nrows * 4, s));

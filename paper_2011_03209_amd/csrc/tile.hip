@@ -84,24 +84,30 @@ template <int PREC> struct Feed {
     int dst[Lay<PREC>::CPT];
 };
 
+// Global bytes of a row consumed per slab (the hi and lo halves of a split
+// slab sit in the same 128 bytes of the interleaved row layout).
+template <int PREC> constexpr uint32_t slab_gbytes() { return Lay<PREC>::RB * Cfg<PREC>::PANELS; }
+
 template <int PREC>
 __device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl, Feed<PREC> &f) {
     using L = Lay<PREC>;
-    const uint32_t rowb = (uint32_t)a.dp * Cfg<PREC>::ESZ;
+    constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
+    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int64_t r0 = (int64_t)(side == 0 ? tl.I : tl.J) * TILE;
         const int64_t nrow = tl.ne - r0;
 #pragma unroll
-        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl)
+        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl)   // lo values: 32 bytes after their hi values
             f.base[side * Cfg<PREC>::PANELS + pnl] =
-                (const char *)(pnl == 0 ? a.panel_hi : a.panel_lo) + (tl.slot0 + r0) * (int64_t)rowb;
+                (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride + pnl * 32;
 #pragma unroll
         for (int q = 0; q < L::CPT; ++q) {
             const int idx = q * NT + threadIdx.x;
             const int r = idx / L::CPR, c = idx % L::CPR;
             const int rr = r < nrow ? r : (int)(nrow - 1);
-            f.voff[side][q] = (uint32_t)rr * rowb + (uint32_t)(c * 16);
+            const int coff = SPLIT ? (c >> 1) * 64 + (c & 1) * 16 : c * 16;
+            f.voff[side][q] = (uint32_t)rr * stride + (uint32_t)coff;
         }
     }
 #pragma unroll
@@ -133,6 +139,15 @@ __device__ __forceinline__ void lstore(char *stage, const Feed<PREC> &f, const u
 #pragma unroll
         for (int q = 0; q < L::CPT; ++q)
             *(u32x4 *)(stage + sp * L::PANEL_BYTES + f.dst[q]) = reg[sp * L::CPT + q];
+}
+
+// The lane index through an empty asm: values derived from it inside a loop
+// body are recomputed there instead of being hoisted into registers that
+// would stay live across the whole loop.
+__device__ __forceinline__ int lane_id_here() {
+    int l = (int)(threadIdx.x & (WAVE - 1));
+    asm volatile("" : "+v"(l));
+    return l;
 }
 
 template <int PREC> struct Acc {
@@ -231,14 +246,15 @@ struct EpiShared {
     int32_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes
 };
 
-// Decisions of one 32 x 32 accumulator block: the row words of its bitmask
-// go to LDS, the lane's column count is added to colc, and the result says
-// whether the block has band pairs.  FULL: the block lies inside the element
-// and off the diagonal, so no bounds or triangle masks are needed.
-template <int PREC, bool FULL, bool DEBUG>
+// Decisions of one 32 x 32 accumulator block (its 16 Gram values per lane in
+// gv): the row words of its bitmask go to LDS, the lane's column count is
+// added to colc, and the result says whether the block has band pairs.
+// FULL: the block lies inside the element and off the diagonal, so no bounds
+// or triangle masks are needed.
+template <bool FULL, bool DEBUG>
 __device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
-                                          const Acc<PREC> &acc, int bm, int bn, int wm, int wn, int &colc) {
-    const int lane = threadIdx.x & (WAVE - 1);
+                                          const f32x16 &gv, int bm, int bn, int wm, int wn, int &colc) {
+    const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
     const int cl = wn * 64 + bn * 32 + li;                  // column within the tile
@@ -255,8 +271,7 @@ __device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, 
     uint64_t anyband = 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        float g = acc.c[bm][bn][v];
-        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
+        const float g = gv[v];
         bool in, band;
         if constexpr (FULL) {
             in = g >= TA[v >> 2][v & 3] + Aj;
@@ -288,56 +303,125 @@ __device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, 
     return anyband != 0;
 }
 
-// Band pairs of one block -> FP64 recheck list (rare; wave-aggregated append).
-template <int PREC>
+// Band pairs of one block -> FP64 recheck list, appended per register row
+// that has any (wave-aggregated).  The list has one segment per persistent
+// workgroup, counted in LDS (`wg_count`); the one-workgroup-per-tile launch
+// shares the segments through global counters.
 __device__ __forceinline__ void epi_band(const TileArgs &a, const TilePos &tl, const EpiShared &es,
-                                      const Acc<PREC> &acc, int bm, int bn, int wm, int wn) {
-    const int lane = threadIdx.x & (WAVE - 1);
+                                         const f32x16 &gv, int bm, int bn, int wm, int wn,
+                                         unsigned int *wg_count) {
+    const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
     const int cl = wn * 64 + bn * 32 + li;
     const int64_t gc = (int64_t)tl.J * TILE + cl;
     const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
     const int r0 = wm * 64 + bm * 32 + 4 * lg;
-    // the decisions are recomputed in each pass rather than kept (keeps the
-    // common path free of their registers)
-    auto band_at = [&](int v) -> bool {
-        const int rl = r0 + 8 * (v >> 2) + (v & 3);
-        const int64_t gr = (int64_t)tl.I * TILE + rl;
-        float g = acc.c[bm][bn][v];
-        if constexpr (Cfg<PREC>::PANELS == 2) g = g + acc.x[bm][bn][v];
-        asm volatile("" : "+v"(g));
-        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
-        const bool self = diag && rl == cl;
-        const bool in = valid && (self || g >= es.thrA[rl] + Aj);
-        return valid && !in && !(g < es.thrB[rl] + Bj);
-    };
-    int nb = 0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) nb += __popcll(__ballot(band_at(v)));
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.band_n, (unsigned long long)nb);
-    base = __shfl(base, 0, WAVE);
+    const int seg = wg_count ? (int)blockIdx.x : (int)(blockIdx.x % (unsigned)a.nseg);
     const uint64_t lt = (1ull << lane) - 1ull;
-    int before = 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int rl = r0 + 8 * (v >> 2) + (v & 3);
         const int64_t gr = (int64_t)tl.I * TILE + rl;
-        const bool band = band_at(v);
+        const float g = gv[v];
+        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
+        const bool self = diag && rl == cl;
+        const bool in = valid && (self || g >= es.thrA[rl] + Aj);
+        const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
         const uint64_t bb = __ballot(band);
+        if (bb == 0) continue;
+        uint32_t base = 0;
+        if (lane == 0)
+            base = wg_count ? atomicAdd(wg_count, (unsigned int)__popcll(bb))
+                            : (uint32_t)atomicAdd(&a.band_n[seg], (unsigned long long)__popcll(bb));
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
         if (band) {
-            const int64_t idx = (int64_t)base + before + __popcll(bb & lt);
+            const int64_t idx = (int64_t)base + __popcll(bb & lt);
             if (idx < a.band_cap) {
                 BandPair bp;
                 bp.si = (int32_t)(tl.slot0 + gr);
                 bp.sj = (int32_t)(tl.slot0 + gc);
                 bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(rl * 4 + (cl >> 5))) * 32u
                          + (uint64_t)(cl & 31);
-                a.band[idx] = bp;
+                a.band[(int64_t)seg * a.band_cap + idx] = bp;
             }
         }
-        before += __popcll(bb);
+    }
+}
+
+// The Gram values of accumulator block blk = 2 bm + bn (blk wave-uniform).
+template <int PREC>
+__device__ __forceinline__ f32x16 acc_block(const Acc<PREC> &acc, int blk) {
+    f32x16 r = acc.c[0][0];
+    if (blk == 1) r = acc.c[0][1];
+    else if (blk == 2) r = acc.c[1][0];
+    else if (blk == 3) r = acc.c[1][1];
+    return r;
+}
+
+// Workgroup barrier over LDS traffic only: the wave's own LDS accesses are
+// complete, global memory operations may still be in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Decisions of the tile's four accumulator blocks per wave, then (after a
+// barrier) the 2 KB bitmask block and the neighbour counts: a row's count is
+// the popcount of its four words, a column's the sum of its partials.
+template <int PREC, bool DEBUG>
+__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC> &acc,
+                                              EpiShared &es, int wm, int wn, unsigned int *wg_count) {
+    if constexpr (Cfg<PREC>::PANELS == 2) {                 // Gram value = hi.hi + cross terms
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < 2; ++bn) acc.c[bm][bn] = acc.c[bm][bn] + acc.x[bm][bn];
+    }
+    const bool diag = tl.I == tl.J;
+    const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
+    unsigned hb = 0;                                        // blocks with band pairs
+    int colc0 = 0, colc1 = 0;
+    if (!DEBUG && full) {
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            const int bm = blk >> 1, bn = blk & 1;
+            if (epi_block<true, false>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0))
+                hb |= 1u << blk;
+        }
+    } else {                                                // diagonal or ragged tiles (few): one copy
+#pragma unroll 1
+        for (int blk = 0; blk < 4; ++blk) {
+            const int bm = blk >> 1, bn = blk & 1;
+            int cc = 0;
+            if (epi_block<false, DEBUG>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc)) hb |= 1u << blk;
+            if (bn) colc1 += cc;
+            else colc0 += cc;
+        }
+    }
+    {
+        const int lane = lane_id_here();
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = colc0;
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = colc1;
+    }
+    if (hb) {
+#pragma unroll 1
+        for (int blk = 0; blk < 4; ++blk)
+            if ((hb >> blk) & 1u) epi_band(a, tl, es, acc_block(acc, blk), blk >> 1, blk & 1, wm, wn, wg_count);
+    }
+    lds_barrier();
+    {
+        uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
+        const int t = (threadIdx.x & ~(WAVE - 1)) + lane_id_here();
+        *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
+        if (t < TILE) {
+            const int64_t r = (int64_t)tl.I * TILE + t;
+            const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
+            const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
+            if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
+        } else {
+            const int cc = t - TILE;
+            const int64_t gc = (int64_t)tl.J * TILE + cc;
+            const int c = es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
+            if (gc < tl.ne && c) atomicAdd(&a.count[tl.slot0 + gc], c);
+        }
     }
 }
 
@@ -346,7 +430,6 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
     using L = Lay<PREC>;
     const int w = threadIdx.x / WAVE;
     const int wm = w >> 1, wn = w & 1;
-    const bool diag = tl.I == tl.J;
 
     // K loop: double-buffered LDS slabs, the next slab's global loads in
     // flight while the current one feeds the matrix cores
@@ -367,59 +450,18 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
     lstore<PREC>(stages, feed, reg);
     __syncthreads();
     Acc<PREC> acc;
-    if (nst > 1) gload<PREC>(feed, L::RB, reg);
+    if (nst > 1) gload<PREC>(feed, slab_gbytes<PREC>(), reg);
     compute_stage<PREC, true>(stages, acc, wm, wn);
     if (nst > 1) lstore<PREC>(stages + L::STAGE_BYTES, feed, reg);
     __syncthreads();
     for (int st = 1; st < nst; ++st) {
         char *cur = stages + (st & 1) * L::STAGE_BYTES;
-        if (st + 1 < nst) gload<PREC>(feed, (uint32_t)(st + 1) * L::RB, reg);
+        if (st + 1 < nst) gload<PREC>(feed, (uint32_t)(st + 1) * slab_gbytes<PREC>(), reg);
         compute_stage<PREC, false>(cur, acc, wm, wn);
         if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, feed, reg);
         __syncthreads();
     }
-
-    // ---------------------------------------------------------------- epilogue
-    const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
-    bool hb[2][2];
-    int colc[2] = {0, 0};
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn) {
-            if (!DEBUG && full) hb[bm][bn] = epi_block<PREC, true, false>(a, tl, es, acc, bm, bn, wm, wn, colc[bn]);
-            else hb[bm][bn] = epi_block<PREC, false, DEBUG>(a, tl, es, acc, bm, bn, wm, wn, colc[bn]);
-        }
-    {
-        const int lane = threadIdx.x & (WAVE - 1);
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = colc[0];
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = colc[1];
-    }
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn)
-            if (hb[bm][bn]) epi_band<PREC>(a, tl, es, acc, bm, bn, wm, wn);
-    __syncthreads();
-    // bitmask block (2 KB, coalesced) and neighbour counts: a row's count is
-    // the popcount of its four words, a column's the sum of its partials
-    {
-        uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
-        const int t = threadIdx.x;
-        *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
-        if (t < TILE) {
-            const int64_t r = (int64_t)tl.I * TILE + t;
-            const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
-            const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
-            if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
-        } else {
-            const int cc = t - TILE;
-            const int64_t gc = (int64_t)tl.J * TILE + cc;
-            const int c = es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
-            if (gc < tl.ne && c) atomicAdd(&a.count[tl.slot0 + gc], c);
-        }
-    }
-    __syncthreads();
+    tile_epilogue<PREC, DEBUG>(a, tl, acc, es, wm, wn, nullptr);
 }
 
 template <int PREC, bool DEBUG>
@@ -437,41 +479,244 @@ __global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
     process_tile<PREC, DEBUG>(a, tl, stages, es);
 }
 
+// ------------------------------------------------------------------ ring form
+// Persistent workgroups (two per CU) stream their tile pairs through a
+// four-slab LDS ring filled by LDS-direct loads (global_load_lds: the data
+// goes from memory to LDS without registers), so three slabs are in flight
+// while the matrix cores work on the fourth, across tile boundaries: the
+// next tile's first slabs and thresholds load during this tile's last slabs
+// and epilogue.  A slab is 64 bytes of every row of both sides (16 KB).  Each
+// wave fills a quarter of a slab with four 1 KB loads; lane l of a load
+// writes LDS bytes [16 l, 16 l + 16) of the load's 1 KB, so a lane reads the
+// global chunk that belongs at that swizzled position.
+constexpr int RNS = 4;                        // ring slabs
+constexpr int RROW = 64;                      // bytes of a row per slab
+constexpr int RSLAB = 2 * TILE * RROW;        // 16 KB
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+}
+
+// LDS-direct loads: M0 holds the wave's LDS destination (set in the same
+// statement; nothing else in these kernels uses M0).  Completion is tracked
+// by hand with vmcnt: the compiler does not see these loads.
+__device__ __forceinline__ void lds_load16(uint32_t lds, const char *sbase, uint32_t voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
+                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
+}
+__device__ __forceinline__ void lds_load4(uint32_t lds, const char *sbase, uint32_t voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, %2"
+                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
+}
+// Wait until at most N vector memory operations of this wave are in flight.
+template <int N> __device__ __forceinline__ void vm_wait() { asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory"); }
+
+__device__ __forceinline__ int rswz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int roff(int r, int c) { return r * RROW + ((c ^ rswz(r)) << 4); }
+
+// One slab of the ring through the matrix cores.  Chunk c of a row holds:
+// FP32 values 4c..4c+3; BF16/FP16 values 8c..8c+7; hi/lo splits the hi
+// (c = 0, 1) or lo (c = 2, 3) halves of values 8(c%2)..8(c%2)+7.
+template <int PREC, bool FIRST>
+__device__ __forceinline__ void ring_compute(const char *slab, Acc<PREC> &acc, int wm, int wn) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int li = lane & 31, lg = lane >> 5;
+    const f32x16 zero = {};
+    const char *A = slab, *B = slab + TILE * RROW;
+    if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int ss = 0; ss < 2; ++ss) {
+            f32x4 av[2], bv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                av[b] = *(const f32x4 *)(A + roff(wm * 64 + b * 32 + li, 2 * ss + lg));
+                bv[b] = *(const f32x4 *)(B + roff(wn * 64 + b * 32 + li, 2 * ss + lg));
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                    for (int bn = 0; bn < 2; ++bn)
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            av[bm][t], bv[bn][t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][bn], 0, 0, 0);
+        }
+    } else if constexpr (Cfg<PREC>::PANELS == 1) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            u32x4 ah[2], bh[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                ah[b] = *(const u32x4 *)(A + roff(wm * 64 + b * 32 + li, 2 * ks + lg));
+                bh[b] = *(const u32x4 *)(B + roff(wn * 64 + b * 32 + li, 2 * ks + lg));
+            }
+            const bool z0 = FIRST && ks == 0;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    if constexpr (PREC == P_BF16)
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
+                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
+                    else
+                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
+                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
+                }
+        }
+    } else {
+        u32x4 ah[2], bh[2], al[2], bl[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ra = wm * 64 + b * 32 + li, rb = wn * 64 + b * 32 + li;
+            ah[b] = *(const u32x4 *)(A + roff(ra, lg));
+            al[b] = *(const u32x4 *)(A + roff(ra, 2 + lg));
+            bh[b] = *(const u32x4 *)(B + roff(rb, lg));
+            bl[b] = *(const u32x4 *)(B + roff(rb, 2 + lg));
+        }
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < 2; ++bn) {
+                if constexpr (PREC == P_BF16X3) {
+                    acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
+                        FIRST ? zero : acc.c[bm][bn], 0, 0, 0);
+                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bl[bn]),
+                        FIRST ? zero : acc.x[bm][bn], 0, 0, 0);
+                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, al[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
+                        acc.x[bm][bn], 0, 0, 0);
+                } else {
+                    acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
+                        FIRST ? zero : acc.c[bm][bn], 0, 0, 0);
+                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bl[bn]),
+                        FIRST ? zero : acc.x[bm][bn], 0, 0, 0);
+                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, al[bm]), __builtin_bit_cast(f16x8, bh[bn]),
+                        acc.x[bm][bn], 0, 0, 0);
+                }
+            }
+    }
+}
+
+// Producer state of one wave for one tile: rows 64 (w % 2) .. + 63 of side
+// w / 2.  `sbase` is the global address of the current slab of the side's
+// first row (advanced by 64 bytes per slab), `vo[i]` lane's byte offset for
+// its chunk in load i (rows past the element clamped to its last row).
+struct RingFeed {
+    const char *sbase;
+    uint32_t vo[4];
+};
+
+__device__ __forceinline__ void ring_setup(const TileArgs &a, const TilePos &tl, int w, int lane, uint32_t stride,
+                                           bool thr, uint32_t thr_lds, RingFeed &f) {
+    const int side = w >> 1;
+    const int64_t r0 = (int64_t)(side ? tl.J : tl.I) * TILE;
+    const int64_t nrow = tl.ne - r0;                        // rows of this side in the element (>= 1)
+    const int rw = (w & 1) * 64;                            // first side row of this wave
+    if (thr) {                                              // the tile's thresholds of these rows
+        const int r = rw + lane;
+        const uint32_t vo = (uint32_t)(r < nrow ? r : (int)(nrow - 1)) * 4u;
+        lds_load4(thr_lds, (const char *)(a.thrA + tl.slot0 + r0), vo);
+        lds_load4(thr_lds + 2 * TILE * 4, (const char *)(a.thrB + tl.slot0 + r0), vo);
+    }
+    f.sbase = (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = rw + i * 16 + (lane >> 2);            // side row of this lane's chunk
+        const int c = (lane & 3) ^ rswz(w * 64 + i * 16 + (lane >> 2));
+        f.vo[i] = (uint32_t)(r < nrow ? r : (int)(nrow - 1)) * stride + (uint32_t)(c << 4);
+    }
+}
+
+// The wave's quarter of the feed's next slab into the ring slot at `slot_lds`.
+__device__ __forceinline__ void ring_issue(RingFeed &f, uint32_t slot_lds, int w) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds_load16(slot_lds + (uint32_t)((w * 4 + i) * 1024), f.sbase, f.vo[i]);
+    f.sbase += RROW;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT, 2) k_tiles_ring(TileArgs a) {
+    __shared__ __attribute__((aligned(1024))) char ring[RNS * RSLAB];
+    __shared__ EpiShared es[2];
+    __shared__ unsigned int band_used;                      // this workgroup's band segment
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wm = w >> 1, wn = w & 1;
+    // this workgroup's items: XCD slice of the item order, strided by the
+    // number of workgroups on the XCD (concurrent items stay consecutive)
+    const int64_t n = a.tt.n_items;
+    const int64_t per = (n + 7) / 8;
+    const int64_t gx = gridDim.x / 8;
+    const int64_t lo = (int64_t)(blockIdx.x % 8) * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    const int64_t first = lo + blockIdx.x / 8;
+    if (first >= hi) return;
+    const int nt = (int)((hi - first + gx - 1) / gx);       // tiles of this workgroup
+    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
+    const int nst = (int)(panel_row_bytes(PREC, a.dp) / RROW);   // slabs per tile (>= 4)
+    const uint32_t ring_lds = lds_addr(ring);
+    const uint32_t thr_lds0 = lds_addr(&es[0].thrA[0]) + (uint32_t)(w * 64 * 4);
+    const uint32_t es_stride = (uint32_t)sizeof(EpiShared);
+    auto slot_lds = [&](int slot) { return ring_lds + (uint32_t)(slot * RSLAB); };
+
+    // The producer runs RNS - 1 slabs ahead of the consumer, into the next
+    // tile during a tile's last slabs; after the last tile it stops, and the
+    // waits below count the loads actually in flight.
+    if (threadIdx.x == 0) band_used = 0;                    // first read after several barriers
+    TilePos tc = tile_lookup(a.tt, first);
+    RingFeed feed;
+    ring_setup(a, tc, w, lane, stride, true, thr_lds0, feed);
+#pragma unroll
+    for (int i = 0; i < RNS - 1; ++i) ring_issue(feed, slot_lds(i), w);
+    int pslot = RNS - 1, cslot = 0;
+
+    Acc<PREC> acc;
+#pragma unroll 1
+    for (int k = 0; k < nt; ++k) {
+        const bool more = k + 1 < nt;
+        const TilePos tn = more ? tile_lookup(a.tt, first + (int64_t)(k + 1) * gx) : tc;
+#pragma unroll 1
+        for (int s = 0; s < nst; ++s) {
+            // loads issued after slab s's own: 4 per later slab in flight (two,
+            // fewer at the very end) plus the next tile's 2 threshold loads
+            if (s + 2 < nst) vm_wait<8>();
+            else if (more) vm_wait<10>();
+            else if (s + 2 == nst) vm_wait<4>();
+            else vm_wait<0>();
+            lds_barrier();
+            if (s + RNS - 1 == nst && more)                 // the producer moves to the next tile
+                ring_setup(a, tn, w, lane, stride, true, thr_lds0 + (uint32_t)((k + 1) & 1) * es_stride, feed);
+            if (s + RNS - 1 < nst || more) {
+                ring_issue(feed, slot_lds(pslot), w);
+                pslot = (pslot + 1) & (RNS - 1);
+            }
+            const char *slab = ring + cslot * RSLAB;
+            cslot = (cslot + 1) & (RNS - 1);
+            if (s == 0) ring_compute<PREC, true>(slab, acc, wm, wn);
+            else ring_compute<PREC, false>(slab, acc, wm, wn);
+        }
+        tile_epilogue<PREC, false>(a, tc, acc, es[k & 1], wm, wn, &band_used);
+        tc = tn;
+    }
+    vm_wait<0>();                                           // no LDS-direct load outlives the workgroup
+    lds_barrier();
+    if (threadIdx.x == 0) a.band_n[blockIdx.x] = band_used;
+}
+
 // FP64 re-decision of band pairs, one pair per wave at a time.  The lanes
 // read the two rows with coalesced loads and sum (x_j - y_j)^2 in FP64 as a
 // tree; that value is within 2 gamma_{d+4} D of the canonical sequential
 // chain, so only pairs closer than that to eps^2 (ties, in practice) need
 // the canonical chain itself, which lane 0 then evaluates in order.
-// Persistent form: a fixed grid (a few workgroups per CU) drains the tile
-// pairs through eight atomic counters, one per XCD slice of the item order
-// (largest elements first).  A workgroup starts on the slice of the XCD it
-// was dealt to and then helps the others; it leaves when every slice is
-// exhausted, so the grid always drains.
-template <int PREC>
-__global__ void __launch_bounds__(NT, 2) k_tiles_persistent(TileArgs a) {
-    __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
-    __shared__ EpiShared es;
-    __shared__ int64_t next;
-    const int64_t n = a.tt.n_items;
-    const int64_t per = (n + 7) / 8;
-    const int x0 = blockIdx.x % 8;
-    for (int k = 0; k < 8; ++k) {
-        const int x = (x0 + k) % 8;
-        const int64_t lo = (int64_t)x * per;
-        const int64_t hi = lo + per < n ? lo + per : n;
-        while (true) {
-            if (threadIdx.x == 0) next = lo + (int64_t)atomicAdd(&a.queue[x], 1u);
-            __syncthreads();
-            const int64_t item = next;
-            __syncthreads();
-            if (item >= hi) break;
-            const TilePos tl = tile_lookup(a.tt, item);
-            process_tile<PREC, false>(a, tl, stages, es);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_recheck(const BandPair *band, int64_t nband, const float *X,
+__global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg,
+                                                 int64_t band_cap, int64_t nband, const float *X,
                                                  int32_t d, const uint32_t *slot_point, double E,
                                                  uint32_t *bitmask, int32_t *count) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -481,7 +726,13 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, int64_t n
     const double gd = (d + 4) * u / (1.0 - (d + 4) * u);
     const double cf = 4.0 * gd / (1.0 - gd);              // twice the certified gap, for margin
     for (int64_t b = wid; b < nband; b += nw) {
-        const BandPair bp = band[b];
+        int lo = 0, hi = nseg;                              // segment g: seg_start[g] <= b < seg_start[g + 1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (seg_start[mid] <= b) lo = mid;
+            else hi = mid;
+        }
+        const BandPair bp = band[(int64_t)lo * band_cap + (b - seg_start[lo])];
         const float *x = X + (int64_t)slot_point[bp.si] * d;
         const float *y = X + (int64_t)slot_point[bp.sj] * d;
         double part = 0.0;
@@ -554,7 +805,7 @@ template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
     if (a.grid > 0 && !a.debug_g) {
-        k_tiles_persistent<PREC><<<dim3((unsigned)a.grid), dim3(NT), 0, s>>>(a);
+        k_tiles_ring<PREC><<<dim3((unsigned)a.grid), dim3(NT), 0, s>>>(a);
         return hipGetLastError();
     }
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
@@ -587,13 +838,14 @@ hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_recheck(const BandPair *band, int64_t nband, const float *X, int32_t d,
-                          const uint32_t *slot_point, double E, uint32_t *bitmask,
-                          int32_t *count, hipStream_t s) {
+hipError_t launch_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg, int64_t band_cap,
+                          int64_t nband, const float *X, int32_t d, const uint32_t *slot_point, double E,
+                          uint32_t *bitmask, int32_t *count, hipStream_t s) {
     if (nband <= 0) return hipSuccess;
     int64_t blocks = (nband + 3) / 4;
     if (blocks > 32768) blocks = 32768;
-    k_recheck<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(band, nband, X, d, slot_point, E, bitmask, count);
+    k_recheck<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(band, seg_start, nseg, band_cap, nband, X, d,
+                                                           slot_point, E, bitmask, count);
     return hipGetLastError();
 }
 

@@ -210,20 +210,49 @@ def test_tile_distances(ctx, prec, data):
         assert np.all(err <= 1e-5 * (nrm[:, None] + nrm[None, :]))
 
 
-@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3])
-def test_persistent_matches_grid_launch(ctx, prec):
-    """The one-workgroup-per-tile launch and the persistent launch give the
-    same graph (and the oracle's)."""
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
+                                  synth.PREC_FP16, synth.PREC_FP16X3])
+@pytest.mark.parametrize("load", ["grid2d_d128", "d256", "d40"])
+def test_persistent_matches_grid_launch(ctx, prec, load):
+    """The persistent LDS-ring launch (default) and the one-workgroup-per-tile
+    launch give the same graph (and the oracle's): ragged elements, 2-D
+    covers, widths that are and are not multiples of the slab."""
     from paper_2011_03209_amd import binding
-    w = synth.mixture_500k_d128_2d(scale=0.01, precision=prec)
+    if load == "grid2d_d128":
+        w = synth.mixture_500k_d128_2d(scale=0.01, precision=prec)
+    elif load == "d256":
+        w = synth.mixture_1m_d256(scale=0.004, precision=prec)
+    else:
+        w = synth.mixture_100k_d64(scale=0.05)
+        w.X = np.ascontiguousarray(w.X[:, :40])
+        w.params.precision = prec
     cloud = ctx.cloud(w.X)
     try:
         gp = cloud.run(w.params)
-        gg = cloud.run(w.params, flags=binding.FLAG_PERSISTENT)
+        gg = cloud.run(w.params, flags=binding.FLAG_TILE_PER_WORKGROUP)
     finally:
         cloud.destroy()
     same_graph(gp, gg)
     same_graph(gp, oracle_graph(w.X, w.params))
+
+
+@pytest.mark.parametrize("per_tile", [False, True])
+def test_band_list_regrows(ctx, per_tile):
+    """Plain BF16 on one 35k-point element leaves more band pairs than the
+    first band list holds: the list grows, the tiles are redone, and the
+    graph is still the oracle's."""
+    from paper_2011_03209_amd import binding
+    w = synth.mixture_1m_d256(scale=0.035, precision=synth.PREC_BF16)
+    ax = w.params.axes[0]
+    params = synth.Params([synth.Axis(ax.kind, 1, 0.0, direction=ax.direction)], eps=w.params.eps,
+                          min_pts=w.params.min_pts, precision=synth.PREC_BF16)
+    cloud = ctx.cloud(w.X)
+    try:
+        g = cloud.run(params, flags=binding.FLAG_TILE_PER_WORKGROUP if per_tile else 0)
+    finally:
+        cloud.destroy()
+    assert g.stats["tile_launches"] > 1, g.stats
+    same_graph(g, oracle_graph(w.X, params))
 
 
 def test_determinism_and_permutation(ctx):
