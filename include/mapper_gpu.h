@@ -102,9 +102,12 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
-#define MAPPER_FLAG_TILE_PER_WORKGROUP 2u  /* distance tiles launched one workgroup per tile
-                                             pair instead of the default persistent grid
-                                             (same graph; for comparison and debugging) */
+#define MAPPER_FLAG_TILE_PER_WORKGROUP 2u  /* distance tiles: one workgroup per tile pair */
+#define MAPPER_FLAG_TILE_PERSISTENT 4u     /* distance tiles: persistent workgroups streaming
+                                             tile pairs through an LDS ring.  Neither flag:
+                                             the faster form for the precision (the split
+                                             forms: one per tile pair; the others: persistent).
+                                             Both forms give the same graph. */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

@@ -205,10 +205,11 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
 int tile_grid_size(int prec, int64_t n_items);
-// seg_start[g] = pairs in segments before g (nseg + 1 entries, the last is the total).
-hipError_t launch_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg, int64_t band_cap,
-                          int64_t nband, const float *X, int32_t d, const uint32_t *slot_point, double E,
-                          uint32_t *bitmask, int32_t *count, hipStream_t s);
+// band_n[g] = pairs in segment g (<= band_cap), nband their sum.
+hipError_t launch_recheck(const BandPair *band, const unsigned long long *band_n, int32_t nseg,
+                          int64_t band_cap, int64_t nband, const float *X, int32_t d,
+                          const uint32_t *slot_point, double E, uint32_t *bitmask, int32_t *count,
+                          hipStream_t s);
 hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
                             double *out, hipStream_t s);
 hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, const float *X,

@@ -633,7 +633,12 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     // band list: one segment per persistent workgroup (the one-workgroup-per-
     // tile launch shares the same segments), grown and the tiles redone if
     // a segment overflows
-    const bool per_tile = (P->flags & MAPPER_FLAG_TILE_PER_WORKGROUP) != 0;
+    // launch form of the distance tiles (both give the same graph): measured
+    // on MI355X, one workgroup per tile pair is faster for the hi/lo splits
+    // and the persistent LDS ring for the single-term precisions
+    bool per_tile = prec_is_split(prec);
+    if (P->flags & MAPPER_FLAG_TILE_PER_WORKGROUP) per_tile = true;
+    if (P->flags & MAPPER_FLAG_TILE_PERSISTENT) per_tile = false;
     const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two workgroups per CU, a multiple of the 8 XCDs
     unsigned long long *band_n = mem.get<unsigned long long>(nseg);
     int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
@@ -680,14 +685,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         band_cap = most + most / 8 + 256;                   // grow and redo the tiles
         band = mem.get<BandPair>((uint64_t)nseg * band_cap);
     }
-    std::vector<int64_t> seg_start(nseg + 1, 0);
-    for (int g = 0; g < nseg; ++g) seg_start[g + 1] = seg_start[g] + (int64_t)segn[g];
-    const int64_t nband = seg_start[nseg];
-    int64_t *d_seg_start = mem.get<int64_t>(nseg + 1);
-    h2d(d_seg_start, seg_start.data(), nseg + 1, s);
+    int64_t nband = 0;
+    for (int g = 0; g < nseg; ++g) nband += (int64_t)segn[g];
     st.band_pairs = nband;
     ev.mark();                                                      // 4
-    HIPCHK(launch_recheck(band, d_seg_start, nseg, band_cap, nband, cloud->X, d, slot_point, E, bitmask, count, s));
+    HIPCHK(launch_recheck(band, band_n, nseg, band_cap, nband, cloud->X, d, slot_point, E, bitmask, count, s));
     ev.mark();                                                      // 5
 
     // ---- clusters

@@ -242,17 +242,17 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
 struct EpiShared {
     __attribute__((aligned(16))) float thrA[2 * TILE];
     __attribute__((aligned(16))) float thrB[2 * TILE];
-    __attribute__((aligned(16))) uint32_t words[TILE * 4];
-    int32_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes
+    __attribute__((aligned(16))) uint32_t words[TILE * 4];    // bitmask block: 4 words per row
+    __attribute__((aligned(16))) uint32_t bwords[TILE * 4];   // band pairs, same layout
+    uint8_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes (<= 32)
 };
 
 // Decisions of one 32 x 32 accumulator block (its 16 Gram values per lane in
-// gv): the row words of its bitmask go to LDS, the lane's column count is
-// added to colc, and the result says whether the block has band pairs.
-// FULL: the block lies inside the element and off the diagonal, so no bounds
-// or triangle masks are needed.
+// gv): the row words of its bitmask and of its band pairs go to LDS, and the
+// lane's column count is added to colc.  FULL: the block lies inside the
+// element and off the diagonal, so no bounds or triangle masks are needed.
 template <bool FULL, bool DEBUG>
-__device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
+__device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
                                           const f32x16 &gv, int bm, int bn, int wm, int wn, int &colc) {
     const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
@@ -267,8 +267,7 @@ __device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, 
         TA[q] = *(const f32x4 *)&es.thrA[r0 + 8 * q];
         TB[q] = *(const f32x4 *)&es.thrB[r0 + 8 * q];
     }
-    int word = 0;                                          // lane li (< 32): row li of the block
-    uint64_t anyband = 0;
+    int word = 0, bword = 0;                               // lane li (< 32): row li of the block
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const float g = gv[v];
@@ -296,55 +295,44 @@ __device__ __forceinline__ bool epi_block(const TileArgs &a, const TilePos &tl, 
         // the low half of the ballot is row 8(v/4) + v%4, the high half the row 4 below
         word = lane_write((int)(uint32_t)ib, 8 * (v >> 2) + (v & 3), word);
         word = lane_write((int)(uint32_t)(ib >> 32), 8 * (v >> 2) + 4 + (v & 3), word);
-        anyband |= __ballot(band) & ~ib;
-        asm volatile("" : "+s"(anyband));                 // fold now: keeps no masks live
+        const uint64_t bb = __ballot(band) & ~ib;           // rare
+        if (bb) {
+            bword = lane_write((int)(uint32_t)bb, 8 * (v >> 2) + (v & 3), bword);
+            bword = lane_write((int)(uint32_t)(bb >> 32), 8 * (v >> 2) + 4 + (v & 3), bword);
+        }
     }
-    if (lane < 32) es.words[(wm * 64 + bm * 32 + li) * 4 + wn * 2 + bn] = (uint32_t)word;
-    return anyband != 0;
+    if (lane < 32) {
+        const int at = (wm * 64 + bm * 32 + li) * 4 + wn * 2 + bn;
+        es.words[at] = (uint32_t)word;
+        es.bwords[at] = (uint32_t)bword;
+    }
 }
 
-// Band pairs of one block -> FP64 recheck list, appended per register row
-// that has any (wave-aggregated).  The list has one segment per persistent
-// workgroup, counted in LDS (`wg_count`); the one-workgroup-per-tile launch
-// shares the segments through global counters.
-__device__ __forceinline__ void epi_band(const TileArgs &a, const TilePos &tl, const EpiShared &es,
-                                         const f32x16 &gv, int bm, int bn, int wm, int wn,
+// The band pairs of tile row t (its band words bw) -> FP64 recheck list.  The
+// list has one segment per persistent workgroup, counted in LDS (`wg_count`);
+// the one-workgroup-per-tile launch shares the segments through global
+// counters.
+__device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw,
                                          unsigned int *wg_count) {
-    const int lane = lane_id_here();
-    const int li = lane & 31, lg = lane >> 5;
-    const bool diag = tl.I == tl.J;
-    const int cl = wn * 64 + bn * 32 + li;
-    const int64_t gc = (int64_t)tl.J * TILE + cl;
-    const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
-    const int r0 = wm * 64 + bm * 32 + 4 * lg;
+    const int n = __popc(bw.x) + __popc(bw.y) + __popc(bw.z) + __popc(bw.w);
     const int seg = wg_count ? (int)blockIdx.x : (int)(blockIdx.x % (unsigned)a.nseg);
-    const uint64_t lt = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int rl = r0 + 8 * (v >> 2) + (v & 3);
-        const int64_t gr = (int64_t)tl.I * TILE + rl;
-        const float g = gv[v];
-        const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
-        const bool self = diag && rl == cl;
-        const bool in = valid && (self || g >= es.thrA[rl] + Aj);
-        const bool band = valid && !in && !(g < es.thrB[rl] + Bj);
-        const uint64_t bb = __ballot(band);
-        if (bb == 0) continue;
-        uint32_t base = 0;
-        if (lane == 0)
-            base = wg_count ? atomicAdd(wg_count, (unsigned int)__popcll(bb))
-                            : (uint32_t)atomicAdd(&a.band_n[seg], (unsigned long long)__popcll(bb));
-        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-        if (band) {
-            const int64_t idx = (int64_t)base + __popcll(bb & lt);
+    int64_t idx = wg_count ? (int64_t)atomicAdd(wg_count, (unsigned int)n)
+                           : (int64_t)atomicAdd(&a.band_n[seg], (unsigned long long)n);
+    const int64_t gr = (int64_t)tl.I * TILE + t;
+    for (int j = 0; j < 4; ++j) {
+        uint32_t m = bw[j];
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
             if (idx < a.band_cap) {
+                const int cl = 32 * j + b;
                 BandPair bp;
                 bp.si = (int32_t)(tl.slot0 + gr);
-                bp.sj = (int32_t)(tl.slot0 + gc);
-                bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(rl * 4 + (cl >> 5))) * 32u
-                         + (uint64_t)(cl & 31);
+                bp.sj = (int32_t)(tl.slot0 + (int64_t)tl.J * TILE + cl);
+                bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(t * 4 + j)) * 32u + (uint64_t)b;
                 a.band[(int64_t)seg * a.band_cap + idx] = bp;
             }
+            ++idx;
         }
     }
 }
@@ -377,34 +365,27 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
     }
     const bool diag = tl.I == tl.J;
     const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
-    unsigned hb = 0;                                        // blocks with band pairs
     int colc0 = 0, colc1 = 0;
     if (!DEBUG && full) {
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
             const int bm = blk >> 1, bn = blk & 1;
-            if (epi_block<true, false>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0))
-                hb |= 1u << blk;
+            epi_block<true, false>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0);
         }
     } else {                                                // diagonal or ragged tiles (few): one copy
 #pragma unroll 1
         for (int blk = 0; blk < 4; ++blk) {
             const int bm = blk >> 1, bn = blk & 1;
             int cc = 0;
-            if (epi_block<false, DEBUG>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc)) hb |= 1u << blk;
+            epi_block<false, DEBUG>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc);
             if (bn) colc1 += cc;
             else colc0 += cc;
         }
     }
     {
         const int lane = lane_id_here();
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = colc0;
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = colc1;
-    }
-    if (hb) {
-#pragma unroll 1
-        for (int blk = 0; blk < 4; ++blk)
-            if ((hb >> blk) & 1u) epi_band(a, tl, es, acc_block(acc, blk), blk >> 1, blk & 1, wm, wn, wg_count);
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = (uint8_t)colc0;
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = (uint8_t)colc1;
     }
     lds_barrier();
     {
@@ -416,10 +397,12 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
             const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
             const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
             if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
+            const u32x4 bw = *(const u32x4 *)(es.bwords + 4 * t);
+            if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw, wg_count);
         } else {
             const int cc = t - TILE;
             const int64_t gc = (int64_t)tl.J * TILE + cc;
-            const int c = es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
+            const int c = (int)es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
             if (gc < tl.ne && c) atomicAdd(&a.count[tl.slot0 + gc], c);
         }
     }
@@ -710,83 +693,6 @@ __global__ void __launch_bounds__(NT, 2) k_tiles_ring(TileArgs a) {
     if (threadIdx.x == 0) a.band_n[blockIdx.x] = band_used;
 }
 
-// FP64 re-decision of band pairs, one pair per wave at a time.  The lanes
-// read the two rows with coalesced loads and sum (x_j - y_j)^2 in FP64 as a
-// tree; that value is within 2 gamma_{d+4} D of the canonical sequential
-// chain, so only pairs closer than that to eps^2 (ties, in practice) need
-// the canonical chain itself, which lane 0 then evaluates in order.
-__global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg,
-                                                 int64_t band_cap, int64_t nband, const float *X,
-                                                 int32_t d, const uint32_t *slot_point, double E,
-                                                 uint32_t *bitmask, int32_t *count) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-    const double u = 0x1.0p-53;
-    const double gd = (d + 4) * u / (1.0 - (d + 4) * u);
-    const double cf = 4.0 * gd / (1.0 - gd);              // twice the certified gap, for margin
-    for (int64_t b = wid; b < nband; b += nw) {
-        int lo = 0, hi = nseg;                              // segment g: seg_start[g] <= b < seg_start[g + 1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (seg_start[mid] <= b) lo = mid;
-            else hi = mid;
-        }
-        const BandPair bp = band[(int64_t)lo * band_cap + (b - seg_start[lo])];
-        const float *x = X + (int64_t)slot_point[bp.si] * d;
-        const float *y = X + (int64_t)slot_point[bp.sj] * d;
-        double part = 0.0;
-        for (int32_t j = lane; j < d; j += WAVE) {
-            const double t = (double)x[j] - (double)y[j];
-            part = __builtin_fma(t, t, part);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
-        bool in;
-        if (fabs(part - E) > cf * part) {
-            in = part <= E;
-        } else {
-            double D = 0.0;                                 // canonical chain, in order
-            if (lane == 0)
-                for (int32_t j = 0; j < d; ++j) {
-                    const double t = (double)x[j] - (double)y[j];
-                    D = __builtin_fma(t, t, D);
-                }
-            D = __shfl(D, 0, WAVE);
-            in = D <= E;
-        }
-        if (in && lane == 0) {
-            atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
-            atomicAdd(&count[bp.si], 1);
-            atomicAdd(&count[bp.sj], 1);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np,
-                                                  const float *X, int32_t d, double *out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np) return;
-    const float *x = X + (int64_t)pa[t] * d;
-    const float *y = X + (int64_t)pb[t] * d;
-    double D = 0.0;
-    for (int32_t j = 0; j < d; ++j) {
-        const double u = (double)x[j] - (double)y[j];
-        D = __builtin_fma(u, u, D);
-    }
-    out[t] = D;
-}
-
-__global__ void __launch_bounds__(256) k_row_norm2(const int32_t *rows, int64_t nr, const float *X,
-                                                   int32_t d, double *out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nr) return;
-    const float *x = X + (int64_t)rows[t] * d;
-    double s = 0.0;
-    for (int32_t j = 0; j < d; ++j) s += (double)x[j] * (double)x[j];
-    out[t] = s;
-}
-
 __global__ void k_build_items(TileTable tt, TileItem *items) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= tt.n_items) return;
@@ -835,31 +741,6 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s) {
     if (tt.n_items <= 0) return hipSuccess;
     k_build_items<<<dim3((unsigned)((tt.n_items + 255) / 256)), dim3(256), 0, s>>>(tt, items);
-    return hipGetLastError();
-}
-
-hipError_t launch_recheck(const BandPair *band, const int64_t *seg_start, int32_t nseg, int64_t band_cap,
-                          int64_t nband, const float *X, int32_t d, const uint32_t *slot_point, double E,
-                          uint32_t *bitmask, int32_t *count, hipStream_t s) {
-    if (nband <= 0) return hipSuccess;
-    int64_t blocks = (nband + 3) / 4;
-    if (blocks > 32768) blocks = 32768;
-    k_recheck<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(band, seg_start, nseg, band_cap, nband, X, d,
-                                                           slot_point, E, bitmask, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
-                            double *out, hipStream_t s) {
-    if (nr <= 0) return hipSuccess;
-    k_row_norm2<<<dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s>>>(rows, nr, X, d, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, const float *X,
-                           int32_t d, double *out, hipStream_t s) {
-    if (np <= 0) return hipSuccess;
-    k_pair_d64<<<dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s>>>(pa, pb, np, X, d, out);
     return hipGetLastError();
 }
 

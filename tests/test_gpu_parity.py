@@ -214,9 +214,9 @@ def test_tile_distances(ctx, prec, data):
                                   synth.PREC_FP16, synth.PREC_FP16X3])
 @pytest.mark.parametrize("load", ["grid2d_d128", "d256", "d40"])
 def test_persistent_matches_grid_launch(ctx, prec, load):
-    """The persistent LDS-ring launch (default) and the one-workgroup-per-tile
-    launch give the same graph (and the oracle's): ragged elements, 2-D
-    covers, widths that are and are not multiples of the slab."""
+    """The persistent LDS-ring launch and the one-workgroup-per-tile launch
+    give the same graph (and the oracle's): ragged elements, 2-D covers,
+    widths that are and are not multiples of the slab."""
     from paper_2011_03209_amd import binding
     if load == "grid2d_d128":
         w = synth.mixture_500k_d128_2d(scale=0.01, precision=prec)
@@ -228,7 +228,7 @@ def test_persistent_matches_grid_launch(ctx, prec, load):
         w.params.precision = prec
     cloud = ctx.cloud(w.X)
     try:
-        gp = cloud.run(w.params)
+        gp = cloud.run(w.params, flags=binding.FLAG_TILE_PERSISTENT)
         gg = cloud.run(w.params, flags=binding.FLAG_TILE_PER_WORKGROUP)
     finally:
         cloud.destroy()
@@ -248,7 +248,7 @@ def test_band_list_regrows(ctx, per_tile):
                           min_pts=w.params.min_pts, precision=synth.PREC_BF16)
     cloud = ctx.cloud(w.X)
     try:
-        g = cloud.run(params, flags=binding.FLAG_TILE_PER_WORKGROUP if per_tile else 0)
+        g = cloud.run(params, flags=binding.FLAG_TILE_PER_WORKGROUP if per_tile else binding.FLAG_TILE_PERSISTENT)
     finally:
         cloud.destroy()
     assert g.stats["tile_launches"] > 1, g.stats
