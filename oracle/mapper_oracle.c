@@ -493,6 +493,24 @@ int orc_mapper(const float *X, int64_t n, int32_t d, int32_t n_axes,
     return 0;
 }
 
+/* Squared distances of all ordered pairs of the given rows (m x m, row-major),
+ * each by the canonical chain (the DBSCAN neighbour routine above), rows in
+ * parallel.  For the band-soundness tests of the GPU tiles. */
+int orc_all_d2(const float *X, int64_t n, int32_t d, const int32_t *rows, int64_t m, double *out)
+{
+    if (!X || !rows || !out || m < 0 || d < 1) return ORC_EINVAL;
+    for (int64_t k = 0; k < m; ++k)
+        if (rows[k] < 0 || rows[k] >= n) return ORC_EINVAL;
+    double *XT = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (size_t)d);
+    if (!XT) return ORC_ENOMEM;
+    for (int64_t k = 0; k < m; ++k)
+        for (int32_t j = 0; j < d; ++j) XT[(int64_t)j * m + k] = (double)X[(int64_t)rows[k] * d + j];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t a = 0; a < m; ++a) row_d2(XT, m, d, a, 0, m, out + a * m);
+    free(XT);
+    return 0;
+}
+
 /* Squared distance of one pair by the canonical chain (for pins and for the
  * tolerance tests of the GPU tiles). */
 double orc_pair_d2(const float *x, const float *y, int32_t d)

@@ -88,6 +88,9 @@ def lib():
         L.orc_pair_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                   ctypes.c_int32]
         L.orc_pair_d2.restype = ctypes.c_double
+        L.orc_all_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+        L.orc_all_d2.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -241,3 +244,15 @@ def pair_d2(x: np.ndarray, y: np.ndarray) -> float:
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
     return float(lib().orc_pair_d2(_p(x, ctypes.c_float), _p(y, ctypes.c_float), x.shape[0]))
+
+
+def all_d2(X: np.ndarray, rows) -> np.ndarray:
+    """Canonical squared distances of all ordered pairs of X[rows] (m x m)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.empty((r.shape[0], r.shape[0]), np.float64)
+    rc = lib().orc_all_d2(_p(X, ctypes.c_float), X.shape[0], X.shape[1], _p(r, ctypes.c_int32), r.shape[0],
+                          _p(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"orc_all_d2 failed ({rc})")
+    return out

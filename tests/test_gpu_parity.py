@@ -173,12 +173,7 @@ def test_dyadic_ties(ctx, seed):
 
 
 def _d64(X, rows):
-    m = len(rows)
-    out = np.zeros((m, m))
-    for i in range(m):
-        for j in range(m):
-            out[i, j] = O.pair_d2(X[rows[i]], X[rows[j]])
-    return out
+    return O.all_d2(X, rows)
 
 
 @pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
@@ -208,6 +203,34 @@ def test_tile_distances(ctx, prec, data):
     assert np.all(err <= band), float((err - band).max())
     if prec == synth.PREC_FP32:
         assert np.all(err <= 1e-5 * (nrm[:, None] + nrm[None, :]))
+
+
+@pytest.fixture(scope="module")
+def large_cloud():
+    """10,000 points of a 256-D mixture with a large common offset on a
+    quarter of them (large |x|), and their exact pairwise distances."""
+    rng = np.random.default_rng(21)
+    X, _ = synth.gaussian_mixture(rng, 10_000, 256, 12)
+    X[:2500] += np.float32(40.0)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    rows = np.arange(X.shape[0], dtype=np.int32)
+    return X, rows, _d64(X, rows)
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
+                                  synth.PREC_FP16, synth.PREC_FP16X3])
+def test_tile_band_soundness_1e8_pairs(ctx, large_cloud, prec):
+    """Band soundness on 1e8 ordered pairs per precision: every tile distance
+    lies within its certified band of the exact FP64 distance."""
+    X, rows, ref = large_cloud
+    cloud = ctx.cloud(X)
+    try:
+        d2, band = cloud.tile_d2(rows, prec, eps=20.0)
+    finally:
+        cloud.destroy()
+    assert d2.shape == ref.shape == (10_000, 10_000)
+    over = np.abs(d2 - ref) - band
+    assert float(over.max()) <= 0.0, float(over.max())
 
 
 @pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
