@@ -123,6 +123,15 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(_P(ctypes.c_double))
 
 
+def _check_axes(params, n: int, d: int):
+    """The C ABI reads d direction floats and n lens values: check the sizes here."""
+    for ax in params.axes:
+        if ax.direction is not None and np.asarray(ax.direction).size != d:
+            raise ValueError(f"projection direction has {np.asarray(ax.direction).size} values, cloud d = {d}")
+        if ax.values is not None and np.asarray(ax.values).size != n:
+            raise ValueError(f"lens values have {np.asarray(ax.values).size} entries, cloud n = {n}")
+
+
 def make_params(params, flags: int = 0, keep: Optional[list] = None) -> _Params:
     """C struct for a synth.Params-like object (axes, eps, min_pts, precision)."""
     if keep is None:
@@ -275,6 +284,7 @@ class Cloud:
             self.h = None
 
     def run(self, params, debug: bool = False, flags: int = 0) -> Graph:
+        _check_axes(params, self.n, self.d)
         keep: list = []
         p = make_params(params, flags | (FLAG_DEBUG_STAGES if debug else 0), keep)
         g = _vp()
@@ -282,6 +292,7 @@ class Cloud:
         return _take_graph(g)
 
     def submit(self, params, debug: bool = False) -> int:
+        _check_axes(params, self.n, self.d)
         keep: list = []
         p = make_params(params, FLAG_DEBUG_STAGES if debug else 0, keep)
         t = ctypes.c_uint64(0)

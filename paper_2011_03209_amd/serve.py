@@ -57,9 +57,12 @@ def run(n_requests=256, slots=3, arena_gb=96.0, scale=1.0, fractions=(0.25, 0.5,
     clouds = [ctx.cloud(X) for X in raw]
     print(f"[serve] {len(clouds)} clouds resident", file=log, flush=True)
     base = synth.serving_requests(raw, n_requests, qps=1.0, precision=precision)
-    # warm-up: one request per cloud
-    for c in range(len(clouds)):
-        clouds[c].run(base[c][2])
+    # warm-up: the first request of each cloud
+    seen = set()
+    for _, c, p in base:
+        if c not in seen:
+            seen.add(c)
+            clouds[c].run(p)
     # saturation: everything at t = 0
     sat = [(0.0, c, p) for (_, c, p) in base]
     t0 = time.perf_counter()
