@@ -42,7 +42,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int NT = 256;              // threads per workgroup
+constexpr int NT = 256;              // threads per workgroup, persistent ring form (4 waves)
+constexpr int NTG = 512;             // threads per workgroup, one-tile-per-workgroup form (8 waves)
 
 template <int PREC> struct Cfg;
 template <> struct Cfg<P_FP32>   { static constexpr int ESZ = 4, KC = 32, PANELS = 1; };
@@ -56,7 +57,7 @@ template <int PREC> struct Lay {
     static constexpr int CPR = RB / 16;                         // 16-byte chunks per row
     static constexpr int PANEL_BYTES = TILE * RB;                // one operand panel
     static constexpr int STAGE_BYTES = 2 * Cfg<PREC>::PANELS * PANEL_BYTES;   // A and B
-    static constexpr int CPT = TILE * CPR / NT;                  // chunks per thread per panel
+    static constexpr int CPT = TILE * CPR / NTG;                 // chunks per thread per panel
     static constexpr int NREG = 2 * Cfg<PREC>::PANELS * CPT;
 };
 
@@ -103,7 +104,7 @@ __device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl,
                 (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride + pnl * 32;
 #pragma unroll
         for (int q = 0; q < L::CPT; ++q) {
-            const int idx = q * NT + threadIdx.x;
+            const int idx = q * NTG + threadIdx.x;
             const int r = idx / L::CPR, c = idx % L::CPR;
             const int rr = r < nrow ? r : (int)(nrow - 1);
             const int coff = SPLIT ? (c >> 1) * 64 + (c & 1) * 16 : c * 16;
@@ -112,7 +113,7 @@ __device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl,
     }
 #pragma unroll
     for (int q = 0; q < L::CPT; ++q) {
-        const int idx = q * NT + threadIdx.x;
+        const int idx = q * NTG + threadIdx.x;
         f.dst[q] = loff<L::CPR>(idx / L::CPR, idx % L::CPR);
     }
 }
@@ -150,15 +151,16 @@ __device__ __forceinline__ int lane_id_here() {
     return l;
 }
 
-template <int PREC> struct Acc {
-    f32x16 c[2][2];
-    f32x16 x[2][2];   // cross-term accumulator of hi/lo splits
+// A wave's accumulators: 2 x BN blocks of 32 x 32 (64 x 32 BN pairs).
+template <int PREC, int BN> struct Acc {
+    f32x16 c[2][BN];
+    f32x16 x[2][BN];   // cross-term accumulator of hi/lo splits
 };
 
 // FIRST: the first slab, whose products start the accumulators (MFMA with a
 // zero addend, so the accumulators need no clearing).
 template <int PREC, bool FIRST>
-__device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc, int wm, int wn) {
+__device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC, 1> &acc, int wm, int wn) {
     using L = Lay<PREC>;
     const f32x16 zero = {};
     constexpr int CPR = L::CPR;
@@ -171,20 +173,17 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
         // lane group g supplies k = 8 ss + 4 g + t for both operands
 #pragma unroll
         for (int ss = 0; ss < Cfg<PREC>::KC / 8; ++ss) {
-            f32x4 av[2], bv[2];
+            f32x4 av[2], bv;
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < 2; ++b)
                 av[b] = *(const f32x4 *)(Ah + loff<CPR>(wm * 64 + b * 32 + li, 2 * ss + lg));
-                bv[b] = *(const f32x4 *)(Bh + loff<CPR>(wn * 64 + b * 32 + li, 2 * ss + lg));
-            }
+            bv = *(const f32x4 *)(Bh + loff<CPR>(wn * 32 + li, 2 * ss + lg));
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-                    for (int bn = 0; bn < 2; ++bn)
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                            av[bm][t], bv[bn][t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][bn], 0, 0, 0);
+                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                        av[bm][t], bv[t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][0], 0, 0, 0);
         }
     } else {
         constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
@@ -192,23 +191,23 @@ __device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC> &acc,
         const char *Bl = Bh + L::PANEL_BYTES;
 #pragma unroll
         for (int ks = 0; ks < Cfg<PREC>::KC / 16; ++ks) {
-            u32x4 ah[2], bh[2], al[2], bl[2];
+            u32x4 ah[2], bh[1], al[2], bl[1];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int oa = loff<CPR>(wm * 64 + b * 32 + li, 2 * ks + lg);
-                const int ob = loff<CPR>(wn * 64 + b * 32 + li, 2 * ks + lg);
                 ah[b] = *(const u32x4 *)(Ah + oa);
-                bh[b] = *(const u32x4 *)(Bh + ob);
-                if constexpr (SPLIT) {
-                    al[b] = *(const u32x4 *)(Al + oa);
-                    bl[b] = *(const u32x4 *)(Bl + ob);
-                }
+                if constexpr (SPLIT) al[b] = *(const u32x4 *)(Al + oa);
+            }
+            {
+                const int ob = loff<CPR>(wn * 32 + li, 2 * ks + lg);
+                bh[0] = *(const u32x4 *)(Bh + ob);
+                if constexpr (SPLIT) bl[0] = *(const u32x4 *)(Bl + ob);
             }
             const bool z0 = FIRST && ks == 0;
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
+                for (int bn = 0; bn < 1; ++bn) {
                     if constexpr (PREC == P_BF16 || PREC == P_BF16X3) {
                         acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
@@ -251,13 +250,13 @@ struct EpiShared {
 // gv): the row words of its bitmask and of its band pairs go to LDS, and the
 // lane's column count is added to colc.  FULL: the block lies inside the
 // element and off the diagonal, so no bounds or triangle masks are needed.
-template <bool FULL, bool DEBUG>
+template <bool FULL, bool DEBUG, int BN>
 __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
                                           const f32x16 &gv, int bm, int bn, int wm, int wn, int &colc) {
     const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
-    const int cl = wn * 64 + bn * 32 + li;                  // column within the tile
+    const int cl = (wn * BN + bn) * 32 + li;                // column within the tile
     const int64_t gc = (int64_t)tl.J * TILE + cl;          // element-local column
     const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
     const int r0 = wm * 64 + bm * 32 + 4 * lg;             // register v holds row r0 + 8(v/4) + v%4
@@ -302,7 +301,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         }
     }
     if (lane < 32) {
-        const int at = (wm * 64 + bm * 32 + li) * 4 + wn * 2 + bn;
+        const int at = (wm * 64 + bm * 32 + li) * 4 + wn * BN + bn;
         es.words[at] = (uint32_t)word;
         es.bwords[at] = (uint32_t)bword;
     }
@@ -337,13 +336,17 @@ __device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl
     }
 }
 
-// The Gram values of accumulator block blk = 2 bm + bn (blk wave-uniform).
-template <int PREC>
-__device__ __forceinline__ f32x16 acc_block(const Acc<PREC> &acc, int blk) {
+// The Gram values of accumulator block blk = BN bm + bn (blk wave-uniform).
+template <int PREC, int BN>
+__device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
     f32x16 r = acc.c[0][0];
-    if (blk == 1) r = acc.c[0][1];
-    else if (blk == 2) r = acc.c[1][0];
-    else if (blk == 3) r = acc.c[1][1];
+    if constexpr (BN == 1) {
+        if (blk == 1) r = acc.c[1][0];
+    } else {
+        if (blk == 1) r = acc.c[0][1];
+        else if (blk == 2) r = acc.c[1][0];
+        else if (blk == 3) r = acc.c[1][1];
+    }
     return r;
 }
 
@@ -351,46 +354,46 @@ __device__ __forceinline__ f32x16 acc_block(const Acc<PREC> &acc, int blk) {
 // complete, global memory operations may still be in flight.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Decisions of the tile's four accumulator blocks per wave, then (after a
-// barrier) the 2 KB bitmask block and the neighbour counts: a row's count is
-// the popcount of its four words, a column's the sum of its partials.
-template <int PREC, bool DEBUG>
-__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC> &acc,
+// Decisions of the wave's 2 x BN accumulator blocks, then (after a barrier)
+// the 2 KB bitmask block and the neighbour counts: a row's count is the
+// popcount of its four words, a column's the sum of its partials.
+template <int PREC, bool DEBUG, int BN>
+__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC, BN> &acc,
                                               EpiShared &es, int wm, int wn, unsigned int *wg_count) {
     if constexpr (Cfg<PREC>::PANELS == 2) {                 // Gram value = hi.hi + cross terms
 #pragma unroll
         for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
-            for (int bn = 0; bn < 2; ++bn) acc.c[bm][bn] = acc.c[bm][bn] + acc.x[bm][bn];
+            for (int bn = 0; bn < BN; ++bn) acc.c[bm][bn] = acc.c[bm][bn] + acc.x[bm][bn];
     }
     const bool diag = tl.I == tl.J;
     const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
     int colc0 = 0, colc1 = 0;
     if (!DEBUG && full) {
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) {
-            const int bm = blk >> 1, bn = blk & 1;
-            epi_block<true, false>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0);
+        for (int blk = 0; blk < 2 * BN; ++blk) {
+            const int bm = blk / BN, bn = blk % BN;
+            epi_block<true, false, BN>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0);
         }
     } else {                                                // diagonal or ragged tiles (few): one copy
 #pragma unroll 1
-        for (int blk = 0; blk < 4; ++blk) {
-            const int bm = blk >> 1, bn = blk & 1;
+        for (int blk = 0; blk < 2 * BN; ++blk) {
+            const int bm = blk / BN, bn = blk % BN;
             int cc = 0;
-            epi_block<false, DEBUG>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc);
+            epi_block<false, DEBUG, BN>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc);
             if (bn) colc1 += cc;
             else colc0 += cc;
         }
     }
     {
         const int lane = lane_id_here();
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + (lane & 31)] = (uint8_t)colc0;
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = (uint8_t)colc1;
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 32 * BN + (lane & 31)] = (uint8_t)colc0;
+        if constexpr (BN == 2) es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = (uint8_t)colc1;
     }
     lds_barrier();
-    {
+    const int t = (threadIdx.x & ~(WAVE - 1)) + lane_id_here();
+    if (t < 2 * TILE) {
         uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
-        const int t = (threadIdx.x & ~(WAVE - 1)) + lane_id_here();
         *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
         if (t < TILE) {
             const int64_t r = (int64_t)tl.I * TILE + t;
@@ -408,11 +411,13 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
     }
 }
 
+// One tile pair by eight waves: wave (wm, wn) owns rows 64 wm .. + 63 and
+// columns 32 wn .. + 31 (two 32 x 32 accumulator blocks).
 template <int PREC, bool DEBUG>
 __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared &es) {
     using L = Lay<PREC>;
-    const int w = threadIdx.x / WAVE;
-    const int wm = w >> 1, wn = w & 1;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int wm = w >> 2, wn = w & 3;
 
     // K loop: double-buffered LDS slabs, the next slab's global loads in
     // flight while the current one feeds the matrix cores
@@ -422,7 +427,7 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
     u32x4 reg[L::NREG];
     gload<PREC>(feed, 0, reg);
     // thresholds of the tile's rows and columns (read in the epilogue)
-    {
+    if (threadIdx.x < 2 * TILE) {
         const int t = threadIdx.x;
         const int64_t rb = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
         const int64_t slot = tl.slot0 + (rb < tl.ne ? rb : tl.ne - 1);
@@ -432,7 +437,7 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
     }
     lstore<PREC>(stages, feed, reg);
     __syncthreads();
-    Acc<PREC> acc;
+    Acc<PREC, 1> acc;
     if (nst > 1) gload<PREC>(feed, slab_gbytes<PREC>(), reg);
     compute_stage<PREC, true>(stages, acc, wm, wn);
     if (nst > 1) lstore<PREC>(stages + L::STAGE_BYTES, feed, reg);
@@ -444,11 +449,11 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
         if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, feed, reg);
         __syncthreads();
     }
-    tile_epilogue<PREC, DEBUG>(a, tl, acc, es, wm, wn, nullptr);
+    tile_epilogue<PREC, DEBUG, 1>(a, tl, acc, es, wm, wn, nullptr);
 }
 
 template <int PREC, bool DEBUG>
-__global__ void __launch_bounds__(NT, 2) k_tiles(TileArgs a) {
+__global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
     __shared__ EpiShared es;
     // XCD-aware order: the hardware deals workgroups round-robin to the 8
@@ -501,7 +506,7 @@ __device__ __forceinline__ int roff(int r, int c) { return r * RROW + ((c ^ rswz
 // FP32 values 4c..4c+3; BF16/FP16 values 8c..8c+7; hi/lo splits the hi
 // (c = 0, 1) or lo (c = 2, 3) halves of values 8(c%2)..8(c%2)+7.
 template <int PREC, bool FIRST>
-__device__ __forceinline__ void ring_compute(const char *slab, Acc<PREC> &acc, int wm, int wn) {
+__device__ __forceinline__ void ring_compute(const char *slab, Acc<PREC, 2> &acc, int wm, int wn) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int li = lane & 31, lg = lane >> 5;
     const f32x16 zero = {};
@@ -660,7 +665,7 @@ __global__ void __launch_bounds__(NT, 2) k_tiles_ring(TileArgs a) {
     for (int i = 0; i < RNS - 1; ++i) ring_issue(feed, slot_lds(i), w);
     int pslot = RNS - 1, cslot = 0;
 
-    Acc<PREC> acc;
+    Acc<PREC, 2> acc;
 #pragma unroll 1
     for (int k = 0; k < nt; ++k) {
         const bool more = k + 1 < nt;
@@ -685,7 +690,7 @@ __global__ void __launch_bounds__(NT, 2) k_tiles_ring(TileArgs a) {
             if (s == 0) ring_compute<PREC, true>(slab, acc, wm, wn);
             else ring_compute<PREC, false>(slab, acc, wm, wn);
         }
-        tile_epilogue<PREC, false>(a, tc, acc, es[k & 1], wm, wn, &band_used);
+        tile_epilogue<PREC, false, 2>(a, tc, acc, es[k & 1], wm, wn, &band_used);
         tc = tn;
     }
     vm_wait<0>();                                           // no LDS-direct load outlives the workgroup
@@ -715,8 +720,8 @@ hipError_t launch_t(const TileArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
-    if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
-    else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NT), 0, s>>>(a);
+    if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
+    else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
     return hipGetLastError();
 }
 
