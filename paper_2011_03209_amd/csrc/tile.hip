@@ -45,102 +45,35 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 constexpr int NT = 256;              // threads per workgroup, persistent ring form (4 waves)
 constexpr int NTG = 512;             // threads per workgroup, one-tile-per-workgroup form (8 waves)
 
+// Per precision: 16-bit or FP32 panel values, one or two (hi/lo) terms.
 template <int PREC> struct Cfg;
-template <> struct Cfg<P_FP32>   { static constexpr int ESZ = 4, KC = 32, PANELS = 1; };
-template <> struct Cfg<P_BF16>   { static constexpr int ESZ = 2, KC = 64, PANELS = 1; };
-template <> struct Cfg<P_FP16>   { static constexpr int ESZ = 2, KC = 64, PANELS = 1; };
-template <> struct Cfg<P_BF16X3> { static constexpr int ESZ = 2, KC = 32, PANELS = 2; };
-template <> struct Cfg<P_FP16X3> { static constexpr int ESZ = 2, KC = 32, PANELS = 2; };
+template <> struct Cfg<P_FP32>   { static constexpr int PANELS = 1; };
+template <> struct Cfg<P_BF16>   { static constexpr int PANELS = 1; };
+template <> struct Cfg<P_FP16>   { static constexpr int PANELS = 1; };
+template <> struct Cfg<P_BF16X3> { static constexpr int PANELS = 2; };
+template <> struct Cfg<P_FP16X3> { static constexpr int PANELS = 2; };
 
-template <int PREC> struct Lay {
-    static constexpr int RB = Cfg<PREC>::KC * Cfg<PREC>::ESZ;   // bytes of a row per slab
-    static constexpr int CPR = RB / 16;                         // 16-byte chunks per row
-    static constexpr int PANEL_BYTES = TILE * RB;                // one operand panel
-    static constexpr int STAGE_BYTES = 2 * Cfg<PREC>::PANELS * PANEL_BYTES;   // A and B
-    static constexpr int CPT = TILE * CPR / NTG;                 // chunks per thread per panel
-    static constexpr int NREG = 2 * Cfg<PREC>::PANELS * CPT;
-};
-
-// LDS rows are unpadded; the 16-byte chunks of row r are permuted by an XOR
-// with swz(r).  16-byte reads of one chunk column by 8 (32-bank) or 16
-// (64-bank) consecutive rows, and writes of consecutive chunks of consecutive
-// rows, then all fall in distinct banks.
-template <int CPR> __device__ __forceinline__ int swz(int r) {
-    if constexpr (CPR == 8) return (r + (r >> 3)) & 7;
-    else return ((r >> 1) ^ (r >> 3)) & 3;
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
 }
 
-template <int CPR> __device__ __forceinline__ int loff(int r, int c) {
-    return (r * CPR + (c ^ swz<CPR>(r))) * 16;
+// LDS-direct loads: M0 holds the wave's LDS destination (set in the same
+// statement; nothing else in these kernels uses M0).  Completion is tracked
+// by hand with vmcnt: the compiler does not see these loads.
+__device__ __forceinline__ void lds_load16(uint32_t lds, const char *sbase, uint32_t voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
+                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
 }
-
-// Per-thread copy plan of one tile.  The row panels of the two sides (and of
-// the hi/lo halves of a split) start at wave-uniform addresses; a thread
-// moves chunk c of rows r_q (q < CPT) of each, found at a 32-bit offset from
-// that start.  Rows past the element are clamped to its last row (masked in
-// the epilogue).
-template <int PREC> struct Feed {
-    const char *base[2 * Cfg<PREC>::PANELS];
-    uint32_t voff[2][Lay<PREC>::CPT];
-    int dst[Lay<PREC>::CPT];
-};
-
-// Global bytes of a row consumed per slab (the hi and lo halves of a split
-// slab sit in the same 128 bytes of the interleaved row layout).
-template <int PREC> constexpr uint32_t slab_gbytes() { return Lay<PREC>::RB * Cfg<PREC>::PANELS; }
-
-template <int PREC>
-__device__ __forceinline__ void feed_setup(const TileArgs &a, const TilePos &tl, Feed<PREC> &f) {
-    using L = Lay<PREC>;
-    constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
-    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const int64_t r0 = (int64_t)(side == 0 ? tl.I : tl.J) * TILE;
-        const int64_t nrow = tl.ne - r0;
-#pragma unroll
-        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl)   // lo values: 32 bytes after their hi values
-            f.base[side * Cfg<PREC>::PANELS + pnl] =
-                (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride + pnl * 32;
-#pragma unroll
-        for (int q = 0; q < L::CPT; ++q) {
-            const int idx = q * NTG + threadIdx.x;
-            const int r = idx / L::CPR, c = idx % L::CPR;
-            const int rr = r < nrow ? r : (int)(nrow - 1);
-            const int coff = SPLIT ? (c >> 1) * 64 + (c & 1) * 16 : c * 16;
-            f.voff[side][q] = (uint32_t)rr * stride + (uint32_t)coff;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < L::CPT; ++q) {
-        const int idx = q * NTG + threadIdx.x;
-        f.dst[q] = loff<L::CPR>(idx / L::CPR, idx % L::CPR);
-    }
+__device__ __forceinline__ void lds_load4(uint32_t lds, const char *sbase, uint32_t voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, %2"
+                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
 }
+// Wait until at most N vector memory operations of this wave are in flight.
+template <int N> __device__ __forceinline__ void vm_wait() { asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory"); }
 
-template <int PREC>
-__device__ __forceinline__ void gload(const Feed<PREC> &f, uint32_t koff, u32x4 *reg) {
-    using L = Lay<PREC>;
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-        for (int pnl = 0; pnl < Cfg<PREC>::PANELS; ++pnl) {
-            const char *bk = f.base[side * Cfg<PREC>::PANELS + pnl] + koff;
-#pragma unroll
-            for (int q = 0; q < L::CPT; ++q)
-                reg[(side * Cfg<PREC>::PANELS + pnl) * L::CPT + q] = *(const u32x4 *)(bk + f.voff[side][q]);
-        }
-}
-
-template <int PREC>
-__device__ __forceinline__ void lstore(char *stage, const Feed<PREC> &f, const u32x4 *reg) {
-    using L = Lay<PREC>;
-#pragma unroll
-    for (int sp = 0; sp < 2 * Cfg<PREC>::PANELS; ++sp)
-#pragma unroll
-        for (int q = 0; q < L::CPT; ++q)
-            *(u32x4 *)(stage + sp * L::PANEL_BYTES + f.dst[q]) = reg[sp * L::CPT + q];
-}
+// Workgroup barrier over LDS traffic only: the wave's own LDS accesses are
+// complete, global memory operations may still be in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // The lane index through an empty asm: values derived from it inside a loop
 // body are recomputed there instead of being hoisted into registers that
@@ -157,84 +90,136 @@ template <int PREC, int BN> struct Acc {
     f32x16 x[2][BN];   // cross-term accumulator of hi/lo splits
 };
 
-// FIRST: the first slab, whose products start the accumulators (MFMA with a
-// zero addend, so the accumulators need no clearing).
-template <int PREC, bool FIRST>
-__device__ __forceinline__ void compute_stage(const char *stage, Acc<PREC, 1> &acc, int wm, int wn) {
-    using L = Lay<PREC>;
-    const f32x16 zero = {};
-    constexpr int CPR = L::CPR;
+// ------------------------------------------------ one tile pair per workgroup
+// A stage is 128 bytes of every row of both sides (A rows 0..127, then B
+// rows): FP32 values 32 s .. + 31, BF16/FP16 values 64 s .. + 63, or for the
+// splits two groups of 16 hi then 16 lo values, exactly as in the panel row.
+// Chunk c (16 bytes) of stage row r sits at LDS offset r 128 + 16 (c ^ swz(r))
+// with swz(r) = (r >> 1) & 7, chosen by measurement on gfx950 (bank-conflict
+// counter of a probe kernel): the operand reads, one chunk column of 32
+// consecutive rows per half-wave, are then free of bank conflicts.
+constexpr int GROW = 128;                     // bytes of a row per stage
+constexpr int GSTAGE = 2 * TILE * GROW;       // 32 KB
+
+__device__ __forceinline__ int goff(int r, int c) { return r * GROW + ((c ^ ((r >> 1) & 7)) << 4); }
+
+// LDS-direct plan of one wave for one tile: wave w fills stage rows
+// 32 w .. + 31 (side w / 4) with four 1 KB loads of 8 rows; lane l of load i
+// writes chunk position l % 8 of stage row 32 w + 8 i + l / 8, so it reads the
+// global chunk that belongs there.  Rows past the element are clamped to its
+// last row (masked in the epilogue).
+struct GridFeed {
+    const char *sbase;                        // the side's first row, stage 0
+    uint32_t vo[4];
+};
+
+__device__ __forceinline__ void grid_setup(const TileArgs &a, const TilePos &tl, int w, int lane,
+                                           uint32_t stride, GridFeed &f) {
+    const int side = w >> 2;
+    const int64_t r0 = (int64_t)(side ? tl.J : tl.I) * TILE;
+    const int64_t nrow = tl.ne - r0;                        // rows of this side in the element (>= 1)
+    f.sbase = (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int sr = (w & 3) * 32 + i * 8 + (lane >> 3);  // side row
+        const int lr = w * 32 + i * 8 + (lane >> 3);        // stage row
+        const int c = (lane & 7) ^ ((lr >> 1) & 7);
+        f.vo[i] = (uint32_t)(sr < nrow ? sr : (int)(nrow - 1)) * stride + (uint32_t)(c << 4);
+    }
+}
+
+__device__ __forceinline__ void grid_issue(const GridFeed &f, uint32_t stage_lds, int w, uint32_t koff) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds_load16(stage_lds + (uint32_t)((w * 4 + i) * 1024), f.sbase + koff, f.vo[i]);
+}
+
+// A stage's operands of one wave (rows 64 wm .. + 63 of A, 32 wn .. + 31 of B):
+//   FP32, BF16, FP16: v[3 h + b] = A block b, v[3 h + 2] = B, chunk 2 h + lane / 32;
+//   splits: v[6 ks + 2 b + l] = A block b, v[6 ks + 4 + l] = B, chunk 4 ks + 2 l + lane / 32
+//           (l = 0 hi, 1 lo).
+struct GridOps {
+    u32x4 v[12];
+};
+
+template <int PREC>
+__device__ __forceinline__ void grid_read(const char *stage, GridOps &o, int wm, int wn) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int li = lane & 31, lg = lane >> 5;
-    const char *Ah = stage;
-    const char *Bh = stage + Cfg<PREC>::PANELS * L::PANEL_BYTES;
+    const int ra0 = wm * 64 + li, ra1 = ra0 + 32, rb = TILE + wn * 32 + li;
+    if constexpr (Cfg<PREC>::PANELS == 1) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            o.v[3 * h + 0] = *(const u32x4 *)(stage + goff(ra0, 2 * h + lg));
+            o.v[3 * h + 1] = *(const u32x4 *)(stage + goff(ra1, 2 * h + lg));
+            o.v[3 * h + 2] = *(const u32x4 *)(stage + goff(rb, 2 * h + lg));
+        }
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const int c = 4 * ks + 2 * l + lg;
+                o.v[6 * ks + l] = *(const u32x4 *)(stage + goff(ra0, c));
+                o.v[6 * ks + 2 + l] = *(const u32x4 *)(stage + goff(ra1, c));
+                o.v[6 * ks + 4 + l] = *(const u32x4 *)(stage + goff(rb, c));
+            }
+    }
+}
+
+// The stage's products into the accumulators (FIRST: the tile's first stage,
+// whose products start them: a zero addend, so they need no clearing).
+template <int PREC, bool FIRST>
+__device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC, 1> &acc) {
+    const f32x16 zero = {};
     if constexpr (PREC == P_FP32) {
-        // 16 bytes = 4 k values per lane; MFMA t of a step takes element t, so
-        // lane group g supplies k = 8 ss + 4 g + t for both operands
 #pragma unroll
-        for (int ss = 0; ss < Cfg<PREC>::KC / 8; ++ss) {
-            f32x4 av[2], bv;
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                av[b] = *(const f32x4 *)(Ah + loff<CPR>(wm * 64 + b * 32 + li, 2 * ss + lg));
-            bv = *(const f32x4 *)(Bh + loff<CPR>(wn * 32 + li, 2 * ss + lg));
+        for (int h = 0; h < 4; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int bm = 0; bm < 2; ++bm)
                     acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                        av[bm][t], bv[t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][0], 0, 0, 0);
-        }
+                        __builtin_bit_cast(f32x4, o.v[3 * h + bm])[t], __builtin_bit_cast(f32x4, o.v[3 * h + 2])[t],
+                        FIRST && h == 0 && t == 0 ? zero : acc.c[bm][0], 0, 0, 0);
+    } else if constexpr (Cfg<PREC>::PANELS == 1) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) {
+                const f32x16 c = FIRST && h == 0 ? zero : acc.c[bm][0];
+                if constexpr (PREC == P_BF16)
+                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, o.v[3 * h + bm]), __builtin_bit_cast(bf16x8, o.v[3 * h + 2]), c,
+                        0, 0, 0);
+                else
+                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, o.v[3 * h + bm]), __builtin_bit_cast(f16x8, o.v[3 * h + 2]), c,
+                        0, 0, 0);
+            }
     } else {
-        constexpr bool SPLIT = Cfg<PREC>::PANELS == 2;
-        const char *Al = Ah + L::PANEL_BYTES;
-        const char *Bl = Bh + L::PANEL_BYTES;
 #pragma unroll
-        for (int ks = 0; ks < Cfg<PREC>::KC / 16; ++ks) {
-            u32x4 ah[2], bh[1], al[2], bl[1];
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int oa = loff<CPR>(wm * 64 + b * 32 + li, 2 * ks + lg);
-                ah[b] = *(const u32x4 *)(Ah + oa);
-                if constexpr (SPLIT) al[b] = *(const u32x4 *)(Al + oa);
-            }
-            {
-                const int ob = loff<CPR>(wn * 32 + li, 2 * ks + lg);
-                bh[0] = *(const u32x4 *)(Bh + ob);
-                if constexpr (SPLIT) bl[0] = *(const u32x4 *)(Bl + ob);
-            }
-            const bool z0 = FIRST && ks == 0;
-#pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-                for (int bn = 0; bn < 1; ++bn) {
-                    if constexpr (PREC == P_BF16 || PREC == P_BF16X3) {
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
-                        if constexpr (SPLIT) {
-                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bl[bn]),
-                                z0 ? zero : acc.x[bm][bn], 0, 0, 0);
-                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                __builtin_bit_cast(bf16x8, al[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                                acc.x[bm][bn], 0, 0, 0);
-                        }
-                    } else {
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
-                        if constexpr (SPLIT) {
-                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bl[bn]),
-                                z0 ? zero : acc.x[bm][bn], 0, 0, 0);
-                            acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                                __builtin_bit_cast(f16x8, al[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                                acc.x[bm][bn], 0, 0, 0);
-                        }
-                    }
+            for (int bm = 0; bm < 2; ++bm) {
+                const u32x4 ah = o.v[6 * ks + 2 * bm], al = o.v[6 * ks + 2 * bm + 1];
+                const u32x4 bh = o.v[6 * ks + 4], bl = o.v[6 * ks + 5];
+                const bool z = FIRST && ks == 0;
+                if constexpr (PREC == P_BF16X3) {
+                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh), z ? zero : acc.c[bm][0], 0, 0, 0);
+                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl), z ? zero : acc.x[bm][0], 0, 0, 0);
+                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh), acc.x[bm][0], 0, 0, 0);
+                } else {
+                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bh), z ? zero : acc.c[bm][0], 0, 0, 0);
+                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bl), z ? zero : acc.x[bm][0], 0, 0, 0);
+                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, al), __builtin_bit_cast(f16x8, bh), acc.x[bm][0], 0, 0, 0);
                 }
-        }
+            }
     }
 }
 
@@ -350,9 +335,6 @@ __device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
     return r;
 }
 
-// Workgroup barrier over LDS traffic only: the wave's own LDS accesses are
-// complete, global memory operations may still be in flight.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Decisions of the wave's 2 x BN accumulator blocks, then (after a barrier)
 // the 2 KB bitmask block and the neighbour counts: a row's count is the
@@ -412,49 +394,46 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
 }
 
 // One tile pair by eight waves: wave (wm, wn) owns rows 64 wm .. + 63 and
-// columns 32 wn .. + 31 (two 32 x 32 accumulator blocks).
+// columns 32 wn .. + 31 (two 32 x 32 accumulator blocks).  Double-buffered
+// stages filled by LDS-direct loads: the next stage loads while the current
+// one feeds the matrix cores.
 template <int PREC, bool DEBUG>
 __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared &es) {
-    using L = Lay<PREC>;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
     const int wm = w >> 2, wn = w & 3;
-
-    // K loop: double-buffered LDS slabs, the next slab's global loads in
-    // flight while the current one feeds the matrix cores
-    const int nst = a.dp / Cfg<PREC>::KC;
-    Feed<PREC> feed;
-    feed_setup<PREC>(a, tl, feed);
-    u32x4 reg[L::NREG];
-    gload<PREC>(feed, 0, reg);
+    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
+    const int nst = (int)(panel_row_bytes(PREC, a.dp) / GROW);   // >= 2
+    const uint32_t st_lds = lds_addr(stages);
+    GridFeed feed;
+    grid_setup(a, tl, w, lane, stride, feed);
+    grid_issue(feed, st_lds, w, 0);
     // thresholds of the tile's rows and columns (read in the epilogue)
     if (threadIdx.x < 2 * TILE) {
         const int t = threadIdx.x;
-        const int64_t rb = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
-        const int64_t slot = tl.slot0 + (rb < tl.ne ? rb : tl.ne - 1);
+        const int64_t rw = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
+        const int64_t slot = tl.slot0 + (rw < tl.ne ? rw : tl.ne - 1);
         const float ta = a.thrA[slot], tb = a.thrB[slot];
         es.thrA[t] = ta;
         es.thrB[t] = tb;
     }
-    lstore<PREC>(stages, feed, reg);
-    __syncthreads();
     Acc<PREC, 1> acc;
-    if (nst > 1) gload<PREC>(feed, slab_gbytes<PREC>(), reg);
-    compute_stage<PREC, true>(stages, acc, wm, wn);
-    if (nst > 1) lstore<PREC>(stages + L::STAGE_BYTES, feed, reg);
-    __syncthreads();
-    for (int st = 1; st < nst; ++st) {
-        char *cur = stages + (st & 1) * L::STAGE_BYTES;
-        if (st + 1 < nst) gload<PREC>(feed, (uint32_t)(st + 1) * slab_gbytes<PREC>(), reg);
-        compute_stage<PREC, false>(cur, acc, wm, wn);
-        if (st + 1 < nst) lstore<PREC>(stages + ((st + 1) & 1) * L::STAGE_BYTES, feed, reg);
-        __syncthreads();
+    GridOps ops;
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+        vm_wait<0>();                                       // this wave's part of stage st has landed
+        lds_barrier();                                      // ... everyone's; stage st - 1 fully read
+        if (st + 1 < nst) grid_issue(feed, st_lds + (uint32_t)(((st + 1) & 1) * GSTAGE), w, (uint32_t)(st + 1) * GROW);
+        grid_read<PREC>(stages + (st & 1) * GSTAGE, ops, wm, wn);
+        if (st == 0) grid_mfma<PREC, true>(ops, acc);
+        else grid_mfma<PREC, false>(ops, acc);
     }
     tile_epilogue<PREC, DEBUG, 1>(a, tl, acc, es, wm, wn, nullptr);
 }
 
 template <int PREC, bool DEBUG>
 __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
-    __shared__ __attribute__((aligned(16))) char stages[2 * Lay<PREC>::STAGE_BYTES];
+    __shared__ __attribute__((aligned(1024))) char stages[2 * GSTAGE];
     __shared__ EpiShared es;
     // XCD-aware order: the hardware deals workgroups round-robin to the 8
     // XCDs, so consecutive tile pairs (which share row panels) are mapped to
@@ -481,25 +460,7 @@ constexpr int RNS = 4;                        // ring slabs
 constexpr int RROW = 64;                      // bytes of a row per slab
 constexpr int RSLAB = 2 * TILE * RROW;        // 16 KB
 
-__device__ __forceinline__ uint32_t lds_addr(const void *p) {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
-}
-
-// LDS-direct loads: M0 holds the wave's LDS destination (set in the same
-// statement; nothing else in these kernels uses M0).  Completion is tracked
-// by hand with vmcnt: the compiler does not see these loads.
-__device__ __forceinline__ void lds_load16(uint32_t lds, const char *sbase, uint32_t voff) {
-    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
-                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
-}
-__device__ __forceinline__ void lds_load4(uint32_t lds, const char *sbase, uint32_t voff) {
-    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, %2"
-                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
-}
-// Wait until at most N vector memory operations of this wave are in flight.
-template <int N> __device__ __forceinline__ void vm_wait() { asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory"); }
-
-__device__ __forceinline__ int rswz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int rswz(int r) { return (r >> 2) & 3; }     // as swz<4>
 __device__ __forceinline__ int roff(int r, int c) { return r * RROW + ((c ^ rswz(r)) << 4); }
 
 // One slab of the ring through the matrix cores.  Chunk c of a row holds:
