@@ -105,9 +105,8 @@ typedef struct {
 #define MAPPER_FLAG_TILE_PER_WORKGROUP 2u  /* distance tiles: one workgroup per tile pair */
 #define MAPPER_FLAG_TILE_PERSISTENT 4u     /* distance tiles: persistent workgroups streaming
                                              tile pairs through an LDS ring.  Neither flag:
-                                             the faster form for the precision (the split
-                                             forms: one per tile pair; the others: persistent).
-                                             Both forms give the same graph. */
+                                             one workgroup per tile pair (the faster form on
+                                             MI355X).  Both forms give the same graph. */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

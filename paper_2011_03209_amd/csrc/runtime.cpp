@@ -634,9 +634,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     // tile launch shares the same segments), grown and the tiles redone if
     // a segment overflows
     // launch form of the distance tiles (both give the same graph): measured
-    // on MI355X, one workgroup per tile pair is faster for the hi/lo splits
-    // and the persistent LDS ring for the single-term precisions
-    bool per_tile = prec_is_split(prec);
+    // on MI355X, one eight-wave workgroup per tile pair is the faster for
+    // every precision; the persistent LDS ring stays available by flag
+    bool per_tile = true;
     if (P->flags & MAPPER_FLAG_TILE_PER_WORKGROUP) per_tile = true;
     if (P->flags & MAPPER_FLAG_TILE_PERSISTENT) per_tile = false;
     const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two workgroups per CU, a multiple of the 8 XCDs
