@@ -180,11 +180,6 @@ def main():
                               **{k: ss[-1][k] for k in ("ms_tiles", "ms_recheck", "ms_cc", "ms_edges",
                                                         "ms_lens", "ms_bin", "band_pairs")}}),
                   file=sys.stderr, flush=True)
-        for name, fl in (("tile-per-workgroup", binding.FLAG_TILE_PER_WORKGROUP),
-                         ("persistent", binding.FLAG_TILE_PERSISTENT)):
-            _, ts, ss = time_path(cloud, w.params, 2, 1, flags=fl)
-            print(json.dumps({"sweep": f"{name} {args.precision}", "s_per_graph": float(np.median(ts)),
-                              "ms_tiles": ss[-1]["ms_tiles"]}), file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

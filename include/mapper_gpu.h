@@ -102,11 +102,6 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
-#define MAPPER_FLAG_TILE_PER_WORKGROUP 2u  /* distance tiles: one workgroup per tile pair */
-#define MAPPER_FLAG_TILE_PERSISTENT 4u     /* distance tiles: persistent workgroups streaming
-                                             tile pairs through an LDS ring.  Neither flag:
-                                             one workgroup per tile pair (the faster form on
-                                             MI355X).  Both forms give the same graph. */
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;

@@ -20,8 +20,6 @@ LIB_PATH = os.path.join(HERE, "libmapper_gpu.so")
 MAPPER_OK, MAPPER_EINVAL, MAPPER_ENOMEM, MAPPER_EDEVICE = 0, -1, -2, -3
 MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
-FLAG_TILE_PER_WORKGROUP = 2
-FLAG_TILE_PERSISTENT = 4
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
 

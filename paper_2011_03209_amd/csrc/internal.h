@@ -199,7 +199,6 @@ struct TileArgs {
     BandPair *band; unsigned long long *band_n; int64_t band_cap; int32_t nseg;
     float *debug_g;            // non-null: write raw Gram values (debug, one element)
     int64_t debug_ld;
-    int grid;                  // > 0: persistent launch of this many workgroups (a multiple of 8)
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).

@@ -6,13 +6,18 @@ namespace mgpu {
 
 namespace {
 
-// FP64 re-decision of band pairs, one pair per wave at a time.  The lanes
-// read the two rows with coalesced loads and sum (x_j - y_j)^2 in FP64 as a
-// tree; that value is within 2 gamma_{d+4} D of the canonical sequential
-// chain, so only pairs closer than that to eps^2 (ties, in practice) need
-// the canonical chain itself, which lane 0 then evaluates in order.
-// Workgroups RECHECK_WG_PER_SEG * g .. + RECHECK_WG_PER_SEG - 1 serve band
-// segment g; their waves take the segment's pairs in turn.
+// FP64 re-decision of band pairs.  A wave takes its segment's pairs 64 at a
+// time: lane l loads pair l's record and the cloud rows of its two slots (so
+// these dependent loads cost one round trip per 64 pairs); then the wave
+// re-decides them four at a time, all lanes on each pair with the loads of
+// the four issued together.  Lane l sums (x_j - y_j)^2 over j = l, l + 64,
+// ... with an FMA chain and the wave adds the partials as a tree.  Any
+// summation order is within gamma_{d+4} D of the exact value, as is the
+// canonical chain (x_j - y_j in FP64, fma in index order), so the two are
+// within 2 gamma_{d+4} D of each other and only pairs that close to eps^2
+// (ties, in practice) need the canonical chain itself, which lane 0 then
+// evaluates.  Workgroups RECHECK_WG_PER_SEG * g .. + RECHECK_WG_PER_SEG - 1
+// serve band segment g.
 constexpr int RECHECK_WG_PER_SEG = 8;
 
 __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const unsigned long long *band_n,
@@ -28,34 +33,71 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
     const double u = 0x1.0p-53;
     const double gd = (d + 4) * u / (1.0 - (d + 4) * u);
     const double cf = 4.0 * gd / (1.0 - gd);              // twice the certified gap, for margin
-    for (int64_t b = wid; b < n; b += nw) {
-        const BandPair bp = sb[b];
-        const float *x = X + (int64_t)slot_point[bp.si] * d;
-        const float *y = X + (int64_t)slot_point[bp.sj] * d;
-        double part = 0.0;
-        for (int32_t j = lane; j < d; j += WAVE) {
-            const double t = (double)x[j] - (double)y[j];
-            part = __builtin_fma(t, t, part);
+    for (int64_t c0 = wid * WAVE; c0 < n; c0 += nw * WAVE) {
+        const int m = (int)(n - c0 < WAVE ? n - c0 : WAVE);  // pairs of this chunk
+        BandPair bp{};
+        int px = 0, py = 0;
+        if (lane < m) {
+            bp = sb[c0 + lane];
+            px = (int)slot_point[bp.si];
+            py = (int)slot_point[bp.sj];
         }
+        for (int g = 0; g < m; g += 4) {
+            const int np = m - g < 4 ? m - g : 4;
+            const float *x[4], *y[4];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
-        bool in;
-        if (fabs(part - E) > cf * part) {
-            in = part <= E;
-        } else {
-            double D = 0.0;                                 // canonical chain, in order
-            if (lane == 0)
-                for (int32_t j = 0; j < d; ++j) {
-                    const double t = (double)x[j] - (double)y[j];
-                    D = __builtin_fma(t, t, D);
+            for (int i = 0; i < 4; ++i) {
+                const int k = g + (i < np ? i : 0);          // slots past np repeat the first pair
+                x[i] = X + (int64_t)__builtin_amdgcn_readlane(px, k) * d;
+                y[i] = X + (int64_t)__builtin_amdgcn_readlane(py, k) * d;
+            }
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int j0 = 0; j0 < d; j0 += 4 * WAVE) {
+                float xv[4][4], yv[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = j0 + q * WAVE + lane;
+                    const int jj = j < d ? j : d - 1;       // in bounds; the term is dropped below
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        xv[i][q] = x[i][jj];
+                        yv[i][q] = y[i][jj];
+                    }
                 }
-            D = __shfl(D, 0, WAVE);
-            in = D <= E;
-        }
-        if (in && lane == 0) {
-            atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
-            atomicAdd(&count[bp.si], 1);
-            atomicAdd(&count[bp.sj], 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool live = j0 + q * WAVE + lane < d;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const double t = live ? (double)xv[i][q] - (double)yv[i][q] : 0.0;
+                        s[i] = __builtin_fma(t, t, s[i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], o, WAVE);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < np) {
+                    bool in = s[i] <= E;
+                    if (fabs(s[i] - E) <= cf * s[i]) {      // a near-tie: the canonical chain decides
+                        double D = 0.0;
+                        if (lane == 0)
+                            for (int32_t j = 0; j < d; ++j) {
+                                const double t = (double)x[i][j] - (double)y[i][j];
+                                D = __builtin_fma(t, t, D);
+                            }
+                        in = __shfl(D, 0, WAVE) <= E;
+                    }
+                    if (in && lane == g + i) {               // the lane holding the pair's record
+                        atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
+                        atomicAdd(&count[bp.si], 1);
+                        atomicAdd(&count[bp.sj], 1);
+                    }
+                }
+            }
         }
     }
 }

@@ -388,11 +388,14 @@ int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneS
         gam(K16 + 2) * 0.5 + std::ldexp(1.0, -12) * 0.67,             // FP16
         gam(K16 + 2) * 0.5 + gam(2 * K16 + 2) * std::ldexp(1.0, -11) + std::ldexp(1.0, -24) * 3, // FP16X3
     };
-    // issued matrix-core seconds per pair (peak FLOP rates, 2 flops per MAC)
+    // issued matrix-core seconds per pair (peak FLOP rates, 2 flops per MAC),
+    // and the fraction of peak each precision's tile kernel reaches (measured
+    // on MI355X at 1M x 256: the 16-bit kernels are bound by the chip's power
+    // limit, not by the matrix cores)
     const double mfma[5] = {2 * K32 / 157e12, 2 * K16 / 2.5e15, 6 * K16 / 2.5e15,
                             2 * K16 / 2.5e15, 6 * K16 / 2.5e15};
-    const double eff[5] = {0.7, 0.45, 0.5, 0.45, 0.5};
-    const double recheck = 2.0 * d * 4.0 / 1.5e12 + 2.0 * d / 20e12;   // gather two rows + FP64 chain
+    const double eff[5] = {0.8, 0.18, 0.41, 0.22, 0.39};
+    const double recheck = 2.0 * d * 4.0 / 6.5e12;          // per band pair: gather of two FP32 rows
     int best = P_FP32;
     double tbest = 1e300;
     for (int p = 0; p < 5; ++p) {
@@ -630,16 +633,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int32_t *count = mem.get<int32_t>(Sa);
     uint32_t *bitmask = mem.get<uint32_t>((uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS);
     st.bitmask_bytes = nblocks * TILE_WORDS * 4;
-    // band list: one segment per persistent workgroup (the one-workgroup-per-
-    // tile launch shares the same segments), grown and the tiles redone if
-    // a segment overflows
-    // launch form of the distance tiles (both give the same graph): measured
-    // on MI355X, one eight-wave workgroup per tile pair is the faster for
-    // every precision; the persistent LDS ring stays available by flag
-    bool per_tile = true;
-    if (P->flags & MAPPER_FLAG_TILE_PER_WORKGROUP) per_tile = true;
-    if (P->flags & MAPPER_FLAG_TILE_PERSISTENT) per_tile = false;
-    const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two workgroups per CU, a multiple of the 8 XCDs
+    // band list: nseg segments, a tile's pairs going to segment blockIdx %
+    // nseg; grown and the tiles redone if a segment overflows
+    const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two per CU, a multiple of the 8 XCDs
     unsigned long long *band_n = mem.get<unsigned long long>(nseg);
     int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
     band_cap = std::max<int64_t>(band_cap, 1024);
@@ -660,7 +656,6 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         HIPCHK(hipMemsetAsync(count, 0, (size_t)Sa * 4, s));
         HIPCHK(hipMemsetAsync(band_n, 0, (size_t)nseg * 8, s));
         TileArgs ta{};
-        ta.grid = per_tile ? 0 : nseg;
         ta.tt = tt;
         ta.panel = panel;
         ta.dp = dp;

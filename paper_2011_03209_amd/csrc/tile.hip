@@ -15,17 +15,16 @@
 // canonical FP64 distance by k_recheck, so the bitmask is exact whatever the
 // tile precision.
 //
-// Layout: a workgroup of 4 waves owns one tile pair; wave (wm, wn) owns the
-// 64 x 64 quadrant as 2 x 2 blocks of 32 x 32 accumulators.  K runs over
-// double-buffered LDS slabs of 128 bytes (64 bytes per panel for hi/lo
-// splits) per row, rows padded by 16 bytes so 16-byte fragment reads from 8
-// consecutive rows hit distinct banks.  In a 32x32 accumulator lane l holds
-// column l%32 of rows 8(v/4) + 4(l/32) + v%4 (v = 0..15), so a ballot of
-// register v yields two 32-bit row words of the bitmask directly.
+// Layout: a workgroup of 8 waves owns one tile pair; wave (wm, wn) owns rows
+// 64 wm .. + 63 and columns 32 wn .. + 31 as 2 x 1 blocks of 32 x 32
+// accumulators.  K runs over double-buffered LDS stages filled by LDS-direct
+// loads.  In a 32x32 accumulator lane l holds column l%32 of rows
+// 8(v/4) + 4(l/32) + v%4 (v = 0..15), so a ballot of register v yields two
+// 32-bit row words of the bitmask directly.
 //
 // Bitmask: one 128 x 128-bit block (128 rows x 4 words) per tile pair, in the
-// element's pair order p = J(J+1)/2 + I; bit (r, c) means pair
-// (I*128 + r, J*128 + c) are neighbours.  Diagonal blocks keep only r <= c,
+// element's supertile order; bit (r, c) means pair (I*128 + r, J*128 + c) are
+// neighbours.  Diagonal blocks keep only r <= c,
 // so every unordered pair is stored once.
 #include "internal.h"
 
@@ -42,8 +41,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int NT = 256;              // threads per workgroup, persistent ring form (4 waves)
-constexpr int NTG = 512;             // threads per workgroup, one-tile-per-workgroup form (8 waves)
+constexpr int NTG = 512;             // threads per workgroup (8 waves)
 
 // Per precision: 16-bit or FP32 panel values, one or two (hi/lo) terms.
 template <int PREC> struct Cfg;
@@ -62,10 +60,6 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p) {
 // by hand with vmcnt: the compiler does not see these loads.
 __device__ __forceinline__ void lds_load16(uint32_t lds, const char *sbase, uint32_t voff) {
     asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
-                 :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
-}
-__device__ __forceinline__ void lds_load4(uint32_t lds, const char *sbase, uint32_t voff) {
-    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, %2"
                  :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(voff), "s"(sbase) : "memory");
 }
 // Wait until at most N vector memory operations of this wave are in flight.
@@ -292,16 +286,12 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
     }
 }
 
-// The band pairs of tile row t (its band words bw) -> FP64 recheck list.  The
-// list has one segment per persistent workgroup, counted in LDS (`wg_count`);
-// the one-workgroup-per-tile launch shares the segments through global
-// counters.
-__device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw,
-                                         unsigned int *wg_count) {
+// The band pairs of tile row t (its band words bw) -> FP64 recheck list, in
+// segment blockIdx % nseg (no single counter is shared by the whole launch).
+__device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw) {
     const int n = __popc(bw.x) + __popc(bw.y) + __popc(bw.z) + __popc(bw.w);
-    const int seg = wg_count ? (int)blockIdx.x : (int)(blockIdx.x % (unsigned)a.nseg);
-    int64_t idx = wg_count ? (int64_t)atomicAdd(wg_count, (unsigned int)n)
-                           : (int64_t)atomicAdd(&a.band_n[seg], (unsigned long long)n);
+    const int seg = (int)(blockIdx.x % (unsigned)a.nseg);
+    int64_t idx = (int64_t)atomicAdd(&a.band_n[seg], (unsigned long long)n);
     const int64_t gr = (int64_t)tl.I * TILE + t;
     for (int j = 0; j < 4; ++j) {
         uint32_t m = bw[j];
@@ -341,7 +331,7 @@ __device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
 // popcount of its four words, a column's the sum of its partials.
 template <int PREC, bool DEBUG, int BN>
 __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC, BN> &acc,
-                                              EpiShared &es, int wm, int wn, unsigned int *wg_count) {
+                                              EpiShared &es, int wm, int wn) {
     if constexpr (Cfg<PREC>::PANELS == 2) {                 // Gram value = hi.hi + cross terms
 #pragma unroll
         for (int bm = 0; bm < 2; ++bm)
@@ -383,7 +373,7 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
             const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
             if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
             const u32x4 bw = *(const u32x4 *)(es.bwords + 4 * t);
-            if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw, wg_count);
+            if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw);
         } else {
             const int cc = t - TILE;
             const int64_t gc = (int64_t)tl.J * TILE + cc;
@@ -428,7 +418,7 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
         if (st == 0) grid_mfma<PREC, true>(ops, acc);
         else grid_mfma<PREC, false>(ops, acc);
     }
-    tile_epilogue<PREC, DEBUG, 1>(a, tl, acc, es, wm, wn, nullptr);
+    tile_epilogue<PREC, DEBUG, 1>(a, tl, acc, es, wm, wn);
 }
 
 template <int PREC, bool DEBUG>
@@ -444,219 +434,6 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     if (item >= a.tt.n_items) return;
     const TilePos tl = tile_lookup(a.tt, item);
     process_tile<PREC, DEBUG>(a, tl, stages, es);
-}
-
-// ------------------------------------------------------------------ ring form
-// Persistent workgroups (two per CU) stream their tile pairs through a
-// four-slab LDS ring filled by LDS-direct loads (global_load_lds: the data
-// goes from memory to LDS without registers), so three slabs are in flight
-// while the matrix cores work on the fourth, across tile boundaries: the
-// next tile's first slabs and thresholds load during this tile's last slabs
-// and epilogue.  A slab is 64 bytes of every row of both sides (16 KB).  Each
-// wave fills a quarter of a slab with four 1 KB loads; lane l of a load
-// writes LDS bytes [16 l, 16 l + 16) of the load's 1 KB, so a lane reads the
-// global chunk that belongs at that swizzled position.
-constexpr int RNS = 4;                        // ring slabs
-constexpr int RROW = 64;                      // bytes of a row per slab
-constexpr int RSLAB = 2 * TILE * RROW;        // 16 KB
-
-__device__ __forceinline__ int rswz(int r) { return (r >> 2) & 3; }     // as swz<4>
-__device__ __forceinline__ int roff(int r, int c) { return r * RROW + ((c ^ rswz(r)) << 4); }
-
-// One slab of the ring through the matrix cores.  Chunk c of a row holds:
-// FP32 values 4c..4c+3; BF16/FP16 values 8c..8c+7; hi/lo splits the hi
-// (c = 0, 1) or lo (c = 2, 3) halves of values 8(c%2)..8(c%2)+7.
-template <int PREC, bool FIRST>
-__device__ __forceinline__ void ring_compute(const char *slab, Acc<PREC, 2> &acc, int wm, int wn) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int li = lane & 31, lg = lane >> 5;
-    const f32x16 zero = {};
-    const char *A = slab, *B = slab + TILE * RROW;
-    if constexpr (PREC == P_FP32) {
-#pragma unroll
-        for (int ss = 0; ss < 2; ++ss) {
-            f32x4 av[2], bv[2];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                av[b] = *(const f32x4 *)(A + roff(wm * 64 + b * 32 + li, 2 * ss + lg));
-                bv[b] = *(const f32x4 *)(B + roff(wn * 64 + b * 32 + li, 2 * ss + lg));
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-                    for (int bn = 0; bn < 2; ++bn)
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                            av[bm][t], bv[bn][t], FIRST && ss == 0 && t == 0 ? zero : acc.c[bm][bn], 0, 0, 0);
-        }
-    } else if constexpr (Cfg<PREC>::PANELS == 1) {
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            u32x4 ah[2], bh[2];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                ah[b] = *(const u32x4 *)(A + roff(wm * 64 + b * 32 + li, 2 * ks + lg));
-                bh[b] = *(const u32x4 *)(B + roff(wn * 64 + b * 32 + li, 2 * ks + lg));
-            }
-            const bool z0 = FIRST && ks == 0;
-#pragma unroll
-            for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-                for (int bn = 0; bn < 2; ++bn) {
-                    if constexpr (PREC == P_BF16)
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
-                    else
-                        acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                            z0 ? zero : acc.c[bm][bn], 0, 0, 0);
-                }
-        }
-    } else {
-        u32x4 ah[2], bh[2], al[2], bl[2];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int ra = wm * 64 + b * 32 + li, rb = wn * 64 + b * 32 + li;
-            ah[b] = *(const u32x4 *)(A + roff(ra, lg));
-            al[b] = *(const u32x4 *)(A + roff(ra, 2 + lg));
-            bh[b] = *(const u32x4 *)(B + roff(rb, lg));
-            bl[b] = *(const u32x4 *)(B + roff(rb, 2 + lg));
-        }
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < 2; ++bn) {
-                if constexpr (PREC == P_BF16X3) {
-                    acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                        FIRST ? zero : acc.c[bm][bn], 0, 0, 0);
-                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, ah[bm]), __builtin_bit_cast(bf16x8, bl[bn]),
-                        FIRST ? zero : acc.x[bm][bn], 0, 0, 0);
-                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, al[bm]), __builtin_bit_cast(bf16x8, bh[bn]),
-                        acc.x[bm][bn], 0, 0, 0);
-                } else {
-                    acc.c[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                        FIRST ? zero : acc.c[bm][bn], 0, 0, 0);
-                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, ah[bm]), __builtin_bit_cast(f16x8, bl[bn]),
-                        FIRST ? zero : acc.x[bm][bn], 0, 0, 0);
-                    acc.x[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, al[bm]), __builtin_bit_cast(f16x8, bh[bn]),
-                        acc.x[bm][bn], 0, 0, 0);
-                }
-            }
-    }
-}
-
-// Producer state of one wave for one tile: rows 64 (w % 2) .. + 63 of side
-// w / 2.  `sbase` is the global address of the current slab of the side's
-// first row (advanced by 64 bytes per slab), `vo[i]` lane's byte offset for
-// its chunk in load i (rows past the element clamped to its last row).
-struct RingFeed {
-    const char *sbase;
-    uint32_t vo[4];
-};
-
-__device__ __forceinline__ void ring_setup(const TileArgs &a, const TilePos &tl, int w, int lane, uint32_t stride,
-                                           bool thr, uint32_t thr_lds, RingFeed &f) {
-    const int side = w >> 1;
-    const int64_t r0 = (int64_t)(side ? tl.J : tl.I) * TILE;
-    const int64_t nrow = tl.ne - r0;                        // rows of this side in the element (>= 1)
-    const int rw = (w & 1) * 64;                            // first side row of this wave
-    if (thr) {                                              // the tile's thresholds of these rows
-        const int r = rw + lane;
-        const uint32_t vo = (uint32_t)(r < nrow ? r : (int)(nrow - 1)) * 4u;
-        lds_load4(thr_lds, (const char *)(a.thrA + tl.slot0 + r0), vo);
-        lds_load4(thr_lds + 2 * TILE * 4, (const char *)(a.thrB + tl.slot0 + r0), vo);
-    }
-    f.sbase = (const char *)a.panel + (tl.slot0 + r0) * (int64_t)stride;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = rw + i * 16 + (lane >> 2);            // side row of this lane's chunk
-        const int c = (lane & 3) ^ rswz(w * 64 + i * 16 + (lane >> 2));
-        f.vo[i] = (uint32_t)(r < nrow ? r : (int)(nrow - 1)) * stride + (uint32_t)(c << 4);
-    }
-}
-
-// The wave's quarter of the feed's next slab into the ring slot at `slot_lds`.
-__device__ __forceinline__ void ring_issue(RingFeed &f, uint32_t slot_lds, int w) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) lds_load16(slot_lds + (uint32_t)((w * 4 + i) * 1024), f.sbase, f.vo[i]);
-    f.sbase += RROW;
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(NT, 2) k_tiles_ring(TileArgs a) {
-    __shared__ __attribute__((aligned(1024))) char ring[RNS * RSLAB];
-    __shared__ EpiShared es[2];
-    __shared__ unsigned int band_used;                      // this workgroup's band segment
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wm = w >> 1, wn = w & 1;
-    // this workgroup's items: XCD slice of the item order, strided by the
-    // number of workgroups on the XCD (concurrent items stay consecutive)
-    const int64_t n = a.tt.n_items;
-    const int64_t per = (n + 7) / 8;
-    const int64_t gx = gridDim.x / 8;
-    const int64_t lo = (int64_t)(blockIdx.x % 8) * per;
-    const int64_t hi = lo + per < n ? lo + per : n;
-    const int64_t first = lo + blockIdx.x / 8;
-    if (first >= hi) return;
-    const int nt = (int)((hi - first + gx - 1) / gx);       // tiles of this workgroup
-    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
-    const int nst = (int)(panel_row_bytes(PREC, a.dp) / RROW);   // slabs per tile (>= 4)
-    const uint32_t ring_lds = lds_addr(ring);
-    const uint32_t thr_lds0 = lds_addr(&es[0].thrA[0]) + (uint32_t)(w * 64 * 4);
-    const uint32_t es_stride = (uint32_t)sizeof(EpiShared);
-    auto slot_lds = [&](int slot) { return ring_lds + (uint32_t)(slot * RSLAB); };
-
-    // The producer runs RNS - 1 slabs ahead of the consumer, into the next
-    // tile during a tile's last slabs; after the last tile it stops, and the
-    // waits below count the loads actually in flight.
-    if (threadIdx.x == 0) band_used = 0;                    // first read after several barriers
-    TilePos tc = tile_lookup(a.tt, first);
-    RingFeed feed;
-    ring_setup(a, tc, w, lane, stride, true, thr_lds0, feed);
-#pragma unroll
-    for (int i = 0; i < RNS - 1; ++i) ring_issue(feed, slot_lds(i), w);
-    int pslot = RNS - 1, cslot = 0;
-
-    Acc<PREC, 2> acc;
-#pragma unroll 1
-    for (int k = 0; k < nt; ++k) {
-        const bool more = k + 1 < nt;
-        const TilePos tn = more ? tile_lookup(a.tt, first + (int64_t)(k + 1) * gx) : tc;
-#pragma unroll 1
-        for (int s = 0; s < nst; ++s) {
-            // loads issued after slab s's own: 4 per later slab in flight (two,
-            // fewer at the very end) plus the next tile's 2 threshold loads
-            if (s + 2 < nst) vm_wait<8>();
-            else if (more) vm_wait<10>();
-            else if (s + 2 == nst) vm_wait<4>();
-            else vm_wait<0>();
-            lds_barrier();
-            if (s + RNS - 1 == nst && more)                 // the producer moves to the next tile
-                ring_setup(a, tn, w, lane, stride, true, thr_lds0 + (uint32_t)((k + 1) & 1) * es_stride, feed);
-            if (s + RNS - 1 < nst || more) {
-                ring_issue(feed, slot_lds(pslot), w);
-                pslot = (pslot + 1) & (RNS - 1);
-            }
-            const char *slab = ring + cslot * RSLAB;
-            cslot = (cslot + 1) & (RNS - 1);
-            if (s == 0) ring_compute<PREC, true>(slab, acc, wm, wn);
-            else ring_compute<PREC, false>(slab, acc, wm, wn);
-        }
-        tile_epilogue<PREC, false, 2>(a, tc, acc, es[k & 1], wm, wn, &band_used);
-        tc = tn;
-    }
-    vm_wait<0>();                                           // no LDS-direct load outlives the workgroup
-    lds_barrier();
-    if (threadIdx.x == 0) a.band_n[blockIdx.x] = band_used;
 }
 
 __global__ void k_build_items(TileTable tt, TileItem *items) {
@@ -676,10 +453,6 @@ __global__ void k_build_items(TileTable tt, TileItem *items) {
 template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
-    if (a.grid > 0 && !a.debug_g) {
-        k_tiles_ring<PREC><<<dim3((unsigned)a.grid), dim3(NT), 0, s>>>(a);
-        return hipGetLastError();
-    }
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
     if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
     else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
