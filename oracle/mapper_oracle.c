@@ -25,6 +25,10 @@
  *            j order in FP64;  values: given.
  *   cover    L = (M-m)/(n-(n-1)p), s = L(1-p), lo_k = m + k s,
  *            hi_k = lo_k + L (k < n-1), hi_{n-1} = M; closed intervals.
+ *   balanced the same formula on the rank axis [0, N-1] of the sorted lens
+ *            values v_0 <= ... <= v_{N-1}, rounded outward to ranks:
+ *            lo_k = v[floor(rlo_k)], hi_k = v[ceil(rhi_k)] (the "balanced"
+ *            cover whose intervals hold equal numbers of points).
  *   distance D(a,b): t_j = (double)x_aj - (double)x_bj, D = fma(t_j,t_j,D)
  *            in j order starting from 0; neighbours iff D <= fl(eps*eps)
  *            (closed eps-ball); a point is its own neighbour.
@@ -59,6 +63,7 @@ typedef struct {
     const double *values;     /* n doubles (VALUES) */
     int32_t n_intervals;
     double overlap;
+    int32_t cover;            /* 0: uniform intervals; 1: balanced */
 } orc_axis;
 
 typedef struct {
@@ -174,6 +179,35 @@ static void uf_union(int64_t *P, int64_t a, int64_t b)
     b = uf_find(P, b);
     if (a == b) return;
     if (a < b) P[b] = a; else P[a] = b;   /* the root is the smallest index */
+}
+
+static int orc_cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Background section: the "balanced" cover, whose intervals hold equal
+ * numbers of points.  The uniform cover is laid on the rank axis [0, N-1] of
+ * the sorted lens values, and each rank interval [rlo, rhi] becomes the
+ * value interval [v[floor(rlo)], v[ceil(rhi)]] (outward, so it is never
+ * empty and the endpoints stay monotone).  A zero endpoint is stored as +0. */
+int orc_cover_balanced(const double *f, int64_t n, int32_t nint, double p, double *lo, double *hi)
+{
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!v) return ORC_ENOMEM;
+    memcpy(v, f, sizeof(double) * (size_t)n);
+    qsort(v, (size_t)n, sizeof(double), orc_cmp_double);
+    orc_cover(0.0, (double)(n - 1), nint, p, lo, hi);
+    for (int32_t k = 0; k < nint; ++k) {
+        int64_t a = (int64_t)floor(lo[k]), b = (int64_t)ceil(hi[k]);
+        if (a < 0) a = 0;
+        if (b > n - 1) b = n - 1;
+        lo[k] = v[a] + 0.0;
+        hi[k] = v[b] + 0.0;
+    }
+    free(v);
+    return 0;
 }
 
 /* DBSCAN of one cover element (members idx[0..nk) in ascending order).
@@ -314,6 +348,7 @@ int orc_validate(const float *X, int64_t n, int32_t d, int32_t n_axes,
         const orc_axis *ax = &axes[a];
         if (ax->n_intervals < 1) return ORC_EINVAL;
         if (!(ax->overlap >= 0.0 && ax->overlap < 1.0)) return ORC_EINVAL;
+        if (ax->cover < 0 || ax->cover > 1) return ORC_EINVAL;
         if (ax->kind == ORC_LENS_COLUMN && (ax->column < 0 || ax->column >= d)) return ORC_EINVAL;
         if (ax->kind == ORC_LENS_PROJECTION) {
             if (!ax->direction) return ORC_EINVAL;
@@ -359,7 +394,12 @@ int orc_mapper(const float *X, int64_t n, int32_t d, int32_t n_axes,
         }
         lo[a] = g->lo + ioff;
         hi[a] = g->hi + ioff;
-        orc_cover(m, M, nint[a], axes[a].overlap, lo[a], hi[a]);
+        if (axes[a].cover == 1) {
+            rc = orc_cover_balanced(f[a], n, nint[a], axes[a].overlap, lo[a], hi[a]);
+            if (rc) { orc_graph_free(g); return rc; }
+        } else {
+            orc_cover(m, M, nint[a], axes[a].overlap, lo[a], hi[a]);
+        }
         for (int32_t k = 0; k < nint[a]; ++k)        /* a range too wide for FP64 endpoints */
             if (!isfinite(lo[a][k]) || !isfinite(hi[a][k])) { orc_graph_free(g); return ORC_EINVAL; }
         ioff += nint[a];

@@ -38,7 +38,8 @@ class _Axis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("column", ctypes.c_int32),
                 ("direction", ctypes.POINTER(ctypes.c_float)),
                 ("values", ctypes.POINTER(ctypes.c_double)),
-                ("n_intervals", ctypes.c_int32), ("overlap", ctypes.c_double)]
+                ("n_intervals", ctypes.c_int32), ("overlap", ctypes.c_double),
+                ("cover", ctypes.c_int32)]
 
 
 class _Graph(ctypes.Structure):
@@ -80,6 +81,10 @@ def lib():
         L.orc_cover.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.orc_cover.restype = None
+        L.orc_cover_balanced.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.orc_cover_balanced.restype = ctypes.c_int
         L.orc_dbscan.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_double,
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -142,6 +147,7 @@ def _axes(params, keep):
         arr[a].column = ax.column
         arr[a].n_intervals = ax.n_intervals
         arr[a].overlap = ax.overlap
+        arr[a].cover = getattr(ax, "cover", 0)
         if ax.direction is not None:
             v = np.ascontiguousarray(ax.direction, dtype=np.float32)
             keep.append(v)
@@ -220,6 +226,19 @@ def cover(m: float, M: float, n_intervals: int, overlap: float):
     hi = np.zeros(n_intervals, np.float64)
     lib().orc_cover(float(m), float(M), int(n_intervals), float(overlap),
                     _p(lo, ctypes.c_double), _p(hi, ctypes.c_double))
+    return lo, hi
+
+
+def cover_balanced(f: np.ndarray, n_intervals: int, overlap: float):
+    """Balanced cover of the lens values f: intervals holding equal numbers
+    of points (the uniform cover on the rank axis, rounded outward)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lo = np.zeros(n_intervals, np.float64)
+    hi = np.zeros(n_intervals, np.float64)
+    rc = lib().orc_cover_balanced(_p(f, ctypes.c_double), f.size, int(n_intervals), float(overlap),
+                                  _p(lo, ctypes.c_double), _p(hi, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(rc)
     return lo, hi
 
 

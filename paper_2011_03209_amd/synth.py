@@ -50,6 +50,7 @@ class Axis:
     column: int = 0
     direction: Optional[np.ndarray] = None   # float32 (d,)
     values: Optional[np.ndarray] = None      # float64 (n,)
+    cover: int = 0                           # 0: uniform intervals; 1: balanced (equal point counts)
 
 
 @dataclasses.dataclass
