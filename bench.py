@@ -180,6 +180,12 @@ def main():
                               **{k: ss[-1][k] for k in ("ms_tiles", "ms_recheck", "ms_cc", "ms_edges",
                                                         "ms_lens", "ms_bin", "band_pairs")}}),
                   file=sys.stderr, flush=True)
+        pb = copy.deepcopy(w.params)
+        pb.axes[0].cover = 1
+        _, ts, ss = time_path(cloud, pb, 2, 1)
+        print(json.dumps({"sweep": f"balanced cover {args.precision}", "s_per_graph": float(np.median(ts)),
+                          **{k: ss[-1][k] for k in ("ms_lens", "ms_bin", "ms_tiles", "pairs", "band_pairs")}}),
+              file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

@@ -90,7 +90,19 @@ typedef struct {
     const double *values;    /* VALUES: n doubles, host; copied; finite */
     int32_t n_intervals;     /* >= 1 */
     double overlap;          /* 0 <= overlap < 1 */
+    int32_t cover;           /* MAPPER_COVER_UNIFORM or MAPPER_COVER_BALANCED */
 } mapper_axis;
+
+/* Cover of one lens axis (Background section).  UNIFORM: n closed intervals
+ * of equal length tiling [min f, max f], neighbours sharing the fraction p of
+ * their length.  BALANCED: intervals holding equal numbers of points (the
+ * "balanced" cover the paper mentions): the uniform cover laid on the rank
+ * axis [0, N-1] of the sorted lens values v_0 <= ... <= v_{N-1}, each rank
+ * interval [a, b] becoming the closed value interval [v[floor a], v[ceil b]];
+ * with distinct values every interval holds between floor(L) + 1 and
+ * ceil(L) + 2 points, L = (N-1) / (n - (n-1) p). */
+#define MAPPER_COVER_UNIFORM 0
+#define MAPPER_COVER_BALANCED 1
 
 typedef struct {
     int32_t n_axes;          /* 1 (1-D mapper) or 2 (2-D mapper) */

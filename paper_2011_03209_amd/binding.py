@@ -34,7 +34,8 @@ class _Axis(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("column", ctypes.c_int32),
                 ("direction", ctypes.POINTER(ctypes.c_float)),
                 ("values", ctypes.POINTER(ctypes.c_double)),
-                ("n_intervals", ctypes.c_int32), ("overlap", ctypes.c_double)]
+                ("n_intervals", ctypes.c_int32), ("overlap", ctypes.c_double),
+                ("cover", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -141,6 +142,7 @@ def make_params(params, flags: int = 0, keep: Optional[list] = None) -> _Params:
         p.axis[a].column = int(ax.column)
         p.axis[a].n_intervals = int(ax.n_intervals)
         p.axis[a].overlap = float(ax.overlap)
+        p.axis[a].cover = int(getattr(ax, "cover", 0))
         if ax.direction is not None:
             v = np.ascontiguousarray(ax.direction, dtype=np.float32)
             keep.append(v)

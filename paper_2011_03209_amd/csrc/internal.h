@@ -130,6 +130,11 @@ hipError_t launch_check_cloud(const float *X, int64_t count, uint32_t *flags_max
 hipError_t launch_lens(const float *X, int64_t n, int32_t d, int kind, int32_t column,
                        const float *dir, const double *values, double *f, hipStream_t s);
 hipError_t launch_range(const double *f, int64_t n, unsigned long long *keys2, hipStream_t s);
+// keys[i] = order-preserving key of f[i], vals[i] = i (for a radix sort of the lens).
+hipError_t launch_lens_keys(const double *f, int64_t n, uint64_t *keys, uint32_t *vals, hipStream_t s);
+// out[i] = the lens value whose key is sorted[rank[i]] (zero as +0).
+hipError_t launch_rank_values(const uint64_t *sorted, const int64_t *rank, int32_t m, double *out,
+                              hipStream_t s);
 
 // prims.hip
 size_t scan_temp_bytes(int64_t n);

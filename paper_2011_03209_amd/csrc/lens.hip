@@ -130,7 +130,39 @@ __global__ void __launch_bounds__(256) k_range(const double *f, int64_t n, unsig
     }
 }
 
+// Balanced cover (the cover whose intervals hold equal numbers of points,
+// Background section): the lens as ordered keys for a radix sort ...
+__global__ void k_lens_keys(const double *f, int64_t n, uint64_t *keys, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = dkey(f[i]);
+    vals[i] = (uint32_t)i;
+}
+
+// ... and the lens values of given ranks read back from the sorted keys (a
+// zero comes back as +0).
+__global__ void k_rank_values(const uint64_t *sorted, const int64_t *rank, int32_t m, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const unsigned long long k = sorted[rank[i]];
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    out[i] = __longlong_as_double((long long)b) + 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_lens_keys(const double *f, int64_t n, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_lens_keys<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(f, n, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_values(const uint64_t *sorted, const int64_t *rank, int32_t m, double *out,
+                              hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    k_rank_values<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(sorted, rank, m, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_check_cloud(const float *X, int64_t count, uint32_t *flags_maxabs, hipStream_t s) {
     int64_t blocks = (count + 255) / 256;

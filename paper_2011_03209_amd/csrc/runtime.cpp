@@ -243,6 +243,8 @@ mapper_status validate(const mapper_cloud *c, const mapper_params *p) {
         const mapper_axis &ax = p->axis[a];
         if (ax.n_intervals < 1) return fail(MAPPER_EINVAL, "n_intervals must be >= 1");
         if (!(ax.overlap >= 0.0 && ax.overlap < 1.0)) return fail(MAPPER_EINVAL, "overlap must be in [0, 1)");
+        if (ax.cover != MAPPER_COVER_UNIFORM && ax.cover != MAPPER_COVER_BALANCED)
+            return fail(MAPPER_EINVAL, "cover must be MAPPER_COVER_UNIFORM or MAPPER_COVER_BALANCED");
         if (ax.kind < 0 || ax.kind > MAPPER_LENS_VALUES) return fail(MAPPER_EINVAL, "bad lens kind");
         if (ax.kind == MAPPER_LENS_COLUMN && (ax.column < 0 || ax.column >= c->d))
             return fail(MAPPER_EINVAL, "lens column out of range");
@@ -334,6 +336,36 @@ struct Events {
         return t;
     }
 };
+
+// Balanced cover: the uniform cover of the rank axis [0, n-1], each rank
+// interval [a, b] rounded outward to [floor a, ceil b] and read back as lens
+// values from a device radix sort of the lens.
+void balanced_endpoints(Arena &arena, const double *f, int64_t n, int nint, double p, std::vector<double> &lo,
+                        std::vector<double> &hi, hipStream_t s) {
+    std::vector<double> rl, rh;
+    cover_endpoints(0.0, (double)(n - 1), nint, p, rl, rh);
+    std::vector<int64_t> rank(2 * (size_t)nint);
+    for (int k = 0; k < nint; ++k) {
+        rank[k] = std::max<int64_t>(0, (int64_t)std::floor(rl[k]));
+        rank[nint + k] = std::min<int64_t>(n - 1, (int64_t)std::ceil(rh[k]));
+    }
+    Scope mem(arena);                                       // released on return, after the sync
+    uint64_t *k1 = mem.get<uint64_t>(n), *k2 = mem.get<uint64_t>(n);
+    uint32_t *v1 = mem.get<uint32_t>(n), *v2 = mem.get<uint32_t>(n);
+    void *tmp = mem.get<char>(sort_temp_bytes(n));
+    int64_t *drank = mem.get<int64_t>(2 * nint);
+    double *dval = mem.get<double>(2 * nint);
+    HIPCHK(launch_lens_keys(f, n, k1, v1, s));
+    bool alt = false;
+    HIPCHK(radix_sort_pairs(k1, v1, k2, v2, n, 64, tmp, &alt, s));
+    h2d(drank, rank.data(), 2 * nint, s);
+    HIPCHK(launch_rank_values(alt ? k2 : k1, drank, 2 * nint, dval, s));
+    std::vector<double> val;
+    d2h(val, dval, 2 * nint, s);
+    HIPCHK(hipStreamSynchronize(s));
+    lo.assign(val.begin(), val.begin() + nint);
+    hi.assign(val.begin() + nint, val.end());
+}
 
 // Items before each supertile column of every element (see tile_decode).
 void build_supertile_columns(const std::vector<int64_t> &T, std::vector<int64_t> &colpre,
@@ -468,7 +500,10 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     double* dhc[2] = {nullptr, nullptr};
     for (int a = 0; a < na; ++a) {
         const double m = key_to_double(rkh[2 * a]), M = key_to_double(rkh[2 * a + 1]);
-        cover_endpoints(m, M, nint[a], P->axis[a].overlap, lo[a], hi[a]);
+        if (P->axis[a].cover == MAPPER_COVER_BALANCED)
+            balanced_endpoints(ctx->arena, f[a], n, nint[a], P->axis[a].overlap, lo[a], hi[a], s);
+        else
+            cover_endpoints(m, M, nint[a], P->axis[a].overlap, lo[a], hi[a]);
         hc[a].resize(nint[a]);
         for (int k = 0; k < nint[a]; ++k) {
             if (!std::isfinite(lo[a][k]) || !std::isfinite(hi[a][k]))

@@ -54,7 +54,7 @@ _ORACLE = {}
 def oracle_graph(X, params):
     """The oracle does not depend on the tile precision: cache it per input."""
     key = (X.shape, float(np.float64(X).sum()), float(np.abs(np.float64(X)).sum()), params.eps,
-           params.min_pts, tuple((a.kind, a.column, a.n_intervals, a.overlap,
+           params.min_pts, tuple((a.kind, a.column, a.n_intervals, a.overlap, getattr(a, "cover", 0),
                                   None if a.direction is None else a.direction.tobytes(),
                                   None if a.values is None else a.values.tobytes()) for a in params.axes))
     if key not in _ORACLE:
@@ -271,6 +271,32 @@ def test_band_list_regrows(ctx):
     assert g.stats["tile_launches"] > 1, g.stats
     assert g.stats["band_pairs"] > 16 * g.stats["tiles"], g.stats
     same_graph(g, oracle_graph(w.X, params))
+
+
+@pytest.mark.parametrize("case", ["mix1d", "grid2d_one_axis", "ties", "fewer_points_than_intervals"])
+def test_balanced_cover(ctx, case):
+    """The balanced cover (intervals holding equal numbers of points): the
+    GPU's endpoints (from a device radix sort of the lens), elements, counts
+    and graph equal the oracle's."""
+    if case == "mix1d":
+        w = synth.mixture_100k_d64(scale=0.05)
+        w.params.axes[0].cover = 1
+        X, params = w.X, with_prec(w.params, synth.PREC_BF16X3)
+    elif case == "grid2d_one_axis":
+        w = synth.mixture_500k_d128_2d(scale=0.01, precision=synth.PREC_FP16)
+        w.params.axes[0].cover = 1
+        X, params = w.X, w.params
+    elif case == "ties":
+        rng = np.random.default_rng(11)
+        X = rng.normal(size=(6000, 16)).astype(np.float32)
+        vals = np.floor(rng.uniform(0, 9, size=6000))               # nine distinct lens values
+        params = synth.Params([synth.Axis(4, 7, 0.4, values=vals, cover=1)], eps=4.5, min_pts=5,
+                              precision=synth.PREC_FP32)
+    else:
+        X = np.random.default_rng(5).normal(size=(5, 3)).astype(np.float32)
+        params = synth.Params([synth.Axis(1, 8, 0.1, cover=1)], eps=2.0, min_pts=1,
+                              precision=synth.PREC_FP32)
+    run_and_compare(ctx, X, params)
 
 
 def test_determinism_and_permutation(ctx):
