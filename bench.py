@@ -186,6 +186,17 @@ def main():
         print(json.dumps({"sweep": f"balanced cover {args.precision}", "s_per_graph": float(np.median(ts)),
                           **{k: ss[-1][k] for k in ("ms_lens", "ms_bin", "ms_tiles", "pairs", "band_pairs")}}),
               file=sys.stderr, flush=True)
+        eps4 = [20.0, 22.0, 24.0, 26.0]
+        t0 = time.perf_counter()
+        cloud.run_eps_sweep(w.params, eps4)
+        t1 = time.perf_counter()
+        gs4 = cloud.run_eps_sweep(w.params, eps4)
+        t2 = time.perf_counter()
+        print(json.dumps({"sweep": f"eps sweep {eps4} {args.precision}", "s_for_all": t2 - t1,
+                          "warm_s": t1 - t0, "ms_tiles": gs4[0].stats["ms_tiles"],
+                          "ms_recheck": gs4[0].stats["ms_recheck"],
+                          "ms_cc_each": [gg.stats["ms_cc"] for gg in gs4],
+                          "nodes": [gg.n_nodes for gg in gs4]}), file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

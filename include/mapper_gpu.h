@@ -161,6 +161,22 @@ mapper_status mapper_cloud_destroy(mapper_cloud *cloud);   /* MAPPER_EBUSY while
 mapper_status mapper_run(mapper_context *ctx, const mapper_cloud *cloud,
                          const mapper_params *params, mapper_graph **out);
 
+/* --- several eps values in one pass, synchronous ------------------------
+ * Interactive recomputation as the DBSCAN parameter changes (Design and
+ * Implementation section: the graph is recomputed on the fly as parameters
+ * change; the eps-selection module of the CIFAR-10 use case).  out[t]
+ * (t < n_eps, 1 <= n_eps <= MAPPER_MAX_EPS_VALUES) receives exactly the graph
+ * mapper_run returns with params->eps = eps_list[t]; params->eps itself is
+ * not used beyond validation.  Lens, cover, pullback sets, panels and the
+ * distance tiles are computed once: each tile pair's Gram values are decided
+ * against every eps value, each value getting its own bitmask and counts.
+ * eps_list: host, n_eps finite values >= 0, any order.  The graphs are owned
+ * by the caller (mapper_graph_destroy each); on error every out[t] is NULL. */
+#define MAPPER_MAX_EPS_VALUES 4
+mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *cloud,
+                                   const mapper_params *params, const double *eps_list,
+                                   int32_t n_eps, mapper_graph **out);
+
 /* --- serving: continuous batching of requests ---------------------------
  * submit returns at once with a ticket; requests are admitted while their
  * workspace fits in the arena and a stream slot is free, and run

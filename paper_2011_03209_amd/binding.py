@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmapper_gpu.so")
 MAPPER_OK, MAPPER_EINVAL, MAPPER_ENOMEM, MAPPER_EDEVICE = 0, -1, -2, -3
 MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
+MAX_EPS_VALUES = 4          # MAPPER_MAX_EPS_VALUES
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
 
@@ -74,6 +75,8 @@ EXPORTS = {
                             ctypes.c_int),
     "mapper_cloud_destroy": ([_vp], ctypes.c_int),
     "mapper_run": ([_vp, _vp, _P(_Params), _P(_vp)], ctypes.c_int),
+    "mapper_run_eps_sweep": ([_vp, _vp, _P(_Params), _P(ctypes.c_double), ctypes.c_int32, _P(_vp)],
+                             ctypes.c_int),
     "mapper_submit": ([_vp, _vp, _P(_Params), _P(ctypes.c_uint64)], ctypes.c_int),
     "mapper_wait": ([_vp, ctypes.c_uint64, ctypes.c_int64, _P(_vp)], ctypes.c_int),
     "mapper_graph_num_nodes": ([_vp], ctypes.c_int64),
@@ -290,6 +293,17 @@ class Cloud:
         g = _vp()
         _check(self.ctx.L.mapper_run(self.ctx.h, self.h, ctypes.byref(p), ctypes.byref(g)))
         return _take_graph(g)
+
+    def run_eps_sweep(self, params, eps_list, debug: bool = False) -> List[Graph]:
+        """The graphs for several eps values (at most MAX_EPS_VALUES) from one
+        pass: graph t equals run(params with eps = eps_list[t])."""
+        _check_axes(params, self.n, self.d)
+        keep: list = []
+        p = make_params(params, FLAG_DEBUG_STAGES if debug else 0, keep)
+        eps = (ctypes.c_double * len(eps_list))(*[float(e) for e in eps_list])
+        out = (_vp * len(eps_list))()
+        _check(self.ctx.L.mapper_run_eps_sweep(self.ctx.h, self.h, ctypes.byref(p), eps, len(eps_list), out))
+        return [_take_graph(_vp(out[t])) for t in range(len(eps_list))]
 
     def submit(self, params, debug: bool = False) -> int:
         _check_axes(params, self.n, self.d)

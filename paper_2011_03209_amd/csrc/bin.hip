@@ -187,11 +187,13 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
             + (rho * xt + rr / rho + rr) * 0.5;           // residual beyond hi + lo
     }
     e += 0x1.0p-40 * nx + (3 * K + 8) * 0x1.0p-110;       // FP64 norm / distance rounding, underflow
-    const double Eh = a.E_scaled * 0.5;
-    const double A = (nx + 2 * e - Eh) * 0.5;               // g >= A_i + A_j  =>  D <= eps^2
-    const double B = (nx - 2 * e - Eh) * 0.5;               // g <  B_i + B_j  =>  D >  eps^2
-    a.thrA[s] = round_up_f(A + 0x1.0p-22 * fabs(A));
-    a.thrB[s] = round_dn_f(B - 0x1.0p-22 * fabs(B));
+    for (int t = 0; t < a.n_levels; ++t) {                  // one threshold pair per eps value
+        const double Eh = a.E_scaled[t] * 0.5;
+        const double A = (nx + 2 * e - Eh) * 0.5;           // g >= A_i + A_j  =>  D <= eps^2
+        const double B = (nx - 2 * e - Eh) * 0.5;           // g <  B_i + B_j  =>  D >  eps^2
+        a.thrA[(int64_t)t * a.n_slots + s] = round_up_f(A + 0x1.0p-22 * fabs(A));
+        a.thrB[(int64_t)t * a.n_slots + s] = round_dn_f(B - 0x1.0p-22 * fabs(B));
+    }
     if (a.dbg_norm2) a.dbg_norm2[s] = nx;
     if (a.dbg_e) a.dbg_e[s] = e;
 }

@@ -11,6 +11,7 @@ namespace mgpu {
 // ---------------------------------------------------------------- tiling
 // Distance tiles are TILE x TILE blocks of one cover element's members.
 constexpr int TILE = 128;
+constexpr int MAX_LEVELS = 4;        // eps values one tile pass can serve
 constexpr int TILE_WORDS = TILE * TILE / 32;      // uint32 words of one bitmask block
 constexpr int WAVE = 64;
 
@@ -119,7 +120,14 @@ __device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T
 // One pair whose tile distance fell inside the certified band of eps^2.
 struct BandPair {
     int32_t si, sj;            // slots (global member positions)
-    uint64_t bit;              // bit index in the bitmask
+    uint64_t bit;              // bit index in the level's bitmask | level << BAND_LEVEL_SHIFT
+};
+constexpr int BAND_LEVEL_SHIFT = 56;
+// The levels' eps^2 and strides, for the FP64 re-decision of band pairs.
+struct Levels {
+    double E[MAX_LEVELS];
+    int64_t level_slots;       // count of level t at t * level_slots
+    uint64_t level_words;      // bitmask of level t at t * level_words
 };
 
 // ---------------------------------------------------------------- launchers
@@ -185,9 +193,10 @@ struct PackArgs {
     const uint32_t *slot_point; int64_t n_slots;
     int prec;
     double scale;              // power of two applied to coordinates
-    double E_scaled;           // eps^2 * scale^2
+    int32_t n_levels;          // eps values served by one tile pass (1 .. MAX_LEVELS)
+    double E_scaled[MAX_LEVELS];   // eps_t^2 * scale^2
     void *panel;               // packed rows (panel_row_bytes each, panel_row_stride apart)
-    float *thrA; float *thrB;  // in-threshold / out-threshold of each slot
+    float *thrA; float *thrB;  // in-threshold / out-threshold of each slot, level t at t * n_slots
     double *dbg_norm2;         // optional: |x_s|^2 (scaled)
     double *dbg_e;             // optional: e_s, the slot's share of the Gram error bound (scaled)
 };
@@ -202,6 +211,9 @@ struct TileArgs {
     // band pairs: nseg segments of band_cap entries; band_n[g] counts the pairs
     // of segment g (past band_cap they are counted but not stored)
     BandPair *band; unsigned long long *band_n; int64_t band_cap; int32_t nseg;
+    // eps values served by the pass: thresholds, counts and bitmask of level t
+    // at t * level_slots (thrA, thrB, count) and t * level_words (bitmask)
+    int32_t n_levels; int64_t level_slots; uint64_t level_words;
     float *debug_g;            // non-null: write raw Gram values (debug, one element)
     int64_t debug_ld;
 };
@@ -212,7 +224,7 @@ int tile_grid_size(int prec, int64_t n_items);
 // band_n[g] = pairs in segment g (<= band_cap), nband their sum.
 hipError_t launch_recheck(const BandPair *band, const unsigned long long *band_n, int32_t nseg,
                           int64_t band_cap, int64_t nband, const float *X, int32_t d,
-                          const uint32_t *slot_point, double E, uint32_t *bitmask, int32_t *count,
+                          const uint32_t *slot_point, const Levels &lv, uint32_t *bitmask, int32_t *count,
                           hipStream_t s);
 hipError_t launch_row_norm2(const int32_t *rows, int64_t nr, const float *X, int32_t d,
                             double *out, hipStream_t s);

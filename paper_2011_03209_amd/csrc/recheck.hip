@@ -22,7 +22,7 @@ constexpr int RECHECK_WG_PER_SEG = 8;
 
 __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const unsigned long long *band_n,
                                                  int64_t band_cap, const float *X,
-                                                 int32_t d, const uint32_t *slot_point, double E,
+                                                 int32_t d, const uint32_t *slot_point, Levels lv,
                                                  uint32_t *bitmask, int32_t *count) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int seg = blockIdx.x / RECHECK_WG_PER_SEG;
@@ -81,6 +81,8 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (i < np) {
+                    const int level = (int)__builtin_amdgcn_readlane((int)(uint32_t)(bp.bit >> BAND_LEVEL_SHIFT), g + i);
+                    const double E = lv.E[level];
                     bool in = s[i] <= E;
                     if (fabs(s[i] - E) <= cf * s[i]) {      // a near-tie: the canonical chain decides
                         double D = 0.0;
@@ -92,9 +94,12 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
                         in = __shfl(D, 0, WAVE) <= E;
                     }
                     if (in && lane == g + i) {               // the lane holding the pair's record
-                        atomicOr(&bitmask[bp.bit >> 5], 1u << (bp.bit & 31u));
-                        atomicAdd(&count[bp.si], 1);
-                        atomicAdd(&count[bp.sj], 1);
+                        const uint64_t bit = bp.bit & ((1ull << BAND_LEVEL_SHIFT) - 1);
+                        uint32_t *bm = bitmask + (uint64_t)level * lv.level_words;
+                        int32_t *cn = count + (int64_t)level * lv.level_slots;
+                        atomicOr(&bm[bit >> 5], 1u << (bit & 31u));
+                        atomicAdd(&cn[bp.si], 1);
+                        atomicAdd(&cn[bp.sj], 1);
                     }
                 }
             }
@@ -130,11 +135,11 @@ __global__ void __launch_bounds__(256) k_row_norm2(const int32_t *rows, int64_t 
 
 hipError_t launch_recheck(const BandPair *band, const unsigned long long *band_n, int32_t nseg,
                           int64_t band_cap, int64_t nband, const float *X, int32_t d,
-                          const uint32_t *slot_point, double E, uint32_t *bitmask, int32_t *count,
+                          const uint32_t *slot_point, const Levels &lv, uint32_t *bitmask, int32_t *count,
                           hipStream_t s) {
     if (nband <= 0) return hipSuccess;
     k_recheck<<<dim3((unsigned)(nseg * RECHECK_WG_PER_SEG)), dim3(256), 0, s>>>(band, band_n, band_cap, X, d,
-                                                                              slot_point, E, bitmask, count);
+                                                                              slot_point, lv, bitmask, count);
     return hipGetLastError();
 }
 

@@ -449,23 +449,34 @@ int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneS
 enum class Phase { Ok, Retry };
 
 struct RunOut {
-    mapper_graph *g = nullptr;
+    std::vector<mapper_graph *> gs;    // one graph per eps value
+    ~RunOut() {
+        for (mapper_graph *g : gs) delete g;
+    }
 };
 
+// The graphs of one cloud and parameter set for n_levels eps values
+// (eps_list, or P->eps when it is null): lens, cover, binning, panels and
+// tiles are shared; every level has its own bitmask, counts and graph.
 Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
-                   hipStream_t s, bool may_retry, RunOut &out) {
+                   hipStream_t s, bool may_retry, RunOut &out, const double *eps_list = nullptr,
+                   int n_levels = 1) {
     Scope mem(ctx->arena);
     Events ev(s);
     const int64_t n = cloud->n;
     const int32_t d = cloud->d;
     const int na = P->n_axes;
-    auto g = std::make_unique<mapper_graph>();
-    mapper_run_stats &st = g->stats;
+    mapper_run_stats st{};
+    std::vector<double> Elev(n_levels);
+    for (int lv = 0; lv < n_levels; ++lv) {
+        const double e = eps_list ? eps_list[lv] : P->eps;
+        Elev[lv] = e * e;
+    }
     const bool dbg = (P->flags & MAPPER_FLAG_DEBUG_STAGES) != 0;
     std::vector<int> nint(2, 1);
     for (int a = 0; a < na; ++a) nint[a] = P->axis[a].n_intervals;
     const int64_t E_count = (int64_t)nint[0] * (na == 2 ? nint[1] : 1);
-    const double E = P->eps * P->eps;
+    const double E = Elev[0];
 
     ev.mark();                                                      // 0
     // ---- lens and range
@@ -648,7 +659,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
 
     const int dp = panel_dp(prec, d);
     void *panel = mem.get<char>((uint64_t)Sa * (uint64_t)panel_row_stride(prec, dp));
-    float *thrA = mem.get<float>(Sa), *thrB = mem.get<float>(Sa);
+    float *thrA = mem.get<float>((uint64_t)n_levels * Sa), *thrB = mem.get<float>((uint64_t)n_levels * Sa);
     PackArgs pk;
     pk.X = cloud->X;
     pk.d = d;
@@ -657,7 +668,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     pk.n_slots = S;
     pk.prec = prec;
     pk.scale = scale;
-    pk.E_scaled = E * scale * scale;
+    pk.n_levels = n_levels;
+    for (int lv = 0; lv < n_levels; ++lv) pk.E_scaled[lv] = Elev[lv] * scale * scale;
     pk.panel = panel;
     pk.thrA = thrA;
     pk.thrB = thrB;
@@ -665,8 +677,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     pk.dbg_e = nullptr;
     HIPCHK(launch_pack(pk, s));
 
-    int32_t *count = mem.get<int32_t>(Sa);
-    uint32_t *bitmask = mem.get<uint32_t>((uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS);
+    const uint64_t level_words = (uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS;
+    int32_t *count_all = mem.get<int32_t>((uint64_t)n_levels * Sa);
+    uint32_t *bitmask_all = mem.get<uint32_t>((uint64_t)n_levels * level_words);
     st.bitmask_bytes = nblocks * TILE_WORDS * 4;
     // band list: nseg segments, a tile's pairs going to segment blockIdx %
     // nseg; grown and the tiles redone if a segment overflows
@@ -688,7 +701,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     ev.mark();                                                      // 3
     std::vector<unsigned long long> segn(nseg);
     for (int launch = 0;; ++launch) {
-        HIPCHK(hipMemsetAsync(count, 0, (size_t)Sa * 4, s));
+        HIPCHK(hipMemsetAsync(count_all, 0, (size_t)n_levels * Sa * 4, s));
         HIPCHK(hipMemsetAsync(band_n, 0, (size_t)nseg * 8, s));
         TileArgs ta{};
         ta.tt = tt;
@@ -696,12 +709,15 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         ta.dp = dp;
         ta.thrA = thrA;
         ta.thrB = thrB;
-        ta.bitmask = bitmask;
-        ta.count = count;
+        ta.bitmask = bitmask_all;
+        ta.count = count_all;
         ta.band = band;
         ta.band_n = band_n;
         ta.band_cap = band_cap;
         ta.nseg = nseg;
+        ta.n_levels = n_levels;
+        ta.level_slots = Sa;
+        ta.level_words = level_words;
         Events kt(s);
         kt.mark();
         HIPCHK(launch_tiles(prec, ta, s));
@@ -719,37 +735,54 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     for (int g = 0; g < nseg; ++g) nband += (int64_t)segn[g];
     st.band_pairs = nband;
     ev.mark();                                                      // 4
-    HIPCHK(launch_recheck(band, band_n, nseg, band_cap, nband, cloud->X, d, slot_point, E, bitmask, count, s));
+    {
+        Levels lvs{};
+        for (int lv = 0; lv < n_levels; ++lv) lvs.E[lv] = Elev[lv];
+        lvs.level_slots = Sa;
+        lvs.level_words = level_words;
+        HIPCHK(launch_recheck(band, band_n, nseg, band_cap, nband, cloud->X, d, slot_point, lvs, bitmask_all,
+                              count_all, s));
+    }
     ev.mark();                                                      // 5
 
+    // ---- one graph per level
+    for (int lv = 0; lv < n_levels; ++lv) {
+    Scope lm(ctx->arena);                                           // this level's work arrays
+    Events lev(s);
+    lev.mark();                                                     // 0
+    int32_t *count = count_all + (int64_t)lv * Sa;
+    uint32_t *bitmask = bitmask_all + (uint64_t)lv * level_words;
+    auto g = std::make_unique<mapper_graph>();
+    g->stats = st;
+
     // ---- clusters
-    int32_t *parent = mem.get<int32_t>(Sa);
-    uint8_t *isroot = mem.get<uint8_t>(Sa);
-    int64_t *rank = mem.get<int64_t>(Sa + 1);
-    int32_t *node = mem.get<int32_t>(Sa);
-    int32_t *node_elem = mem.get<int32_t>(Sa);
+    int32_t *parent = lm.get<int32_t>(Sa);
+    uint8_t *isroot = lm.get<uint8_t>(Sa);
+    int64_t *rank = lm.get<int64_t>(Sa + 1);
+    int32_t *node = lm.get<int32_t>(Sa);
+    int32_t *node_elem = lm.get<int32_t>(Sa);
     // row blocks of all elements, numbered element by element
     std::vector<int64_t> rb_off(std::max<int64_t>(E_count, 1), 0);
     int64_t nrb = 0;
     for (int64_t e = 0; e < E_count; ++e) { rb_off[e] = nrb; nrb += T[e]; }
-    int64_t *d_rb_off = mem.get<int64_t>(rb_off.size());
+    int64_t *d_rb_off = lm.get<int64_t>(rb_off.size());
     h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
     HIPCHK(launch_cc_init(parent, S, s));
     HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
-    void *stmp2 = mem.get<char>(scan_temp_bytes(Sa + 1));
+    void *stmp2 = lm.get<char>(scan_temp_bytes(Sa + 1));
     HIPCHK(launch_scan_u8(isroot, rank, S, stmp2, s));
     HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, slot_elem, node, node_elem, S, s));
     {
-        uint8_t *ncflag = mem.get<uint8_t>(std::max<int64_t>(nrb, 1));
+        uint8_t *ncflag = lm.get<uint8_t>(std::max<int64_t>(nrb, 1));
         HIPCHK(hipMemsetAsync(ncflag, 0, (size_t)std::max<int64_t>(nrb, 1), s));
         HIPCHK(launch_noncore_flags(count, P->min_pts, slot_elem, elem_off, d_rb_off, ncflag, S, s));
         HIPCHK(launch_border(tt, bitmask, count, P->min_pts, ncflag, d_rb_off, node, s));
     }
     int64_t N = 0;
     HIPCHK(hipMemcpyAsync(&N, rank + S, 8, hipMemcpyDeviceToHost, s));
-    ev.mark();                                                      // 6
+    lev.mark();                                                     // 1
 
     // ---- node CSR: (node, point) sorted stably by node
     uint8_t *lab = isroot;       // reuse
@@ -760,53 +793,53 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     HIPCHK(hipMemcpyAsync(&M, mp + S, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int64_t Ma = std::max<int64_t>(M, 1);
-    uint64_t *k1 = mem.get<uint64_t>(Ma), *k2 = mem.get<uint64_t>(Ma);
-    uint32_t *v1 = mem.get<uint32_t>(Ma), *v2 = mem.get<uint32_t>(Ma);
-    void *sortmp2 = mem.get<char>(sort_temp_bytes(Ma));
+    uint64_t *k1 = lm.get<uint64_t>(Ma), *k2 = lm.get<uint64_t>(Ma);
+    uint32_t *v1 = lm.get<uint32_t>(Ma), *v2 = lm.get<uint32_t>(Ma);
+    void *sortmp2 = lm.get<char>(sort_temp_bytes(Ma));
     HIPCHK(launch_member_pairs(node, slot_point, mp, S, k1, v1, s));
     HIPCHK(radix_sort_pairs(k1, v1, k2, v2, M, bits_for((uint64_t)std::max<int64_t>(N - 1, 0)), sortmp2, &alt, s));
     uint64_t *nk = alt ? k2 : k1;
     uint32_t *nv = alt ? v2 : v1;
-    int64_t *node_off = mem.get<int64_t>(N + 1);
+    int64_t *node_off = lm.get<int64_t>(N + 1);
     HIPCHK(launch_node_offsets_from_sorted(nk, M, N, node_off, s));
-    int32_t *members = mem.get<int32_t>(Ma);
+    int32_t *members = lm.get<int32_t>(Ma);
     HIPCHK(launch_u32_to_i32(nv, members, M, s));
     // ---- edges: regroup (point, node) by point; stable, so nodes stay ascending
-    uint64_t *ptk = mem.get<uint64_t>(Ma), *ptk2 = mem.get<uint64_t>(Ma);
-    uint32_t *ptn = mem.get<uint32_t>(Ma), *ptn2 = mem.get<uint32_t>(Ma);
+    uint64_t *ptk = lm.get<uint64_t>(Ma), *ptk2 = lm.get<uint64_t>(Ma);
+    uint32_t *ptn = lm.get<uint32_t>(Ma), *ptn2 = lm.get<uint32_t>(Ma);
     HIPCHK(launch_widen_u32(nv, ptk, M, s));
     HIPCHK(launch_narrow_u64(nk, ptn, M, s));
     HIPCHK(radix_sort_pairs(ptk, ptn, ptk2, ptn2, M, bits_for((uint64_t)std::max<int64_t>(n - 1, 0)), sortmp2, &alt, s));
     uint64_t *sp_k = alt ? ptk2 : ptk;
     uint32_t *sp_n = alt ? ptn2 : ptn;
-    int32_t *ecnt = mem.get<int32_t>(Ma);
-    int64_t *epos = mem.get<int64_t>(Ma + 1);
-    void *stmp3 = mem.get<char>(scan_temp_bytes(Ma + 1));
+    int32_t *ecnt = lm.get<int32_t>(Ma);
+    int64_t *epos = lm.get<int64_t>(Ma + 1);
+    void *stmp3 = lm.get<char>(scan_temp_bytes(Ma + 1));
     HIPCHK(launch_edge_counts(sp_k, M, ecnt, s));
     HIPCHK(launch_scan_i32(ecnt, epos, M, stmp3, s));
     int64_t EP = 0;
     HIPCHK(hipMemcpyAsync(&EP, epos + M, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int64_t EPa = std::max<int64_t>(EP, 1);
-    uint64_t *ek = mem.get<uint64_t>(EPa), *ek2 = mem.get<uint64_t>(EPa);
-    uint32_t *ev1 = mem.get<uint32_t>(EPa), *ev2 = mem.get<uint32_t>(EPa);
-    void *sortmp3 = mem.get<char>(sort_temp_bytes(EPa));
+    uint64_t *ek = lm.get<uint64_t>(EPa), *ek2 = lm.get<uint64_t>(EPa);
+    uint32_t *ev1 = lm.get<uint32_t>(EPa), *ev2 = lm.get<uint32_t>(EPa);
+    void *sortmp3 = lm.get<char>(sort_temp_bytes(EPa));
     HIPCHK(launch_edge_emit(sp_k, sp_n, M, epos, N, ek, s));
     HIPCHK(hipMemsetAsync(ev1, 0, (size_t)EPa * 4, s));
     HIPCHK(radix_sort_pairs(ek, ev1, ek2, ev2, EP, bits_for((uint64_t)N * (uint64_t)N), sortmp3, &alt, s));
     uint64_t *sek = alt ? ek2 : ek;
-    uint8_t *rs = mem.get<uint8_t>(EPa);
-    int64_t *rr = mem.get<int64_t>(EPa + 1);
-    void *stmp4 = mem.get<char>(scan_temp_bytes(EPa + 1));
+    uint8_t *rs = lm.get<uint8_t>(EPa);
+    int64_t *rr = lm.get<int64_t>(EPa + 1);
+    void *stmp4 = lm.get<char>(scan_temp_bytes(EPa + 1));
     HIPCHK(launch_run_starts(sek, EP, rs, s));
     HIPCHK(launch_scan_u8(rs, rr, EP, stmp4, s));
     int64_t NE = 0;
     HIPCHK(hipMemcpyAsync(&NE, rr + EP, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    int32_t *edges = mem.get<int32_t>(2 * std::max<int64_t>(NE, 1));
-    int32_t *weights = mem.get<int32_t>(std::max<int64_t>(NE, 1));
+    int32_t *edges = lm.get<int32_t>(2 * std::max<int64_t>(NE, 1));
+    int32_t *weights = lm.get<int32_t>(std::max<int64_t>(NE, 1));
     HIPCHK(launch_edge_compact(sek, EP, rr, N, edges, weights, s));
-    ev.mark();                                                      // 7
+    lev.mark();                                                     // 2
 
     // ---- graph to the host
     d2h(g->node_element, node_elem, N, s);
@@ -858,26 +891,31 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         g->stages["slot_core"] = {std::vector<char>((char *)corev.data(), (char *)corev.data() + S + 1), S};
         g->stages.erase("slot_node_raw");
     }
-    st.ms_lens = ev.ms(0, 1);
-    st.ms_bin = ev.ms(1, 2);
-    st.ms_recheck = ev.ms(4, 5);
-    st.ms_cc = ev.ms(5, 6);
-    st.ms_edges = ev.ms(6, 7);
-    st.ms_total = ev.ms(0, 7);
-    st.arena_peak_bytes = mem.bytes();
+    g->stats.ms_lens = ev.ms(0, 1);                                 // the stream has passed every event
+    g->stats.ms_bin = ev.ms(1, 2);
+    g->stats.ms_recheck = ev.ms(4, 5);
+    g->stats.ms_cc = lev.ms(0, 1);
+    g->stats.ms_edges = lev.ms(1, 2);
+    g->stats.ms_total = ev.ms(0, 5) + lev.ms(0, 2);
+    g->stats.arena_peak_bytes = mem.bytes() + lm.bytes();
+    out.gs.push_back(g.release());
+    }
     (void)may_retry;
-    out.g = g.release();
     return Phase::Ok;
 }
 
+// out[0 .. n_levels) receive the graphs (n_levels eps values from eps_list,
+// or P->eps when it is null).
 mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
-                          hipStream_t s, bool may_retry, mapper_graph **out, bool *retry) {
+                          hipStream_t s, bool may_retry, mapper_graph **out, bool *retry,
+                          const double *eps_list = nullptr, int n_levels = 1) {
     *retry = false;
     try {
         HIPCHK(hipSetDevice(ctx->device));
         RunOut ro;
-        run_pipeline(ctx, cloud, P, s, may_retry, ro);
-        *out = ro.g;
+        run_pipeline(ctx, cloud, P, s, may_retry, ro, eps_list, n_levels);
+        for (int lv = 0; lv < n_levels; ++lv) out[lv] = ro.gs[lv];
+        ro.gs.clear();
         return MAPPER_OK;
     } catch (NoMem &nm) {
         (void)hipStreamSynchronize(s);
@@ -1058,6 +1096,23 @@ mapper_status mapper_run(mapper_context *ctx, const mapper_cloud *cloud, const m
     return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry);
 }
 
+static_assert(MAPPER_MAX_EPS_VALUES == mgpu::MAX_LEVELS, "eps values per pass");
+
+mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
+                                   const double *eps_list, int32_t n_eps, mapper_graph **out) {
+    if (!ctx || !out || !eps_list) return fail(MAPPER_EINVAL, "null argument");
+    if (n_eps < 1 || n_eps > MAPPER_MAX_EPS_VALUES) return fail(MAPPER_EINVAL, "n_eps must be in [1, MAPPER_MAX_EPS_VALUES]");
+    for (int t = 0; t < n_eps; ++t) {
+        out[t] = nullptr;
+        if (!(eps_list[t] >= 0.0) || !std::isfinite(eps_list[t]))
+            return fail(MAPPER_EINVAL, "eps values must be finite and >= 0");
+    }
+    mapper_status v = validate(cloud, params);
+    if (v != MAPPER_OK) return v;
+    bool retry;
+    return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry, eps_list, n_eps);
+}
+
 mapper_status mapper_submit(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
                             uint64_t *ticket) {
     if (!ctx || !ticket) return fail(MAPPER_EINVAL, "null argument");
@@ -1167,7 +1222,8 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         pk.n_slots = nrows;
         pk.prec = precision;
         pk.scale = scale;
-        pk.E_scaled = eps * eps * scale * scale;
+        pk.n_levels = 1;
+        pk.E_scaled[0] = eps * eps * scale * scale;
         pk.panel = mem.get<char>((uint64_t)nrows * (uint64_t)panel_row_stride(precision, dp));
         pk.thrA = mem.get<float>(nrows);
         pk.thrB = mem.get<float>(nrows);
@@ -1201,6 +1257,9 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.band = nullptr;
         ta.band_n = mem.get<unsigned long long>(1);
         ta.nseg = 1;
+        ta.n_levels = 1;
+        ta.level_slots = nrows;
+        ta.level_words = (uint64_t)P * TILE_WORDS;
         ta.debug_g = mem.get<float>((uint64_t)nrows * nrows);
         ta.debug_ld = nrows;
         HIPCHK(hipMemsetAsync(ta.count, 0, (size_t)nrows * 4, s));

@@ -217,9 +217,11 @@ __device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC, 1> &acc) {
     }
 }
 
-struct EpiShared {
-    __attribute__((aligned(16))) float thrA[2 * TILE];
-    __attribute__((aligned(16))) float thrB[2 * TILE];
+// LV: eps values (levels) the workgroup can serve; the decisions of one
+// level at a time go through words, bwords and colcnt.
+template <int LV> struct EpiShared {
+    __attribute__((aligned(16))) float thrA[LV][2 * TILE];
+    __attribute__((aligned(16))) float thrB[LV][2 * TILE];
     __attribute__((aligned(16))) uint32_t words[TILE * 4];    // bitmask block: 4 words per row
     __attribute__((aligned(16))) uint32_t bwords[TILE * 4];   // band pairs, same layout
     uint8_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes (<= 32)
@@ -229,21 +231,21 @@ struct EpiShared {
 // gv): the row words of its bitmask and of its band pairs go to LDS, and the
 // lane's column count is added to colc.  FULL: the block lies inside the
 // element and off the diagonal, so no bounds or triangle masks are needed.
-template <bool FULL, bool DEBUG, int BN>
-__device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared &es,
+template <bool FULL, bool DEBUG, int BN, int LV>
+__device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared<LV> &es, int lv,
                                           const f32x16 &gv, int bm, int bn, int wm, int wn, int &colc) {
     const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
     const int cl = (wn * BN + bn) * 32 + li;                // column within the tile
     const int64_t gc = (int64_t)tl.J * TILE + cl;          // element-local column
-    const float Aj = es.thrA[TILE + cl], Bj = es.thrB[TILE + cl];
+    const float Aj = es.thrA[lv][TILE + cl], Bj = es.thrB[lv][TILE + cl];
     const int r0 = wm * 64 + bm * 32 + 4 * lg;             // register v holds row r0 + 8(v/4) + v%4
     f32x4 TA[4], TB[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        TA[q] = *(const f32x4 *)&es.thrA[r0 + 8 * q];
-        TB[q] = *(const f32x4 *)&es.thrB[r0 + 8 * q];
+        TA[q] = *(const f32x4 *)&es.thrA[lv][r0 + 8 * q];
+        TB[q] = *(const f32x4 *)&es.thrB[lv][r0 + 8 * q];
     }
     int word = 0, bword = 0;                               // lane li (< 32): row li of the block
 #pragma unroll
@@ -286,9 +288,10 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
     }
 }
 
-// The band pairs of tile row t (its band words bw) -> FP64 recheck list, in
-// segment blockIdx % nseg (no single counter is shared by the whole launch).
-__device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw) {
+// The band pairs of tile row t (its band words bw) at level lv -> FP64
+// recheck list, in segment blockIdx % nseg (no single counter is shared by
+// the whole launch).
+__device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw, int lv) {
     const int n = __popc(bw.x) + __popc(bw.y) + __popc(bw.z) + __popc(bw.w);
     const int seg = (int)(blockIdx.x % (unsigned)a.nseg);
     int64_t idx = (int64_t)atomicAdd(&a.band_n[seg], (unsigned long long)n);
@@ -303,7 +306,8 @@ __device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl
                 BandPair bp;
                 bp.si = (int32_t)(tl.slot0 + gr);
                 bp.sj = (int32_t)(tl.slot0 + (int64_t)tl.J * TILE + cl);
-                bp.bit = ((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(t * 4 + j)) * 32u + (uint64_t)b;
+                bp.bit = (((uint64_t)tl.blk * TILE_WORDS + (uint64_t)(t * 4 + j)) * 32u + (uint64_t)b) |
+                         ((uint64_t)lv << BAND_LEVEL_SHIFT);
                 a.band[(int64_t)seg * a.band_cap + idx] = bp;
             }
             ++idx;
@@ -326,59 +330,52 @@ __device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
 }
 
 
-// Decisions of the wave's 2 x BN accumulator blocks, then (after a barrier)
-// the 2 KB bitmask block and the neighbour counts: a row's count is the
-// popcount of its four words, a column's the sum of its partials.
-template <int PREC, bool DEBUG, int BN>
-__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC, BN> &acc,
-                                              EpiShared &es, int wm, int wn) {
+// Per level: decisions of the wave's two accumulator blocks, then (after a
+// barrier) the level's 2 KB bitmask block and neighbour counts: a row's count
+// is the popcount of its four words, a column's the sum of its partials.
+template <int PREC, bool DEBUG, int LV>
+__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC, 1> &acc,
+                                              EpiShared<LV> &es, int wm, int wn) {
     if constexpr (Cfg<PREC>::PANELS == 2) {                 // Gram value = hi.hi + cross terms
 #pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < BN; ++bn) acc.c[bm][bn] = acc.c[bm][bn] + acc.x[bm][bn];
+        for (int bm = 0; bm < 2; ++bm) acc.c[bm][0] = acc.c[bm][0] + acc.x[bm][0];
     }
     const bool diag = tl.I == tl.J;
     const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
-    int colc0 = 0, colc1 = 0;
-    if (!DEBUG && full) {
-#pragma unroll
-        for (int blk = 0; blk < 2 * BN; ++blk) {
-            const int bm = blk / BN, bn = blk % BN;
-            epi_block<true, false, BN>(a, tl, es, acc.c[bm][bn], bm, bn, wm, wn, bn ? colc1 : colc0);
-        }
-    } else {                                                // diagonal or ragged tiles (few): one copy
+    const int nlev = LV == 1 ? 1 : a.n_levels;
 #pragma unroll 1
-        for (int blk = 0; blk < 2 * BN; ++blk) {
-            const int bm = blk / BN, bn = blk % BN;
-            int cc = 0;
-            epi_block<false, DEBUG, BN>(a, tl, es, acc_block(acc, blk), bm, bn, wm, wn, cc);
-            if (bn) colc1 += cc;
-            else colc0 += cc;
+    for (int lv = 0; lv < nlev; ++lv) {
+        if (lv > 0) lds_barrier();                          // the previous level's words are stored
+        int colc = 0;
+        if (!DEBUG && full) {
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) epi_block<true, false, 1, LV>(a, tl, es, lv, acc.c[bm][0], bm, 0, wm, wn, colc);
+        } else {                                            // diagonal or ragged tiles (few): one copy
+#pragma unroll 1
+            for (int bm = 0; bm < 2; ++bm)
+                epi_block<false, DEBUG, 1, LV>(a, tl, es, lv, acc_block(acc, bm), bm, 0, wm, wn, colc);
         }
-    }
-    {
         const int lane = lane_id_here();
-        es.colcnt[wm * 2 + (lane >> 5)][wn * 32 * BN + (lane & 31)] = (uint8_t)colc0;
-        if constexpr (BN == 2) es.colcnt[wm * 2 + (lane >> 5)][wn * 64 + 32 + (lane & 31)] = (uint8_t)colc1;
-    }
-    lds_barrier();
-    const int t = (threadIdx.x & ~(WAVE - 1)) + lane_id_here();
-    if (t < 2 * TILE) {
-        uint32_t *dst = a.bitmask + (uint64_t)tl.blk * TILE_WORDS;
-        *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
-        if (t < TILE) {
-            const int64_t r = (int64_t)tl.I * TILE + t;
-            const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
-            const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
-            if (r < tl.ne && c) atomicAdd(&a.count[tl.slot0 + r], c);
-            const u32x4 bw = *(const u32x4 *)(es.bwords + 4 * t);
-            if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw);
-        } else {
-            const int cc = t - TILE;
-            const int64_t gc = (int64_t)tl.J * TILE + cc;
-            const int c = (int)es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
-            if (gc < tl.ne && c) atomicAdd(&a.count[tl.slot0 + gc], c);
+        es.colcnt[wm * 2 + (lane >> 5)][wn * 32 + (lane & 31)] = (uint8_t)colc;
+        lds_barrier();
+        const int t = (threadIdx.x & ~(WAVE - 1)) + lane;
+        if (t < 2 * TILE) {
+            uint32_t *dst = a.bitmask + (uint64_t)lv * a.level_words + (uint64_t)tl.blk * TILE_WORDS;
+            int32_t *cnt = a.count + (int64_t)lv * a.level_slots + tl.slot0;
+            *(uint2 *)(dst + 2 * t) = *(const uint2 *)(es.words + 2 * t);
+            if (t < TILE) {
+                const int64_t r = (int64_t)tl.I * TILE + t;
+                const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
+                const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
+                if (r < tl.ne && c) atomicAdd(&cnt[r], c);
+                const u32x4 bw = *(const u32x4 *)(es.bwords + 4 * t);
+                if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw, lv);
+            } else {
+                const int cc = t - TILE;
+                const int64_t gc = (int64_t)tl.J * TILE + cc;
+                const int c = (int)es.colcnt[0][cc] + es.colcnt[1][cc] + es.colcnt[2][cc] + es.colcnt[3][cc];
+                if (gc < tl.ne && c) atomicAdd(&cnt[gc], c);
+            }
         }
     }
 }
@@ -387,8 +384,8 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
 // columns 32 wn .. + 31 (two 32 x 32 accumulator blocks).  Double-buffered
 // stages filled by LDS-direct loads: the next stage loads while the current
 // one feeds the matrix cores.
-template <int PREC, bool DEBUG>
-__device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared &es) {
+template <int PREC, bool DEBUG, int LV>
+__device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages, EpiShared<LV> &es) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wm = w >> 2, wn = w & 3;
@@ -398,14 +395,19 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
     GridFeed feed;
     grid_setup(a, tl, w, lane, stride, feed);
     grid_issue(feed, st_lds, w, 0);
-    // thresholds of the tile's rows and columns (read in the epilogue)
+    // thresholds of the tile's rows and columns at every level (read in the epilogue)
     if (threadIdx.x < 2 * TILE) {
         const int t = threadIdx.x;
         const int64_t rw = (t < TILE ? (int64_t)tl.I : (int64_t)tl.J) * TILE + (t & (TILE - 1));
         const int64_t slot = tl.slot0 + (rw < tl.ne ? rw : tl.ne - 1);
-        const float ta = a.thrA[slot], tb = a.thrB[slot];
-        es.thrA[t] = ta;
-        es.thrB[t] = tb;
+#pragma unroll
+        for (int lv = 0; lv < LV; ++lv) {
+            if (lv == 0 || lv < a.n_levels) {
+                const float ta = a.thrA[lv * a.level_slots + slot], tb = a.thrB[lv * a.level_slots + slot];
+                es.thrA[lv][t] = ta;
+                es.thrB[lv][t] = tb;
+            }
+        }
     }
     Acc<PREC, 1> acc;
     GridOps ops;
@@ -418,13 +420,15 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
         if (st == 0) grid_mfma<PREC, true>(ops, acc);
         else grid_mfma<PREC, false>(ops, acc);
     }
-    tile_epilogue<PREC, DEBUG, 1>(a, tl, acc, es, wm, wn);
+    tile_epilogue<PREC, DEBUG, LV>(a, tl, acc, es, wm, wn);
 }
 
-template <int PREC, bool DEBUG>
+// LV = 1: one eps value; LV = MAX_LEVELS: up to that many (a parameter sweep
+// served by one pass over the tiles).
+template <int PREC, bool DEBUG, int LV>
 __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     __shared__ __attribute__((aligned(1024))) char stages[2 * GSTAGE];
-    __shared__ EpiShared es;
+    __shared__ EpiShared<LV> es;
     // XCD-aware order: the hardware deals workgroups round-robin to the 8
     // XCDs, so consecutive tile pairs (which share row panels) are mapped to
     // one XCD and its L2.
@@ -433,7 +437,7 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (item >= a.tt.n_items) return;
     const TilePos tl = tile_lookup(a.tt, item);
-    process_tile<PREC, DEBUG>(a, tl, stages, es);
+    process_tile<PREC, DEBUG, LV>(a, tl, stages, es);
 }
 
 __global__ void k_build_items(TileTable tt, TileItem *items) {
@@ -454,8 +458,10 @@ template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
     const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
-    if (a.debug_g) k_tiles<PREC, true><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
-    else k_tiles<PREC, false><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
+    if (a.n_levels < 1 || a.n_levels > MAX_LEVELS || (a.debug_g && a.n_levels != 1)) return hipErrorInvalidValue;
+    if (a.debug_g) k_tiles<PREC, true, 1><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
+    else if (a.n_levels == 1) k_tiles<PREC, false, 1><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
+    else k_tiles<PREC, false, MAX_LEVELS><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
     return hipGetLastError();
 }
 

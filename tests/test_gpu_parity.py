@@ -270,6 +270,7 @@ def test_band_list_regrows(ctx):
         cloud.destroy()
     assert g.stats["tile_launches"] > 1, g.stats
     assert g.stats["band_pairs"] > 16 * g.stats["tiles"], g.stats
+    assert g.stats["ms_recheck"] > 0 and g.stats["ms_tiles"] > 0 and g.stats["ms_cc"] > 0, g.stats
     same_graph(g, oracle_graph(w.X, params))
 
 
@@ -297,6 +298,55 @@ def test_balanced_cover(ctx, case):
         params = synth.Params([synth.Axis(1, 8, 0.1, cover=1)], eps=2.0, min_pts=1,
                               precision=synth.PREC_FP32)
     run_and_compare(ctx, X, params)
+
+
+@pytest.mark.parametrize("case", ["d64_fp32", "d256_bf16x3", "grid2d_fp16", "bf16_close_eps"])
+def test_eps_sweep(ctx, case):
+    """One pass for several eps values (any order, repeats allowed) gives for
+    each value the oracle's graph and stages (counts, core flags, node of
+    every slot); close values share band pairs, each re-decided per value."""
+    import copy
+    if case == "d64_fp32":
+        w = synth.mixture_100k_d64(scale=0.05)
+        params, eps = with_prec(w.params, synth.PREC_FP32), [12.5, 9.0, 15.0, 12.5]
+    elif case == "d256_bf16x3":
+        w = synth.mixture_1m_d256(scale=0.004, precision=synth.PREC_BF16X3)
+        params, eps = w.params, [24.0, 22.6, 25.5]
+    elif case == "grid2d_fp16":
+        w = synth.mixture_500k_d128_2d(scale=0.01, precision=synth.PREC_FP16)
+        params, eps = w.params, [17.0, 15.0, 19.0, 21.0]
+    else:
+        w = synth.mixture_1m_d256(scale=0.004, precision=synth.PREC_BF16)
+        params, eps = w.params, [24.0, 24.01]
+    print(f"[case] eps sweep {case} {eps}", flush=True)
+    cloud = ctx.cloud(w.X)
+    try:
+        gs = cloud.run_eps_sweep(params, eps, debug=True)
+        single = cloud.run(copy.copy(params), debug=False)
+    finally:
+        cloud.destroy()
+    assert len(gs) == len(eps)
+    for e, g in zip(eps, gs):
+        p = copy.copy(params)
+        p.eps = e
+        ref = oracle_graph(w.X, p)
+        same_stages(g, ref, len(p.axes))
+        same_graph(g, ref)
+    same_graph(single, gs[0])
+
+
+def test_eps_sweep_errors(ctx):
+    from paper_2011_03209_amd import binding
+    w = synth.mixture_100k_d64(scale=0.01)
+    cloud = ctx.cloud(w.X)
+    try:
+        for bad in ([], [1.0] * (binding.MAX_EPS_VALUES + 1), [1.0, -2.0], [float("nan")]):
+            with pytest.raises(binding.MapperError):
+                cloud.run_eps_sweep(w.params, bad)
+        g = cloud.run_eps_sweep(w.params, [w.params.eps])[0]      # one value: the plain run
+        same_graph(g, cloud.run(w.params))
+    finally:
+        cloud.destroy()
 
 
 def test_determinism_and_permutation(ctx):
