@@ -551,6 +551,47 @@ int orc_all_d2(const float *X, int64_t n, int32_t d, const int32_t *rows, int64_
     return 0;
 }
 
+/* k-th nearest-neighbour squared distances (the eps-selection module of the
+ * CIFAR-10 use case plots the distribution of the distances to the k-th
+ * nearest neighbour).  out[i] = the k-th smallest canonical D(x_i, x_j) over
+ * the other points j != i, ties counted with multiplicity, 1 <= k <= n-1.
+ * The k smallest values of a row are kept in a sorted array. */
+int orc_knn_d2(const float *X, int64_t n, int32_t d, int32_t k, double *out)
+{
+    if (!X || !out || n < 2 || d < 1 || k < 1 || (int64_t)k > n - 1) return ORC_EINVAL;
+    double *XT = (double *)malloc(sizeof(double) * (size_t)n * (size_t)d);
+    if (!XT) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < d; ++j) XT[(int64_t)j * n + i] = (double)X[i * (int64_t)d + j];
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *D = (double *)malloc(sizeof(double) * (size_t)n);
+        double *best = (double *)malloc(sizeof(double) * (size_t)k);
+        if (!D || !best) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t a = 0; a < n; ++a) {
+                row_d2(XT, n, d, a, 0, n, D);
+                for (int32_t q = 0; q < k; ++q) best[q] = INFINITY;
+                for (int64_t b = 0; b < n; ++b) {
+                    if (b == a || !(D[b] < best[k - 1])) continue;
+                    int32_t q = k - 1;                  /* insertion into the sorted k smallest */
+                    while (q > 0 && best[q - 1] > D[b]) { best[q] = best[q - 1]; --q; }
+                    best[q] = D[b];
+                }
+                out[a] = best[k - 1];
+            }
+        }
+        free(D);
+        free(best);
+    }
+    free(XT);
+    return fail ? ORC_ENOMEM : 0;
+}
+
 /* Squared distance of one pair by the canonical chain (for pins and for the
  * tolerance tests of the GPU tiles). */
 double orc_pair_d2(const float *x, const float *y, int32_t d)

@@ -90,6 +90,9 @@ def lib():
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
         L.orc_dbscan.restype = ctypes.c_int64
+        L.orc_knn_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_double)]
+        L.orc_knn_d2.restype = ctypes.c_int
         L.orc_pair_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                   ctypes.c_int32]
         L.orc_pair_d2.restype = ctypes.c_double
@@ -257,6 +260,17 @@ def dbscan(X: np.ndarray, members: np.ndarray, eps: float, min_pts: int):
     if rc < 0:
         raise OracleError(int(rc))
     return cnt[:nk], core[:nk].astype(bool), cid[:nk]
+
+
+def knn_d2(X: np.ndarray, k: int) -> np.ndarray:
+    """k-th smallest canonical squared distance from each point to the others."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    out = np.zeros(n, np.float64)
+    rc = lib().orc_knn_d2(_p(X, ctypes.c_float), n, d, int(k), _p(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
 
 
 def pair_d2(x: np.ndarray, y: np.ndarray) -> float:

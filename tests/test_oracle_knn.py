@@ -1,0 +1,70 @@
+"""Pins of the oracle's k-th nearest-neighbour distances (CPU).
+
+- exact rational brute force on dyadic-grid inputs (every FP64 step of the
+  canonical chain is then exact, so the k-th smallest must agree exactly);
+- DBSCAN's core rule: with one interval and minPts = k + 1 a point is core
+  (neighbour count, self included, >= minPts) exactly when its k-th nearest
+  other point lies within eps, so knn_d2 <= eps^2 must equal the pinned
+  mapper oracle's core flags;
+- k = 1 against scipy's k-d tree nearest neighbour;
+- duplicated points: the k-th distance is 0 while k < the copies;
+- monotone in k.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from oracle import oracle as O
+from paper_2011_03209_amd import synth
+
+
+def dyadic_cloud(seed, n, d):
+    rng = np.random.default_rng(seed)
+    return (rng.integers(-16, 17, size=(n, d)) / 8.0).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_exact_bruteforce(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, d = int(rng.integers(2, 40)), int(rng.integers(1, 5))
+    X = dyadic_cloud(seed, n, d)
+    F = [[Fraction(float(v)) for v in row] for row in X]
+    for k in sorted({1, min(3, n - 1), n - 1}):
+        got = O.knn_d2(X, k)
+        for i in range(n):
+            ds = sorted(sum((a - b) ** 2 for a, b in zip(F[i], F[j])) for j in range(n) if j != i)
+            assert got[i] == float(ds[k - 1]), (i, k)
+
+
+@pytest.mark.parametrize("k", [1, 4, 9])
+def test_core_rule(k):
+    w = synth.mixture_100k_d64(scale=0.01)
+    X = np.ascontiguousarray(w.X[:, :8])
+    kd = O.knn_d2(X, k)
+    eps = float(np.sqrt(np.median(kd)))                               # about half the points core
+    params = synth.Params([synth.Axis(1, 1, 0.0)], eps=eps, min_pts=k + 1)
+    g = O.mapper(X, params)
+    core = g.slot_core.astype(bool)[np.argsort(g.elem_members)]      # one element: every point once
+    assert core.size == X.shape[0]
+    assert np.array_equal(core, kd <= eps * eps)
+    assert 0 < core.sum() < X.shape[0]                                # the rule is exercised both ways
+
+
+def test_nearest_neighbour_kdtree():
+    X = dyadic_cloud(7, 500, 3)
+    X = np.unique(X, axis=0)                                          # distinct points
+    dist, _ = cKDTree(X.astype(np.float64)).query(X.astype(np.float64), k=2)
+    got = np.sqrt(O.knn_d2(X, 1))
+    assert np.allclose(got, dist[:, 1], rtol=1e-15, atol=0)
+
+
+def test_duplicates_and_monotone():
+    base = np.random.default_rng(3).normal(size=(50, 6)).astype(np.float32)
+    X = np.repeat(base, 4, axis=0)                                    # every point four times
+    assert np.all(O.knn_d2(X, 3) == 0.0)
+    assert np.all(O.knn_d2(X, 4) > 0.0)
+    ks = [O.knn_d2(X, k) for k in (1, 2, 4, 7, 12)]
+    for a, b in zip(ks, ks[1:]):
+        assert np.all(a <= b)
