@@ -197,6 +197,16 @@ def main():
                           "ms_recheck": gs4[0].stats["ms_recheck"],
                           "ms_cc_each": [gg.stats["ms_cc"] for gg in gs4],
                           "nodes": [gg.n_nodes for gg in gs4]}), file=sys.stderr, flush=True)
+        sub = ctx.cloud(np.ascontiguousarray(w.X[:100_000]))
+        sub.knn_d2(5, prec)
+        t0 = time.perf_counter()
+        kd, kst = sub.knn_d2(5, prec)
+        t1 = time.perf_counter()
+        sub.destroy()
+        print(json.dumps({"sweep": f"knn k=5 100000x256 {args.precision}", "s": t1 - t0,
+                          "ms_screen": kst["ms_tiles"], "ms_fp64": kst["ms_recheck"],
+                          "candidates": kst["band_pairs"], "pairs": kst["pairs"],
+                          "median_knn_d": float(np.sqrt(np.median(kd)))}), file=sys.stderr, flush=True)
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}

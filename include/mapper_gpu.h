@@ -177,6 +177,20 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
                                    const mapper_params *params, const double *eps_list,
                                    int32_t n_eps, mapper_graph **out);
 
+/* --- k-th nearest-neighbour distances, synchronous -----------------------
+ * The eps-selection module of the CIFAR-10 use case (Case Studies section)
+ * plots the distribution of every point's distance to its k-th nearest
+ * neighbour to choose eps.  out_d2[i] (host, n doubles) = the k-th smallest
+ * canonical squared distance D(x_i, x_j) over the other points j != i, ties
+ * counted with multiplicity; D is the FP64 chain of the eps tiles (x_j - y_j
+ * in FP64, fma in coordinate order), so the result is exact and does not
+ * depend on `precision` (a MAPPER_PREC_*, AUTO = BF16X3), which only sets
+ * the matrix-core screening pass.  1 <= k <= min(16, n - 1).  stats may be
+ * NULL; ms_tiles is the two screening passes, ms_recheck the FP64 step,
+ * band_pairs the candidate pairs it evaluated. */
+mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int32_t k,
+                            int32_t precision, double *out_d2, mapper_run_stats *stats);
+
 /* --- serving: continuous batching of requests ---------------------------
  * submit returns at once with a ticket; requests are admitted while their
  * workspace fits in the arena and a stream slot is free, and run

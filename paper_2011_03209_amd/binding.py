@@ -75,6 +75,8 @@ EXPORTS = {
                             ctypes.c_int),
     "mapper_cloud_destroy": ([_vp], ctypes.c_int),
     "mapper_run": ([_vp, _vp, _P(_Params), _P(_vp)], ctypes.c_int),
+    "mapper_knn_d2": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double), _P(RunStats)],
+                      ctypes.c_int),
     "mapper_run_eps_sweep": ([_vp, _vp, _P(_Params), _P(ctypes.c_double), ctypes.c_int32, _P(_vp)],
                              ctypes.c_int),
     "mapper_submit": ([_vp, _vp, _P(_Params), _P(ctypes.c_uint64)], ctypes.c_int),
@@ -304,6 +306,15 @@ class Cloud:
         out = (_vp * len(eps_list))()
         _check(self.ctx.L.mapper_run_eps_sweep(self.ctx.h, self.h, ctypes.byref(p), eps, len(eps_list), out))
         return [_take_graph(_vp(out[t])) for t in range(len(eps_list))]
+
+    def knn_d2(self, k: int, precision: int = 5):
+        """k-th smallest canonical squared distance from every point to the
+        others (exact); returns (values, stats dict)."""
+        out = np.zeros(self.n, np.float64)
+        st = RunStats()
+        _check(self.ctx.L.mapper_knn_d2(self.ctx.h, self.h, int(k), int(precision),
+                                        out.ctypes.data_as(_P(ctypes.c_double)), ctypes.byref(st)))
+        return out, st.as_dict()
 
     def submit(self, params, debug: bool = False) -> int:
         _check_axes(params, self.n, self.d)

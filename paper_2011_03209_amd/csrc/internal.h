@@ -218,6 +218,25 @@ struct TileArgs {
     int64_t debug_ld;
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
+// k-th nearest-neighbour squared distances over the whole cloud (tile.hip).
+constexpr int KNN_KMAX = 16;         // largest k
+
+struct KnnArgs {
+    TileArgs t;                        // panel, dp (the Gram tiles)
+    int64_t n;                         // points (= slots, identity map)
+    int32_t T, C;                      // row blocks; column-block chunks per row block
+    const float *hU, *hL;              // per point, scaled (packing thresholds at eps = 0)
+    float *part;                       // pass 1: per (chunk, row, quarter) the 16 smallest U
+    const float *thr;                  // pass 2: T_i
+    int32_t *cand, *ccnt;              // pass 2: candidates of row i at i * cmax, their count
+    int32_t cmax;
+};
+
+hipError_t launch_knn_pass(int prec, int pass, const KnnArgs &a, hipStream_t s);
+hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, int32_t k, float *thr,
+                            hipStream_t s);
+hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
+                            const int32_t *ccnt, int32_t cmax, double *out, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
 int tile_grid_size(int prec, int64_t n_items);

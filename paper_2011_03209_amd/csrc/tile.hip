@@ -440,6 +440,184 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     process_tile<PREC, DEBUG, LV>(a, tl, stages, es);
 }
 
+// ------------------------------------------------------------------- k-NN
+// k-th nearest-neighbour squared distances over the whole cloud (the
+// eps-selection module of the CIFAR-10 use case plots their distribution).
+// Same Gram tiles and certified error bound as the eps tiles, over the full
+// T x T grid of 128-row blocks: with hU_s >= |x_s|^2/2 + e_s and
+// hL_s <= |x_s|^2/2 - e_s (the packing thresholds at eps = 0),
+//   L_ij = 2 (hL_i + hL_j - g) <= D_ij <= U_ij = 2 (hU_i + hU_j - g),
+// each evaluated in FP32 with a relative margin 2^-22 (|S| + |g|) that covers
+// its two roundings.  Pass 1: T_i = k-th smallest U_ij (j != i) >= the true
+// k-th smallest D.  Pass 2: every j with L_ij <= T_i is a candidate; that
+// set holds every j with D_ij <= the k-th smallest D, so the k-th smallest
+// canonical FP64 D over the candidates (k_knn_final) is the exact answer.
+//
+// A workgroup owns row block I and a chunk of column blocks.  After each
+// tile's products the bounds go to LDS (the stage buffers, free by then),
+// row r at rotation r so the row scans below are free of bank conflicts;
+// thread t then scans row t % 128, columns 32 (t / 128) .. + 31.
+__device__ __forceinline__ int knn_off(int r, int c) { return r * TILE + ((c + r) & (TILE - 1)); }
+
+// b: the 16 smallest values seen, ascending; insert u (dropping the largest).
+__device__ __forceinline__ void top16_insert(float (&b)[KNN_KMAX], float u) {
+#pragma unroll
+    for (int q = KNN_KMAX - 1; q > 0; --q) b[q] = fminf(b[q], fmaxf(b[q - 1], u));
+    b[0] = fminf(b[0], u);
+}
+
+template <int PREC, int PASS>
+__global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
+    __shared__ __attribute__((aligned(1024))) char stages[2 * GSTAGE];   // also the bound tile
+    __shared__ float hI[TILE], hJ[TILE];
+    float *U = (float *)stages;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wm = w >> 2, wn = w & 3;
+    const int I = (int)(blockIdx.x / (unsigned)a.C), ch = (int)(blockIdx.x % (unsigned)a.C);
+    const int J0 = (int)((int64_t)ch * a.T / a.C), J1 = (int)((int64_t)(ch + 1) * a.T / a.C);
+    const int r = threadIdx.x & (TILE - 1), qtr = threadIdx.x >> 7;
+    const int64_t grow = (int64_t)I * TILE + r;
+    const bool rvalid = grow < a.n;
+    const float *hsrc = PASS == 1 ? a.hU : a.hL;
+    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.t.dp);
+    const int nst = (int)(panel_row_bytes(PREC, a.t.dp) / GROW);
+    const uint32_t st_lds = lds_addr(stages);
+    float best[KNN_KMAX];
+#pragma unroll
+    for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inff();
+    const float thr_r = PASS == 2 ? a.thr[rvalid ? grow : a.n - 1] : 0.f;
+    if (threadIdx.x < TILE) {
+        const int64_t gi = (int64_t)I * TILE + threadIdx.x;
+        hI[threadIdx.x] = hsrc[gi < a.n ? gi : a.n - 1];
+    }
+#pragma unroll 1
+    for (int J = J0; J < J1; ++J) {
+        TilePos tl;
+        tl.e = 0;
+        tl.I = I;
+        tl.J = J;
+        tl.ne = a.n;
+        tl.slot0 = 0;
+        tl.blk = 0;
+        GridFeed feed;
+        grid_setup(a.t, tl, w, lane, stride, feed);
+        grid_issue(feed, st_lds, w, 0);
+        if (threadIdx.x < TILE) {
+            const int64_t gj = (int64_t)J * TILE + threadIdx.x;
+            hJ[threadIdx.x] = hsrc[gj < a.n ? gj : a.n - 1];
+        }
+        Acc<PREC, 1> acc;
+        GridOps ops;
+#pragma unroll 1
+        for (int st = 0; st < nst; ++st) {
+            vm_wait<0>();
+            lds_barrier();
+            if (st + 1 < nst) grid_issue(feed, st_lds + (uint32_t)(((st + 1) & 1) * GSTAGE), w, (uint32_t)(st + 1) * GROW);
+            grid_read<PREC>(stages + (st & 1) * GSTAGE, ops, wm, wn);
+            if (st == 0) grid_mfma<PREC, true>(ops, acc);
+            else grid_mfma<PREC, false>(ops, acc);
+        }
+        if constexpr (Cfg<PREC>::PANELS == 2) {
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) acc.c[bm][0] = acc.c[bm][0] + acc.x[bm][0];
+        }
+        lds_barrier();                                      // every wave is done with the stages
+        {
+            const int li = lane_id_here();
+            const int col = wn * 32 + (li & 31);
+            const float hj = hJ[col];
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * (li >> 5) + (v & 3);
+                    const float g = acc.c[bm][0][v];
+                    const float S = hI[row] + hj;
+                    const float m = 0x1.0p-22f * (fabsf(S) + fabsf(g));
+                    U[knn_off(row, col)] = PASS == 1 ? 2.f * ((S - g) + m) : 2.f * ((S - g) - m);
+                }
+        }
+        lds_barrier();
+        if (rvalid) {
+#pragma unroll 4
+            for (int i = 0; i < 32; ++i) {
+                const int col = 32 * qtr + i;
+                const int64_t gcol = (int64_t)J * TILE + col;
+                if (gcol >= a.n || gcol == grow) continue;
+                const float u = U[knn_off(r, col)];
+                if constexpr (PASS == 1) {
+                    if (u < best[KNN_KMAX - 1]) top16_insert(best, u);
+                } else {
+                    if (u <= thr_r) {
+                        const int slot = atomicAdd(&a.ccnt[grow], 1);
+                        if (slot < a.cmax) a.cand[grow * a.cmax + slot] = (int32_t)gcol;
+                    }
+                }
+            }
+        }
+        lds_barrier();                                      // the bound tile is read; stages free
+    }
+    if constexpr (PASS == 1) {
+        const int64_t rows = (int64_t)a.T * TILE;
+        float *dst = a.part + (((int64_t)ch * rows + grow) * 4 + qtr) * KNN_KMAX;
+#pragma unroll
+        for (int q = 0; q < KNN_KMAX; ++q) dst[q] = best[q];
+    }
+}
+
+// T_i = the k-th smallest of row i's partial lists (chunks x quarters).
+__global__ void k_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, int32_t k, float *thr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float best[KNN_KMAX];
+#pragma unroll
+    for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inff();
+    const int64_t rows = (int64_t)T * TILE;
+    for (int c = 0; c < C; ++c)
+        for (int qt = 0; qt < 4; ++qt) {
+            const float *src = part + (((int64_t)c * rows + i) * 4 + qt) * KNN_KMAX;
+            for (int q = 0; q < KNN_KMAX; ++q) {
+                const float u = src[q];
+                if (u < best[KNN_KMAX - 1]) top16_insert(best, u);
+            }
+        }
+    float kth = best[0];
+#pragma unroll
+    for (int q = 1; q < KNN_KMAX; ++q) kth = q == k - 1 ? best[q] : kth;
+    thr[i] = kth;
+}
+
+// The exact answer: canonical FP64 D (x_j - y_j in FP64, fma in index
+// order) over row i's candidates, k-th smallest.
+__global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
+                            const int32_t *ccnt, int32_t cmax, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int cnt = ccnt[i] < cmax ? ccnt[i] : cmax;
+    double best[KNN_KMAX];
+#pragma unroll
+    for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inf();
+    const float *x = X + i * d;
+    for (int s = 0; s < cnt; ++s) {
+        const float *y = X + (int64_t)cand[i * cmax + s] * d;
+        double D = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double t = (double)x[j] - (double)y[j];
+            D = __builtin_fma(t, t, D);
+        }
+        if (D < best[KNN_KMAX - 1]) {
+#pragma unroll
+            for (int q = KNN_KMAX - 1; q > 0; --q) best[q] = fmin(best[q], fmax(best[q - 1], D));
+            best[0] = fmin(best[0], D);
+        }
+    }
+    double kth = best[0];
+#pragma unroll
+    for (int q = 1; q < KNN_KMAX; ++q) kth = q == k - 1 ? best[q] : kth;
+    out[i] = kth;
+}
+
 __global__ void k_build_items(TileTable tt, TileItem *items) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= tt.n_items) return;
@@ -481,6 +659,38 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
     case P_FP16X3: return launch_t<P_FP16X3>(a, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int PREC>
+hipError_t launch_knn_t(int pass, const KnnArgs &a, hipStream_t s) {
+    const unsigned G = (unsigned)((int64_t)a.T * a.C);
+    if (pass == 1) k_knn<PREC, 1><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    else k_knn<PREC, 2><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_pass(int prec, int pass, const KnnArgs &a, hipStream_t s) {
+    if (a.n < 2 || a.T < 1 || a.C < 1 || (pass != 1 && pass != 2)) return hipErrorInvalidValue;
+    switch (prec) {
+    case P_FP32: return launch_knn_t<P_FP32>(pass, a, s);
+    case P_BF16: return launch_knn_t<P_BF16>(pass, a, s);
+    case P_BF16X3: return launch_knn_t<P_BF16X3>(pass, a, s);
+    case P_FP16: return launch_knn_t<P_FP16>(pass, a, s);
+    case P_FP16X3: return launch_knn_t<P_FP16X3>(pass, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, int32_t k, float *thr,
+                            hipStream_t s) {
+    k_knn_merge<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(part, C, T, n, k, thr);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
+                            const int32_t *ccnt, int32_t cmax, double *out, hipStream_t s) {
+    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s) {

@@ -1,0 +1,73 @@
+"""k-th nearest-neighbour squared distances on the GPU (certified matrix-core
+screening, FP64 canonical distances of the candidates) against the oracle:
+bit-exact, every precision, ragged sizes, widths that are and are not
+multiples of a stage, duplicated points (candidate lists that must grow)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_03209_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2011_03209_amd import binding
+    c = binding.Context(arena_bytes=24 << 30)
+    yield c
+    c.close()
+
+
+def run(ctx, X, k, prec):
+    print(f"[case] knn n={X.shape[0]} d={X.shape[1]} k={k} prec={prec}", flush=True)
+    cloud = ctx.cloud(X)
+    try:
+        got, st = cloud.knn_d2(k, prec)
+    finally:
+        cloud.destroy()
+    ref = O.knn_d2(X, k)
+    assert np.array_equal(got, ref), (np.flatnonzero(got != ref)[:5], got[got != ref][:5], ref[got != ref][:5])
+    return st
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16, synth.PREC_BF16X3,
+                                  synth.PREC_FP16, synth.PREC_FP16X3])
+def test_precisions(ctx, prec):
+    X = synth.mixture_100k_d64(scale=0.03).X                       # 3000 x 64, clustered
+    st = run(ctx, X, 5, prec)
+    assert st["band_pairs"] >= 5 * X.shape[0]
+
+
+@pytest.mark.parametrize("n,d,k,prec", [(300, 3, 1, synth.PREC_FP32), (129, 40, 16, synth.PREC_BF16X3),
+                                        (2500, 40, 7, synth.PREC_FP16), (5000, 256, 16, synth.PREC_BF16X3),
+                                        (2, 5, 1, synth.PREC_FP16X3)])
+def test_shapes(ctx, n, d, k, prec):
+    X = np.random.default_rng(n + d).normal(size=(n, d)).astype(np.float32)
+    run(ctx, X, k, prec)
+
+
+def test_mixture_d256(ctx):
+    X = synth.mixture_1m_d256(scale=0.012).X                       # 12000 x 256
+    run(ctx, X, 5, synth.PREC_BF16X3)
+
+
+def test_duplicates_grow_candidate_lists(ctx):
+    base = np.random.default_rng(4).normal(size=(30, 16)).astype(np.float32)
+    X = np.repeat(base, 100, axis=0)                               # 99 exact copies of every point
+    st = run(ctx, X, 5, synth.PREC_BF16)
+    assert st["tile_launches"] > 1, st
+
+
+def test_errors(ctx):
+    from paper_2011_03209_amd import binding
+    X = np.random.default_rng(1).normal(size=(10, 4)).astype(np.float32)
+    cloud = ctx.cloud(X)
+    try:
+        for k in (0, 10, 17):
+            with pytest.raises(binding.MapperError):
+                cloud.knn_d2(k)
+        with pytest.raises(binding.MapperError):
+            cloud.knn_d2(3, 9)
+    finally:
+        cloud.destroy()
