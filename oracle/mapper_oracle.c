@@ -22,7 +22,10 @@
  *            L2: sqrt(S) with S = sum_j x_j*x_j accumulated in j order in FP64
  *            (each product of two floats is exact in FP64) and a correctly
  *            rounded sqrt;  projection on a float vector v: sum_j x_j*v_j in
- *            j order in FP64;  values: given.
+ *            j order in FP64;  values: given;  k-NN distance (a density
+ *            lens): sqrt of the k-th smallest D(x, y) over the other points,
+ *            k = the axis' column field;  eccentricity (L-inf): sqrt of the
+ *            largest D(x, y) over the other points.
  *   cover    L = (M-m)/(n-(n-1)p), s = L(1-p), lo_k = m + k s,
  *            hi_k = lo_k + L (k < n-1), hi_{n-1} = M; closed intervals.
  *   balanced the same formula on the rank axis [0, N-1] of the sorted lens
@@ -54,7 +57,8 @@
 #define ORC_ENOMEM (-2)
 
 enum { ORC_LENS_COLUMN = 0, ORC_LENS_L2 = 1, ORC_LENS_LINF = 2,
-       ORC_LENS_PROJECTION = 3, ORC_LENS_VALUES = 4 };
+       ORC_LENS_PROJECTION = 3, ORC_LENS_VALUES = 4,
+       ORC_LENS_KNN_DISTANCE = 5, ORC_LENS_ECCENTRICITY = 6 };
 
 typedef struct {
     int32_t kind;
@@ -82,6 +86,9 @@ typedef struct {
     uint8_t *slot_core;       /* 1 if core */
     int32_t *slot_node;       /* node id, or -1 for noise */
 } orc_graph;
+
+int orc_knn_d2(const float *X, int64_t n, int32_t d, int32_t k, double *out);
+int orc_ecc_d2(const float *X, int64_t n, int32_t d, double *out);
 
 /* ------------------------------------------------------------------ lens */
 
@@ -358,7 +365,9 @@ int orc_validate(const float *X, int64_t n, int32_t d, int32_t n_axes,
             if (!ax->values) return ORC_EINVAL;
             for (int64_t i = 0; i < n; ++i) if (!isfinite(ax->values[i])) return ORC_EINVAL;
         }
-        if (ax->kind < 0 || ax->kind > 4) return ORC_EINVAL;
+        if (ax->kind < 0 || ax->kind > 6) return ORC_EINVAL;
+        if (ax->kind == ORC_LENS_KNN_DISTANCE && (ax->column < 1 || (int64_t)ax->column > n - 1)) return ORC_EINVAL;
+        if (ax->kind == ORC_LENS_ECCENTRICITY && n < 2) return ORC_EINVAL;
     }
     for (int64_t i = 0; i < n * (int64_t)d; ++i) if (!isfinite(X[i])) return ORC_EINVAL;
     return 0;
@@ -385,7 +394,13 @@ int orc_mapper(const float *X, int64_t n, int32_t d, int32_t n_axes,
     int64_t ioff = 0;
     for (int32_t a = 0; a < n_axes; ++a) {
         f[a] = g->lens + (int64_t)a * n;
-        rc = orc_lens(X, n, d, &axes[a], f[a]);
+        if (axes[a].kind == ORC_LENS_KNN_DISTANCE || axes[a].kind == ORC_LENS_ECCENTRICITY) {
+            rc = axes[a].kind == ORC_LENS_KNN_DISTANCE ? orc_knn_d2(X, n, d, axes[a].column, f[a])
+                                                       : orc_ecc_d2(X, n, d, f[a]);
+            for (int64_t i = 0; i < n && !rc; ++i) f[a][i] = sqrt(f[a][i]);
+        } else {
+            rc = orc_lens(X, n, d, &axes[a], f[a]);
+        }
         if (rc) { orc_graph_free(g); return rc; }
         double m = f[a][0], M = f[a][0];
         for (int64_t i = 1; i < n; ++i) {
@@ -587,6 +602,40 @@ int orc_knn_d2(const float *X, int64_t n, int32_t d, int32_t k, double *out)
         }
         free(D);
         free(best);
+    }
+    free(XT);
+    return fail ? ORC_ENOMEM : 0;
+}
+
+/* The eccentricity lens (Background and Design sections list eccentricity
+ * among the filter functions): the L-infinity eccentricity of a point is its
+ * largest distance to the other points; out[i] = max over j != i of the
+ * canonical D(x_i, x_j) (its square root is the lens). */
+int orc_ecc_d2(const float *X, int64_t n, int32_t d, double *out)
+{
+    if (!X || !out || n < 2 || d < 1) return ORC_EINVAL;
+    double *XT = (double *)malloc(sizeof(double) * (size_t)n * (size_t)d);
+    if (!XT) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < d; ++j) XT[(int64_t)j * n + i] = (double)X[i * (int64_t)d + j];
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *D = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!D) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t a = 0; a < n; ++a) {
+                row_d2(XT, n, d, a, 0, n, D);
+                double m = 0.0;
+                for (int64_t b = 0; b < n; ++b)
+                    if (b != a && D[b] > m) m = D[b];
+                out[a] = m;
+            }
+        }
+        free(D);
     }
     free(XT);
     return fail ? ORC_ENOMEM : 0;

@@ -93,6 +93,9 @@ def lib():
         L.orc_knn_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)]
         L.orc_knn_d2.restype = ctypes.c_int
+        L.orc_ecc_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_double)]
+        L.orc_ecc_d2.restype = ctypes.c_int
         L.orc_pair_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                   ctypes.c_int32]
         L.orc_pair_d2.restype = ctypes.c_double
@@ -268,6 +271,17 @@ def knn_d2(X: np.ndarray, k: int) -> np.ndarray:
     n, d = X.shape
     out = np.zeros(n, np.float64)
     rc = lib().orc_knn_d2(_p(X, ctypes.c_float), n, d, int(k), _p(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def ecc_d2(X: np.ndarray) -> np.ndarray:
+    """Largest canonical squared distance from each point to the others."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    out = np.zeros(n, np.float64)
+    rc = lib().orc_ecc_d2(_p(X, ctypes.c_float), n, d, _p(out, ctypes.c_double))
     if rc != 0:
         raise OracleError(rc)
     return out

@@ -32,6 +32,8 @@ LENS_L2 = 1
 LENS_LINF = 2
 LENS_PROJECTION = 3
 LENS_VALUES = 4
+LENS_KNN_DISTANCE = 5      # sqrt of the k-th nearest-neighbour squared distance (k = column)
+LENS_ECCENTRICITY = 6      # sqrt of the largest squared distance to another point
 
 PREC_FP32 = 0
 PREC_BF16 = 1
