@@ -69,7 +69,14 @@ typedef enum {
     MAPPER_LENS_L2 = 1,          /* f(x) = ||x||_2 */
     MAPPER_LENS_LINF = 2,        /* f(x) = max_j |x_j| */
     MAPPER_LENS_PROJECTION = 3,  /* f(x) = <x, direction> */
-    MAPPER_LENS_VALUES = 4       /* f given per point */
+    MAPPER_LENS_VALUES = 4,      /* f given per point */
+    /* Whole-cloud lenses (the density and eccentricity filters the paper
+     * lists, Background and Design sections), exact in FP64: */
+    MAPPER_LENS_KNN_DISTANCE = 5,  /* f(x) = distance to the k-th nearest other point,
+                                      k = the axis' column field (1..16); small where the
+                                      cloud is dense (see mapper_knn_d2) */
+    MAPPER_LENS_ECCENTRICITY = 6   /* f(x) = largest distance to another point
+                                      (L-infinity eccentricity) */
 } mapper_lens_kind;
 
 typedef enum {
@@ -85,7 +92,7 @@ typedef enum {
  * intervals n, overlap p). */
 typedef struct {
     int32_t kind;            /* mapper_lens_kind */
-    int32_t column;          /* COLUMN: 0 <= column < d */
+    int32_t column;          /* COLUMN: 0 <= column < d; KNN_DISTANCE: k */
     const float *direction;  /* PROJECTION: d floats, host; copied */
     const double *values;    /* VALUES: n doubles, host; copied; finite */
     int32_t n_intervals;     /* >= 1 */

@@ -230,13 +230,16 @@ struct KnnArgs {
     const float *thr;                  // pass 2: T_i
     int32_t *cand, *ccnt;              // pass 2: candidates of row i at i * cmax, their count
     int32_t cmax;
+    int32_t mode;                      // 0: k-th smallest D; 1: largest D (values negated)
 };
 
 hipError_t launch_knn_pass(int prec, int pass, const KnnArgs &a, hipStream_t s);
 hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, int32_t k, float *thr,
                             hipStream_t s);
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, double *out, hipStream_t s);
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out, hipStream_t s);
+// f[i] = sqrt(f[i]) (correctly rounded FP64).
+hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
 int tile_grid_size(int prec, int64_t n_items);

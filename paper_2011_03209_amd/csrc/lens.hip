@@ -149,7 +149,18 @@ __global__ void k_rank_values(const uint64_t *sorted, const int64_t *rank, int32
     out[i] = __longlong_as_double((long long)b) + 0.0;
 }
 
+__global__ void k_sqrt(double *f, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = sqrt(f[i]);
+}
+
 }  // namespace
+
+hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_sqrt<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(f, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_lens_keys(const double *f, int64_t n, uint64_t *keys, uint32_t *vals, hipStream_t s) {
     if (n <= 0) return hipSuccess;

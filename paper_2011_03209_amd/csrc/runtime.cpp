@@ -245,7 +245,11 @@ mapper_status validate(const mapper_cloud *c, const mapper_params *p) {
         if (!(ax.overlap >= 0.0 && ax.overlap < 1.0)) return fail(MAPPER_EINVAL, "overlap must be in [0, 1)");
         if (ax.cover != MAPPER_COVER_UNIFORM && ax.cover != MAPPER_COVER_BALANCED)
             return fail(MAPPER_EINVAL, "cover must be MAPPER_COVER_UNIFORM or MAPPER_COVER_BALANCED");
-        if (ax.kind < 0 || ax.kind > MAPPER_LENS_VALUES) return fail(MAPPER_EINVAL, "bad lens kind");
+        if (ax.kind < 0 || ax.kind > MAPPER_LENS_ECCENTRICITY) return fail(MAPPER_EINVAL, "bad lens kind");
+        if (ax.kind == MAPPER_LENS_KNN_DISTANCE && (ax.column < 1 || ax.column > 16 || (int64_t)ax.column > c->n - 1))
+            return fail(MAPPER_EINVAL, "k-NN distance lens: k (the column field) must be in [1, min(16, n - 1)]");
+        if (ax.kind == MAPPER_LENS_ECCENTRICITY && c->n < 2)
+            return fail(MAPPER_EINVAL, "eccentricity lens needs at least two points");
         if (ax.kind == MAPPER_LENS_COLUMN && (ax.column < 0 || ax.column >= c->d))
             return fail(MAPPER_EINVAL, "lens column out of range");
         if (ax.kind == MAPPER_LENS_PROJECTION) {
@@ -445,6 +449,100 @@ int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneS
     return best;
 }
 
+// k-NN screening and FP64 step on the whole cloud (see k_knn): dout[i]
+// (device) = the k-th smallest canonical D over j != i (mode 0) or the
+// largest (mode 1, k = 1).  Synchronous; its work arrays are released on
+// return.
+void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32_t mode, int prec,
+                double *dout, mapper_run_stats &st, hipStream_t s) {
+    Scope mem(ctx->arena);
+    const int64_t n = cloud->n;
+    const int32_t d = cloud->d;
+    const int32_t T = (int32_t)((n + TILE - 1) / TILE);
+    // column-block chunks: enough workgroups to fill the chip twice over
+    const int32_t C = (int32_t)std::max<int64_t>(1, std::min<int64_t>(T, (4 * ctx->cus + T - 1) / T));
+    st.precision = prec;
+    st.tile_m = st.tile_n = TILE;
+    st.split_terms = prec_is_split(prec) ? 3 : 1;
+    st.pairs = n * (n - 1);
+    st.tiles = 2 * (int64_t)T * T;
+    std::vector<uint32_t> iota((size_t)n);
+    for (int64_t i = 0; i < n; ++i) iota[i] = (uint32_t)i;
+    uint32_t *ident = mem.get<uint32_t>(n);
+    h2d(ident, iota.data(), n, s);
+    double scale = 1.0;
+    if (cloud->maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)cloud->maxabs));
+    const int dp = panel_dp(prec, d);
+    PackArgs pk{};
+    pk.X = cloud->X;
+    pk.d = d;
+    pk.dp = dp;
+    pk.slot_point = ident;
+    pk.n_slots = n;
+    pk.prec = prec;
+    pk.scale = scale;
+    pk.n_levels = 1;
+    pk.E_scaled[0] = 0.0;                               // thresholds at eps = 0: |x|^2/2 +- e
+    pk.panel = mem.get<char>((uint64_t)n * (uint64_t)panel_row_stride(prec, dp));
+    float *hU = mem.get<float>(n), *hL = mem.get<float>(n);
+    pk.thrA = hU;
+    pk.thrB = hL;
+    HIPCHK(launch_pack(pk, s));
+    KnnArgs ka{};
+    ka.t.panel = pk.panel;
+    ka.t.dp = dp;
+    ka.t.n_levels = 1;
+    ka.mode = mode;
+    ka.n = n;
+    ka.T = T;
+    ka.C = C;
+    ka.hU = hU;
+    ka.hL = hL;
+    ka.part = mem.get<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
+    float *thr = mem.get<float>(n);
+    ka.thr = thr;
+    Events ev(s);
+    ev.mark();
+    HIPCHK(launch_knn_pass(prec, 1, ka, s));
+    HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
+    ev.mark();
+    int32_t cmax = 64;
+    int32_t *ccnt = mem.get<int32_t>(n);
+    int64_t ncand = 0;
+    for (;;) {
+        Scope cm(ctx->arena);
+        ka.cand = cm.get<int32_t>((uint64_t)n * cmax);
+        ka.ccnt = ccnt;
+        ka.cmax = cmax;
+        Events e2(s);
+        e2.mark();
+        HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
+        HIPCHK(launch_knn_pass(prec, 2, ka, s));
+        e2.mark();
+        HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, mode, dout, s));
+        e2.mark();
+        std::vector<int32_t> cc;
+        d2h(cc, ccnt, n, s);
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t most = 0;
+        ncand = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            most = std::max<int64_t>(most, cc[i]);
+            ncand += cc[i];
+        }
+        st.ms_tiles = ev.ms(0, 1) + e2.ms(0, 1);
+        st.ms_recheck = e2.ms(1, 2);
+        if (most <= cmax) break;
+        if (most > (int64_t)0x7fffffff / std::max<int64_t>(n, 1)) throw NoMem{(uint64_t)most * (uint64_t)n * 4};
+        cmax = (int32_t)most;                           // grow the candidate lists and redo pass 2
+        ++st.tile_launches;
+    }
+    st.tile_launches += 1;
+    st.band_pairs = ncand;
+    st.ms_total = st.ms_tiles + st.ms_recheck;
+    st.arena_peak_bytes = mem.bytes();
+}
+
 // ------------------------------------------------------------------ the run
 enum class Phase { Ok, Retry };
 
@@ -499,7 +597,14 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
             vals = mem.get<double>(n);
             h2d(vals, ax.values, n, s);
         }
-        HIPCHK(launch_lens(cloud->X, n, d, ax.kind, ax.column, dir, vals, f[a], s));
+        if (ax.kind == MAPPER_LENS_KNN_DISTANCE || ax.kind == MAPPER_LENS_ECCENTRICITY) {
+            mapper_run_stats ks{};                          // whole-cloud lens: k-NN screening + FP64
+            const bool ecc = ax.kind == MAPPER_LENS_ECCENTRICITY;
+            knn_device(ctx, cloud, ecc ? 1 : ax.column, ecc ? 1 : 0, P_BF16X3, f[a], ks, s);
+            HIPCHK(launch_sqrt(f[a], n, s));
+        } else {
+            HIPCHK(launch_lens(cloud->X, n, d, ax.kind, ax.column, dir, vals, f[a], s));
+        }
         HIPCHK(launch_range(f[a], n, rk + 2 * a, s));
     }
     std::vector<unsigned long long> rkh;
@@ -1125,93 +1230,10 @@ mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int3
     try {
         HIPCHK(hipSetDevice(ctx->device));
         Scope mem(ctx->arena);
-        const int64_t n = cloud->n;
-        const int32_t d = cloud->d;
-        const int32_t T = (int32_t)((n + TILE - 1) / TILE);
-        // column-block chunks: enough workgroups to fill the chip twice over
-        const int32_t C = (int32_t)std::max<int64_t>(1, std::min<int64_t>(T, (4 * ctx->cus + T - 1) / T));
+        double *dout = mem.get<double>(cloud->n);
         mapper_run_stats st{};
-        st.precision = prec;
-        st.tile_m = st.tile_n = TILE;
-        st.split_terms = prec_is_split(prec) ? 3 : 1;
-        st.pairs = n * (n - 1);
-        st.tiles = 2 * (int64_t)T * T;
-        std::vector<uint32_t> iota((size_t)n);
-        for (int64_t i = 0; i < n; ++i) iota[i] = (uint32_t)i;
-        uint32_t *ident = mem.get<uint32_t>(n);
-        h2d(ident, iota.data(), n, s);
-        double scale = 1.0;
-        if (cloud->maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)cloud->maxabs));
-        const int dp = panel_dp(prec, d);
-        PackArgs pk{};
-        pk.X = cloud->X;
-        pk.d = d;
-        pk.dp = dp;
-        pk.slot_point = ident;
-        pk.n_slots = n;
-        pk.prec = prec;
-        pk.scale = scale;
-        pk.n_levels = 1;
-        pk.E_scaled[0] = 0.0;                               // thresholds at eps = 0: |x|^2/2 +- e
-        pk.panel = mem.get<char>((uint64_t)n * (uint64_t)panel_row_stride(prec, dp));
-        float *hU = mem.get<float>(n), *hL = mem.get<float>(n);
-        pk.thrA = hU;
-        pk.thrB = hL;
-        HIPCHK(launch_pack(pk, s));
-        KnnArgs ka{};
-        ka.t.panel = pk.panel;
-        ka.t.dp = dp;
-        ka.t.n_levels = 1;
-        ka.n = n;
-        ka.T = T;
-        ka.C = C;
-        ka.hU = hU;
-        ka.hL = hL;
-        ka.part = mem.get<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
-        float *thr = mem.get<float>(n);
-        ka.thr = thr;
-        Events ev(s);
-        ev.mark();
-        HIPCHK(launch_knn_pass(prec, 1, ka, s));
-        HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
-        ev.mark();
-        int32_t cmax = 64;
-        int32_t *ccnt = mem.get<int32_t>(n);
-        double *dout = mem.get<double>(n);
-        int64_t ncand = 0;
-        for (;;) {
-            Scope cm(ctx->arena);
-            ka.cand = cm.get<int32_t>((uint64_t)n * cmax);
-            ka.ccnt = ccnt;
-            ka.cmax = cmax;
-            Events e2(s);
-            e2.mark();
-            HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
-            HIPCHK(launch_knn_pass(prec, 2, ka, s));
-            e2.mark();
-            HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, dout, s));
-            e2.mark();
-            std::vector<int32_t> cc;
-            d2h(cc, ccnt, n, s);
-            HIPCHK(hipStreamSynchronize(s));
-            int64_t most = 0;
-            ncand = 0;
-            for (int64_t i = 0; i < n; ++i) {
-                most = std::max<int64_t>(most, cc[i]);
-                ncand += cc[i];
-            }
-            st.ms_tiles = ev.ms(0, 1) + e2.ms(0, 1);
-            st.ms_recheck = e2.ms(1, 2);
-            if (most <= cmax) break;
-            if (most > (int64_t)0x7fffffff / std::max<int64_t>(n, 1)) throw NoMem{(uint64_t)most * (uint64_t)n * 4};
-            cmax = (int32_t)most;                           // grow the candidate lists and redo pass 2
-            ++st.tile_launches;
-        }
-        st.tile_launches += 1;
-        st.band_pairs = ncand;
-        st.ms_total = st.ms_tiles + st.ms_recheck;
-        st.arena_peak_bytes = mem.bytes();
-        HIPCHK(hipMemcpyAsync(out_d2, dout, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        knn_device(ctx, cloud, k, 0, prec, dout, st, s);
+        HIPCHK(hipMemcpyAsync(out_d2, dout, (size_t)cloud->n * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (stats) *stats = st;
         return MAPPER_OK;

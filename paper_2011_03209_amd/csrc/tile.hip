@@ -452,6 +452,9 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
 // k-th smallest D.  Pass 2: every j with L_ij <= T_i is a candidate; that
 // set holds every j with D_ij <= the k-th smallest D, so the k-th smallest
 // canonical FP64 D over the candidates (k_knn_final) is the exact answer.
+// mode 1 (the largest D, for the eccentricity lens) runs the same passes on
+// negated values: -L in pass 1 (its smallest is -max L), -U in pass 2, -D
+// in the final step, k = 1.
 //
 // A workgroup owns row block I and a chunk of column blocks.  After each
 // tile's products the bounds go to LDS (the stage buffers, free by then),
@@ -479,7 +482,9 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
     const int r = threadIdx.x & (TILE - 1), qtr = threadIdx.x >> 7;
     const int64_t grow = (int64_t)I * TILE + r;
     const bool rvalid = grow < a.n;
-    const float *hsrc = PASS == 1 ? a.hU : a.hL;
+    const bool upper = (PASS == 1) != (a.mode == 1);       // which bound this pass needs
+    const float sgn = a.mode == 1 ? -1.f : 1.f;
+    const float *hsrc = upper ? a.hU : a.hL;
     const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.t.dp);
     const int nst = (int)(panel_row_bytes(PREC, a.t.dp) / GROW);
     const uint32_t st_lds = lds_addr(stages);
@@ -535,7 +540,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
                     const float g = acc.c[bm][0][v];
                     const float S = hI[row] + hj;
                     const float m = 0x1.0p-22f * (fabsf(S) + fabsf(g));
-                    U[knn_off(row, col)] = PASS == 1 ? 2.f * ((S - g) + m) : 2.f * ((S - g) - m);
+                    U[knn_off(row, col)] = sgn * (upper ? 2.f * ((S - g) + m) : 2.f * ((S - g) - m));
                 }
         }
         lds_barrier();
@@ -591,7 +596,7 @@ __global__ void k_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 // The exact answer: canonical FP64 D (x_j - y_j in FP64, fma in index
 // order) over row i's candidates, k-th smallest.
 __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, double *out) {
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int cnt = ccnt[i] < cmax ? ccnt[i] : cmax;
@@ -606,6 +611,7 @@ __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
             const double t = (double)x[j] - (double)y[j];
             D = __builtin_fma(t, t, D);
         }
+        if (mode == 1) D = -D;
         if (D < best[KNN_KMAX - 1]) {
 #pragma unroll
             for (int q = KNN_KMAX - 1; q > 0; --q) best[q] = fmin(best[q], fmax(best[q - 1], D));
@@ -615,7 +621,7 @@ __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
     double kth = best[0];
 #pragma unroll
     for (int q = 1; q < KNN_KMAX; ++q) kth = q == k - 1 ? best[q] : kth;
-    out[i] = kth;
+    out[i] = mode == 1 ? -kth : kth;
 }
 
 __global__ void k_build_items(TileTable tt, TileItem *items) {
@@ -688,8 +694,8 @@ hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 }
 
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, double *out, hipStream_t s) {
-    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, out);
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out, hipStream_t s) {
+    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, out);
     return hipGetLastError();
 }
 

@@ -71,3 +71,27 @@ def test_errors(ctx):
             cloud.knn_d2(3, 9)
     finally:
         cloud.destroy()
+
+
+@pytest.mark.parametrize("kind,k,prec", [(synth.LENS_ECCENTRICITY, 0, synth.PREC_BF16X3),
+                                         (synth.LENS_KNN_DISTANCE, 5, synth.PREC_FP16),
+                                         (synth.LENS_KNN_DISTANCE, 1, synth.PREC_FP32)])
+def test_cloud_lens_mapper(ctx, kind, k, prec):
+    """The eccentricity and k-NN distance lenses feed the whole mapper: the
+    GPU's lens values are the oracle's bit for bit, and so is the graph."""
+    w = synth.mixture_100k_d64(scale=0.03)
+    X = np.ascontiguousarray(w.X[:, :32])
+    params = synth.Params([synth.Axis(kind, 8, 0.3, column=k)], eps=7.0, min_pts=5, precision=prec)
+    print(f"[case] cloud lens kind={kind} k={k} prec={prec}", flush=True)
+    cloud = ctx.cloud(X)
+    try:
+        g = cloud.run(params, debug=True)
+    finally:
+        cloud.destroy()
+    ref = O.mapper(X, params)
+    assert g.stages["lens"].view(np.uint64).tolist() == ref.lens.reshape(-1).view(np.uint64).tolist()
+    assert np.array_equal(g.node_offsets, ref.node_offsets)
+    assert np.array_equal(g.node_members, ref.node_members)
+    assert np.array_equal(g.edges, ref.edges)
+    assert np.array_equal(g.edge_weights, ref.edge_weights)
+    assert g.n_nodes > 1
