@@ -78,10 +78,10 @@ __device__ __forceinline__ int lane_id_here() {
     return l;
 }
 
-// A wave's accumulators: 2 x BN blocks of 32 x 32 (64 x 32 BN pairs).
-template <int PREC, int BN> struct Acc {
-    f32x16 c[2][BN];
-    f32x16 x[2][BN];   // cross-term accumulator of hi/lo splits
+// A wave's accumulators: two blocks of 32 x 32 (64 x 32 pairs).
+template <int PREC> struct Acc {
+    f32x16 c[2];
+    f32x16 x[2];       // cross-term accumulator of hi/lo splits
 };
 
 // ------------------------------------------------ one tile pair per workgroup
@@ -163,7 +163,7 @@ __device__ __forceinline__ void grid_read(const char *stage, GridOps &o, int wm,
 // The stage's products into the accumulators (FIRST: the tile's first stage,
 // whose products start them: a zero addend, so they need no clearing).
 template <int PREC, bool FIRST>
-__device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC, 1> &acc) {
+__device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC> &acc) {
     const f32x16 zero = {};
     if constexpr (PREC == P_FP32) {
 #pragma unroll
@@ -172,21 +172,21 @@ __device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC, 1> &acc) {
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int bm = 0; bm < 2; ++bm)
-                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                    acc.c[bm] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                         __builtin_bit_cast(f32x4, o.v[3 * h + bm])[t], __builtin_bit_cast(f32x4, o.v[3 * h + 2])[t],
-                        FIRST && h == 0 && t == 0 ? zero : acc.c[bm][0], 0, 0, 0);
+                        FIRST && h == 0 && t == 0 ? zero : acc.c[bm], 0, 0, 0);
     } else if constexpr (Cfg<PREC>::PANELS == 1) {
 #pragma unroll
         for (int h = 0; h < 4; ++h)
 #pragma unroll
             for (int bm = 0; bm < 2; ++bm) {
-                const f32x16 c = FIRST && h == 0 ? zero : acc.c[bm][0];
+                const f32x16 c = FIRST && h == 0 ? zero : acc.c[bm];
                 if constexpr (PREC == P_BF16)
-                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    acc.c[bm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                         __builtin_bit_cast(bf16x8, o.v[3 * h + bm]), __builtin_bit_cast(bf16x8, o.v[3 * h + 2]), c,
                         0, 0, 0);
                 else
-                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    acc.c[bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                         __builtin_bit_cast(f16x8, o.v[3 * h + bm]), __builtin_bit_cast(f16x8, o.v[3 * h + 2]), c,
                         0, 0, 0);
             }
@@ -199,19 +199,19 @@ __device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC, 1> &acc) {
                 const u32x4 bh = o.v[6 * ks + 4], bl = o.v[6 * ks + 5];
                 const bool z = FIRST && ks == 0;
                 if constexpr (PREC == P_BF16X3) {
-                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh), z ? zero : acc.c[bm][0], 0, 0, 0);
-                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl), z ? zero : acc.x[bm][0], 0, 0, 0);
-                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh), acc.x[bm][0], 0, 0, 0);
+                    acc.c[bm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh), z ? zero : acc.c[bm], 0, 0, 0);
+                    acc.x[bm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl), z ? zero : acc.x[bm], 0, 0, 0);
+                    acc.x[bm] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh), acc.x[bm], 0, 0, 0);
                 } else {
-                    acc.c[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bh), z ? zero : acc.c[bm][0], 0, 0, 0);
-                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bl), z ? zero : acc.x[bm][0], 0, 0, 0);
-                    acc.x[bm][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8, al), __builtin_bit_cast(f16x8, bh), acc.x[bm][0], 0, 0, 0);
+                    acc.c[bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bh), z ? zero : acc.c[bm], 0, 0, 0);
+                    acc.x[bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, ah), __builtin_bit_cast(f16x8, bl), z ? zero : acc.x[bm], 0, 0, 0);
+                    acc.x[bm] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, al), __builtin_bit_cast(f16x8, bh), acc.x[bm], 0, 0, 0);
                 }
             }
     }
@@ -231,13 +231,13 @@ template <int LV> struct EpiShared {
 // gv): the row words of its bitmask and of its band pairs go to LDS, and the
 // lane's column count is added to colc.  FULL: the block lies inside the
 // element and off the diagonal, so no bounds or triangle masks are needed.
-template <bool FULL, bool DEBUG, int BN, int LV>
+template <bool FULL, bool DEBUG, int LV>
 __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared<LV> &es, int lv,
-                                          const f32x16 &gv, int bm, int bn, int wm, int wn, int &colc) {
+                                          const f32x16 &gv, int bm, int wm, int wn, int &colc) {
     const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
-    const int cl = (wn * BN + bn) * 32 + li;                // column within the tile
+    const int cl = wn * 32 + li;                            // column within the tile
     const int64_t gc = (int64_t)tl.J * TILE + cl;          // element-local column
     const float Aj = es.thrA[lv][TILE + cl], Bj = es.thrB[lv][TILE + cl];
     const int r0 = wm * 64 + bm * 32 + 4 * lg;             // register v holds row r0 + 8(v/4) + v%4
@@ -282,7 +282,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         }
     }
     if (lane < 32) {
-        const int at = (wm * 64 + bm * 32 + li) * 4 + wn * BN + bn;
+        const int at = (wm * 64 + bm * 32 + li) * 4 + wn;
         es.words[at] = (uint32_t)word;
         es.bwords[at] = (uint32_t)bword;
     }
@@ -315,18 +315,11 @@ __device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl
     }
 }
 
-// The Gram values of accumulator block blk = BN bm + bn (blk wave-uniform).
-template <int PREC, int BN>
-__device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
-    f32x16 r = acc.c[0][0];
-    if constexpr (BN == 1) {
-        if (blk == 1) r = acc.c[1][0];
-    } else {
-        if (blk == 1) r = acc.c[0][1];
-        else if (blk == 2) r = acc.c[1][0];
-        else if (blk == 3) r = acc.c[1][1];
-    }
-    return r;
+// The Gram values of accumulator block bm (wave-uniform), selected without
+// indexing the accumulator array by a run-time value.
+template <int PREC>
+__device__ __forceinline__ f32x16 acc_block(const Acc<PREC> &acc, int bm) {
+    return bm == 1 ? acc.c[1] : acc.c[0];
 }
 
 
@@ -334,11 +327,11 @@ __device__ __forceinline__ f32x16 acc_block(const Acc<PREC, BN> &acc, int blk) {
 // barrier) the level's 2 KB bitmask block and neighbour counts: a row's count
 // is the popcount of its four words, a column's the sum of its partials.
 template <int PREC, bool DEBUG, int LV>
-__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC, 1> &acc,
+__device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &tl, Acc<PREC> &acc,
                                               EpiShared<LV> &es, int wm, int wn) {
     if constexpr (Cfg<PREC>::PANELS == 2) {                 // Gram value = hi.hi + cross terms
 #pragma unroll
-        for (int bm = 0; bm < 2; ++bm) acc.c[bm][0] = acc.c[bm][0] + acc.x[bm][0];
+        for (int bm = 0; bm < 2; ++bm) acc.c[bm] = acc.c[bm] + acc.x[bm];
     }
     const bool diag = tl.I == tl.J;
     const bool full = !diag && (int64_t)(tl.I + 1) * TILE <= tl.ne && (int64_t)(tl.J + 1) * TILE <= tl.ne;
@@ -349,11 +342,11 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
         int colc = 0;
         if (!DEBUG && full) {
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm) epi_block<true, false, 1, LV>(a, tl, es, lv, acc.c[bm][0], bm, 0, wm, wn, colc);
+            for (int bm = 0; bm < 2; ++bm) epi_block<true, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
         } else {                                            // diagonal or ragged tiles (few): one copy
 #pragma unroll 1
             for (int bm = 0; bm < 2; ++bm)
-                epi_block<false, DEBUG, 1, LV>(a, tl, es, lv, acc_block(acc, bm), bm, 0, wm, wn, colc);
+                epi_block<false, DEBUG, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
         }
         const int lane = lane_id_here();
         es.colcnt[wm * 2 + (lane >> 5)][wn * 32 + (lane & 31)] = (uint8_t)colc;
@@ -409,7 +402,7 @@ __device__ void process_tile(const TileArgs &a, const TilePos &tl, char *stages,
             }
         }
     }
-    Acc<PREC, 1> acc;
+    Acc<PREC> acc;
     GridOps ops;
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
@@ -512,7 +505,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
             const int64_t gj = (int64_t)J * TILE + threadIdx.x;
             hJ[threadIdx.x] = hsrc[gj < a.n ? gj : a.n - 1];
         }
-        Acc<PREC, 1> acc;
+        Acc<PREC> acc;
         GridOps ops;
 #pragma unroll 1
         for (int st = 0; st < nst; ++st) {
@@ -525,7 +518,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
         }
         if constexpr (Cfg<PREC>::PANELS == 2) {
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm) acc.c[bm][0] = acc.c[bm][0] + acc.x[bm][0];
+            for (int bm = 0; bm < 2; ++bm) acc.c[bm] = acc.c[bm] + acc.x[bm];
         }
         lds_barrier();                                      // every wave is done with the stages
         {
@@ -537,7 +530,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int row = wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * (li >> 5) + (v & 3);
-                    const float g = acc.c[bm][0][v];
+                    const float g = acc.c[bm][v];
                     const float S = hI[row] + hj;
                     const float m = 0x1.0p-22f * (fabsf(S) + fabsf(g));
                     U[knn_off(row, col)] = sgn * (upper ? 2.f * ((S - g) + m) : 2.f * ((S - g) - m));
