@@ -89,6 +89,7 @@ typedef struct {
 
 int orc_knn_d2(const float *X, int64_t n, int32_t d, int32_t k, double *out);
 int orc_ecc_d2(const float *X, int64_t n, int32_t d, double *out);
+double orc_pair_d2(const float *x, const float *y, int32_t d);
 
 /* ------------------------------------------------------------------ lens */
 
@@ -604,6 +605,42 @@ int orc_knn_d2(const float *X, int64_t n, int32_t d, int32_t k, double *out)
         free(best);
     }
     free(XT);
+    return fail ? ORC_ENOMEM : 0;
+}
+
+/* orc_knn_d2 for the listed rows only (rows[q] in [0, n)): out[q] = the
+ * k-th smallest canonical D(x_rows[q], x_j) over j != rows[q]. */
+int orc_knn_d2_rows(const float *X, int64_t n, int32_t d, int32_t k, const int32_t *rows, int64_t m,
+                    double *out)
+{
+    if (!X || !rows || !out || n < 2 || d < 1 || k < 1 || (int64_t)k > n - 1 || m < 0) return ORC_EINVAL;
+    for (int64_t q = 0; q < m; ++q)
+        if (rows[q] < 0 || rows[q] >= n) return ORC_EINVAL;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *best = (double *)malloc(sizeof(double) * (size_t)k);
+        if (!best) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t q = 0; q < m; ++q) {
+                const int64_t a = rows[q];
+                for (int32_t s = 0; s < k; ++s) best[s] = INFINITY;
+                for (int64_t b = 0; b < n; ++b) {
+                    if (b == a) continue;
+                    const double D = orc_pair_d2(X + a * (int64_t)d, X + b * (int64_t)d, d);
+                    if (!(D < best[k - 1])) continue;
+                    int32_t s = k - 1;
+                    while (s > 0 && best[s - 1] > D) { best[s] = best[s - 1]; --s; }
+                    best[s] = D;
+                }
+                out[q] = best[k - 1];
+            }
+        }
+        free(best);
+    }
     return fail ? ORC_ENOMEM : 0;
 }
 

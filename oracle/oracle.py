@@ -93,6 +93,10 @@ def lib():
         L.orc_knn_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)]
         L.orc_knn_d2.restype = ctypes.c_int
+        L.orc_knn_d2_rows.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.orc_knn_d2_rows.restype = ctypes.c_int
         L.orc_ecc_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)]
         L.orc_ecc_d2.restype = ctypes.c_int
@@ -271,6 +275,19 @@ def knn_d2(X: np.ndarray, k: int) -> np.ndarray:
     n, d = X.shape
     out = np.zeros(n, np.float64)
     rc = lib().orc_knn_d2(_p(X, ctypes.c_float), n, d, int(k), _p(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def knn_d2_rows(X: np.ndarray, k: int, rows) -> np.ndarray:
+    """knn_d2 for the listed rows only."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros(r.size, np.float64)
+    rc = lib().orc_knn_d2_rows(_p(X, ctypes.c_float), n, d, int(k), _p(r, ctypes.c_int32), r.size,
+                               _p(out, ctypes.c_double))
     if rc != 0:
         raise OracleError(rc)
     return out

@@ -95,3 +95,19 @@ def test_cloud_lens_mapper(ctx, kind, k, prec):
     assert np.array_equal(g.edges, ref.edges)
     assert np.array_equal(g.edge_weights, ref.edge_weights)
     assert g.n_nodes > 1
+
+
+def test_knn_100k_d256_sampled(ctx):
+    """The benchmark's k-NN configuration (the first 100,000 points of the
+    1M x 256 cloud, k = 5, BF16x3 screening): 256 sampled rows against the
+    oracle row by row; every value is a canonical distance to some point."""
+    X = np.ascontiguousarray(synth.mixture_1m_d256().X[:100_000])
+    cloud = ctx.cloud(X)
+    try:
+        got, st = cloud.knn_d2(5, synth.PREC_BF16X3)
+    finally:
+        cloud.destroy()
+    rows = np.random.default_rng(12).choice(X.shape[0], 256, replace=False)
+    assert np.array_equal(got[rows], O.knn_d2_rows(X, 5, rows))
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    assert st["band_pairs"] >= 5 * X.shape[0]

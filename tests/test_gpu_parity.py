@@ -453,22 +453,19 @@ def test_full_size_1m_d256(ctx):
         cloud.destroy()
     same_graph(gb, gf)
     ax = w.params.axes[0]
-    rng = np.random.default_rng(4)
-    pick = rng.choice(w.X.shape[0], 2000, replace=False)
-    f_ref = O.lens(w.X[pick], ax)
-    assert np.array_equal(gb.stages["lens"][pick], f_ref)
-    lo, hi = O.cover(float(gb.stages["lens"].min()), float(gb.stages["lens"].max()), ax.n_intervals, ax.overlap)
+    f = O.lens(w.X, ax)                                     # the oracle's own lens of all points
+    assert np.array_equal(gb.stages["lens"], f)
+    lo, hi = O.cover(float(f.min()), float(f.max()), ax.n_intervals, ax.overlap)
     assert np.array_equal(gb.stages["lo"], lo) and np.array_equal(gb.stages["hi"], hi)
     eo = gb.stages["elem_offsets"]
     sizes = np.diff(eo)
-    f = gb.stages["lens"]
     for e in np.argsort(sizes)[:6]:
         if sizes[e] == 0:
             continue
         mem = gb.stages["elem_members"][eo[e]:eo[e + 1]]
         want = np.nonzero((lo[e] <= f) & (f <= hi[e]))[0]
         assert np.array_equal(mem, want)
-        cnt, core, cid = O.dbscan(w.X, mem, w.params.eps, w.params.min_pts)
+        cnt, core, cid = O.dbscan(w.X, want, w.params.eps, w.params.min_pts)
         assert np.array_equal(gb.stages["slot_count"][eo[e]:eo[e + 1]], cnt)
         node = gb.stages["slot_node"][eo[e]:eo[e + 1]]
         first = node[node >= 0].min() if (node >= 0).any() else 0
@@ -486,3 +483,43 @@ def test_full_size_1m_d256(ctx):
                 want[(vs[i], vs[j])] = want.get((vs[i], vs[j]), 0) + 1
     got = {(int(a), int(b)): int(c) for (a, b), c in zip(gb.edges, gb.edge_weights)}
     assert got == want
+
+
+def test_full_size_balanced_cover(ctx):
+    """1M x 256 with the balanced cover: the GPU's endpoints (device radix
+    sort of the lens) are the oracle's, computed from the oracle's own lens,
+    and the smallest elements hold exactly the points inside them."""
+    w = synth.mixture_1m_d256()
+    w.params.axes[0].cover = 1
+    cloud = ctx.cloud(w.X)
+    try:
+        g = cloud.run(w.params, debug=True)
+    finally:
+        cloud.destroy()
+    ax = w.params.axes[0]
+    f = O.lens(w.X, ax)
+    lo, hi = O.cover_balanced(f, ax.n_intervals, ax.overlap)
+    assert np.array_equal(g.stages["lo"], lo) and np.array_equal(g.stages["hi"], hi)
+    eo = g.stages["elem_offsets"]
+    sizes = np.diff(eo)
+    assert sizes.max() - sizes.min() <= 3
+    for e in (0, ax.n_intervals // 2, ax.n_intervals - 1):
+        mem = g.stages["elem_members"][eo[e]:eo[e + 1]]
+        assert np.array_equal(mem, np.nonzero((lo[e] <= f) & (f <= hi[e]))[0])
+
+
+def test_full_size_eps_sweep(ctx):
+    """1M x 256, the four eps values the benchmark sweeps: each graph of the
+    one-pass sweep is the graph of its own run."""
+    import copy
+    w = synth.mixture_1m_d256()
+    eps = [20.0, 22.0, 24.0, 26.0]
+    cloud = ctx.cloud(w.X)
+    try:
+        gs = cloud.run_eps_sweep(w.params, eps)
+        for e, g in zip(eps, gs):
+            p = copy.copy(w.params)
+            p.eps = e
+            same_graph(g, cloud.run(p))
+    finally:
+        cloud.destroy()

@@ -68,3 +68,10 @@ def test_duplicates_and_monotone():
     ks = [O.knn_d2(X, k) for k in (1, 2, 4, 7, 12)]
     for a, b in zip(ks, ks[1:]):
         assert np.all(a <= b)
+
+
+def test_rows_variant_matches():
+    X = np.random.default_rng(9).normal(size=(400, 12)).astype(np.float32)
+    rows = np.random.default_rng(10).choice(400, 37, replace=False)
+    for k in (1, 6, 16):
+        assert np.array_equal(O.knn_d2_rows(X, k, rows), O.knn_d2(X, k)[rows])
