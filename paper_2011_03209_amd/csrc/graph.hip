@@ -373,30 +373,46 @@ __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bi
         ((uint4 *)W)[lane + 64] = src[lane + 64];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    int32_t cmin0 = NOISE, cmin1 = NOISE;
+    // non-core rows r: the lowest node among their core neighbour columns
     const int64_t rowbase = tl.slot0 + (int64_t)tl.I * TILE;
-    for (int r = 0; r < TILE; ++r) {
-        const bool rcore = (coreI[r >> 6] >> (r & 63)) & 1ull;
-        const bool rnc = (ncI[r >> 6] >> (r & 63)) & 1ull;
-        if (!rcore && !rnc) continue;
-        const uint32_t wa = W[r * 4 + (lane >> 5)], wb = W[r * 4 + 2 + (lane >> 5)];
-        const bool b0 = (wa >> (lane & 31)) & 1u, b1 = (wb >> (lane & 31)) & 1u;
-        if (rnc) {           // non-core row: lowest node among core columns
-            int32_t m = NOISE;
-            if (b0 && ((coreJ[0] >> lane) & 1ull)) m = N[TILE + lane];
-            if (b1 && ((coreJ[1] >> lane) & 1ull)) m = min(m, N[TILE + 64 + lane]);
+    if (rows_nc) {
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, WAVE));
-            if (lane == 0 && m != NOISE) atomicMin(&node[rowbase + r], m);
-        } else {             // core row: non-core columns take its node
-            const int32_t rn = N[r];
-            if (b0 && ((ncJ[0] >> lane) & 1ull)) cmin0 = min(cmin0, rn);
-            if (b1 && ((ncJ[1] >> lane) & 1ull)) cmin1 = min(cmin1, rn);
+        for (int h = 0; h < 2; ++h) {
+            uint64_t todo = ncI[h];
+            while (todo) {
+                const int r = 64 * h + __ffsll((long long)todo) - 1;
+                todo &= todo - 1;
+                const uint32_t wa = W[r * 4 + (lane >> 5)], wb = W[r * 4 + 2 + (lane >> 5)];
+                int32_t m = NOISE;
+                if (((wa >> (lane & 31)) & 1u) && ((coreJ[0] >> lane) & 1ull)) m = N[TILE + lane];
+                if (((wb >> (lane & 31)) & 1u) && ((coreJ[1] >> lane) & 1ull)) m = min(m, N[TILE + 64 + lane]);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, WAVE));
+                if (lane == 0 && m != NOISE) atomicMin(&node[rowbase + r], m);
+            }
         }
     }
+    // non-core columns c: the lowest node among their core neighbour rows
+    // (lane l checks rows l and l + 64 of the column)
     const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
-    if (cmin0 != NOISE) atomicMin(&node[colbase + lane], cmin0);
-    if (cmin1 != NOISE) atomicMin(&node[colbase + 64 + lane], cmin1);
+    if (cols_nc) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint64_t todo = ncJ[h];
+            while (todo) {
+                const int c = 64 * h + __ffsll((long long)todo) - 1;
+                todo &= todo - 1;
+                const int wc = c >> 5;
+                const uint32_t bit = 1u << (c & 31);
+                int32_t m = NOISE;
+                if ((W[lane * 4 + wc] & bit) && ((coreI[0] >> lane) & 1ull)) m = N[lane];
+                if ((W[(lane + 64) * 4 + wc] & bit) && ((coreI[1] >> lane) & 1ull)) m = min(m, N[64 + lane]);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, WAVE));
+                if (lane == 0 && m != NOISE) atomicMin(&node[colbase + c], m);
+            }
+        }
+    }
 }
 
 __global__ void k_flag_labelled(const int32_t *node, uint8_t *flag, int64_t n) {
