@@ -40,18 +40,6 @@ __device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x) {
     }
 }
 
-// An ancestor of x, following parents with ordinary (cacheable) loads and no
-// writes.  A stale parent is still an ancestor, so the result is always a
-// member of x's set; it serves as a label, never as a hook target.
-__device__ __forceinline__ int32_t uf_label(const int32_t *P, int32_t x) {
-    int32_t p = P[x];
-    while (p != x) {
-        x = p;
-        p = P[x];
-    }
-    return x;
-}
-
 // Merge the sets of a and b; returns a representative of the merged set.
 __device__ int32_t uf_union(int32_t *P, int32_t a, int32_t b) {
     while (true) {
@@ -132,14 +120,19 @@ __device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int3
     int32_t lab[4];
     bool cr[2];
     uint64_t cc[2];
+    // every load of the block at once: counts, parents (one hop: the parents
+    // were compressed before this kernel, and any ancestor serves as a label)
+    // and the bitmask block
+    int32_t cnt[4], par[4];
+    bool valid[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t loc = q < 2 ? (int64_t)tl.I * TILE + 2 * lane + q : (int64_t)tl.J * TILE + lane + 64 * (q - 2);
-        const bool c = loc < tl.ne && count[tl.slot0 + loc] >= min_pts;
-        lab[q] = c ? uf_label(parent, (int32_t)(tl.slot0 + loc)) : -1;
-        if (q < 2) cr[q] = c; else cc[q - 2] = __ballot(c);
+        valid[q] = loc < tl.ne;
+        const int64_t sl = tl.slot0 + (valid[q] ? loc : 0);
+        cnt[q] = count[sl];
+        par[q] = parent[sl];
     }
-    if (__ballot(cr[0] || cr[1]) == 0 || (cc[0] | cc[1]) == 0) return;
     uint32_t wd[8];
     {
         const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS) + 2 * lane;
@@ -147,6 +140,13 @@ __device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int3
         wd[0] = u0.x; wd[1] = u0.y; wd[2] = u0.z; wd[3] = u0.w;
         wd[4] = u1.x; wd[5] = u1.y; wd[6] = u1.z; wd[7] = u1.w;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool c = valid[q] && cnt[q] >= min_pts;
+        lab[q] = c ? par[q] : -1;
+        if (q < 2) cr[q] = c; else cc[q - 2] = __ballot(c);
+    }
+    if (__ballot(cr[0] || cr[1]) == 0 || (cc[0] | cc[1]) == 0) return;
     // core-core bits of my two rows (columns 0..63 and 64..127)
     const uint64_t b00 = cr[0] ? ((((uint64_t)wd[1] << 32) | wd[0]) & cc[0]) : 0;
     const uint64_t b01 = cr[0] ? ((((uint64_t)wd[3] << 32) | wd[2]) & cc[1]) : 0;
@@ -300,6 +300,15 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
 __global__ void k_cc_init(int32_t *parent, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) parent[i] = (int32_t)i;
+}
+
+// parent[i] = the root of i (path compression before the block pass).
+__global__ void k_cc_compress(int32_t *parent, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t r = uf_find(parent, (int32_t)i);
+        if (r != (int32_t)i) __hip_atomic_store(&parent[i], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __global__ void k_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
@@ -501,6 +510,12 @@ inline unsigned wave_blocks(int64_t items) {
 }
 
 }  // namespace
+
+hipError_t launch_cc_compress(int32_t *parent, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_cc_compress<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(parent, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_cc_init(int32_t *parent, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -255,6 +255,8 @@ hipError_t launch_pair_d64(const int32_t *pa, const int32_t *pb, int64_t np, con
 
 // graph.hip
 hipError_t launch_cc_init(int32_t *parent, int64_t n_slots, hipStream_t s);
+// parent[i] = root of i for every slot (path compression).
+hipError_t launch_cc_compress(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
                            int32_t min_pts, int32_t *parent, hipStream_t s);
 hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,

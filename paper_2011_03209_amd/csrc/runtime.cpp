@@ -874,6 +874,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
     HIPCHK(launch_cc_init(parent, S, s));
     HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, bitmask, count, P->min_pts, parent, s));
+    HIPCHK(launch_cc_compress(parent, S, s));
     HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
     void *stmp2 = lm.get<char>(scan_temp_bytes(Sa + 1));
