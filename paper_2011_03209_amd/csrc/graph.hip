@@ -120,9 +120,9 @@ __device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int3
     int32_t lab[4];
     bool cr[2];
     uint64_t cc[2];
-    // every load of the block at once: counts, parents (one hop: the parents
-    // were compressed before this kernel, and any ancestor serves as a label)
-    // and the bitmask block
+    // the block's first loads at once: counts, parents (the first hop of
+    // each label chain; the parents were compressed before this kernel) and
+    // the bitmask block
     int32_t cnt[4], par[4];
     bool valid[4];
 #pragma unroll
@@ -143,7 +143,17 @@ __device__ void cc_block(const WaveTile &tl, const uint32_t *bitmask, const int3
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const bool c = valid[q] && cnt[q] >= min_pts;
-        lab[q] = c ? par[q] : -1;
+        // the label: the current root (any ancestor would be correct, but a
+        // stale one makes the block look inconsistent and costs merge rounds)
+        int32_t x = par[q];
+        if (c) {
+            int32_t p2 = parent[x];
+            while (p2 != x) {
+                x = p2;
+                p2 = parent[x];
+            }
+        }
+        lab[q] = c ? x : -1;
         if (q < 2) cr[q] = c; else cc[q - 2] = __ballot(c);
     }
     if (__ballot(cr[0] || cr[1]) == 0 || (cc[0] | cc[1]) == 0) return;
@@ -401,10 +411,12 @@ __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bi
             }
         }
     }
-    // non-core columns c: the lowest node among their core neighbour rows
-    // (lane l checks rows l and l + 64 of the column)
+    // non-core columns c: the lowest node among their core neighbour rows.
+    // Few of them: one pass per column (lane l checks rows l and l + 64);
+    // many: one scan over the core rows, each lane keeping its two columns'
+    // minima.
     const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
-    if (cols_nc) {
+    if (cols_nc && __popcll(ncJ[0]) + __popcll(ncJ[1]) <= 16) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             uint64_t todo = ncJ[h];
@@ -421,6 +433,22 @@ __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bi
                 if (lane == 0 && m != NOISE) atomicMin(&node[colbase + c], m);
             }
         }
+    } else if (cols_nc) {
+        int32_t cmin0 = NOISE, cmin1 = NOISE;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint64_t todo = coreI[h];
+            while (todo) {
+                const int r = 64 * h + __ffsll((long long)todo) - 1;
+                todo &= todo - 1;
+                const uint32_t wa = W[r * 4 + (lane >> 5)], wb = W[r * 4 + 2 + (lane >> 5)];
+                const int32_t rn = N[r];
+                if (((wa >> (lane & 31)) & 1u) && ((ncJ[0] >> lane) & 1ull)) cmin0 = min(cmin0, rn);
+                if (((wb >> (lane & 31)) & 1u) && ((ncJ[1] >> lane) & 1ull)) cmin1 = min(cmin1, rn);
+            }
+        }
+        if (cmin0 != NOISE) atomicMin(&node[colbase + lane], cmin0);
+        if (cmin1 != NOISE) atomicMin(&node[colbase + 64 + lane], cmin1);
     }
 }
 
