@@ -144,6 +144,12 @@ def _cases():
     # tiny magnitudes (power-of-two rescaling keeps FP32/FP16 tiles exact-safe)
     Xs = (rng.normal(size=(500, 16)) * 1e-20).astype(np.float32)
     out.append(("tiny", Xs, synth.Params([synth.Axis(synth.LENS_L2, 3, 0.3)], 5.5e-20, 4)))
+    # huge magnitudes (FP64 distances far above FP32 range after scaling back)
+    Xh = (rng.normal(size=(400, 24)) * 1e30).astype(np.float32)
+    out.append(("huge", Xh, synth.Params([synth.Axis(synth.LENS_L2, 4, 0.3)], 6.0e30, 4)))
+    # very wide rows: many stages, ragged last one
+    Xw = rng.normal(size=(200, 2050)).astype(np.float32)
+    out.append(("d2050", Xw, synth.Params([synth.Axis(synth.LENS_LINF, 2, 0.3)], 64.0, 3)))
     # 2-D with one axis of one interval
     out.append(("2d_1x9", Xv, synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0),
                                              synth.Axis(synth.LENS_COLUMN, 9, 0.5, column=1)], 3.0, 3)))
@@ -158,6 +164,27 @@ CASES = _cases()
 def test_edge_cases(ctx, case, prec):
     name, X, params = CASES[case]
     run_and_compare(ctx, X, with_prec(params, prec))
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_edge_cases_eps_sweep(ctx, case):
+    """The eps sweep on every edge case: eps, half of it and twice it in one
+    pass, each graph the oracle's."""
+    import copy
+    name, X, params = CASES[case]
+    params = with_prec(params, synth.PREC_BF16X3)
+    eps = [params.eps, params.eps * 0.5, params.eps * 2.0]
+    cloud = ctx.cloud(X)
+    try:
+        gs = cloud.run_eps_sweep(params, eps, debug=True)
+    finally:
+        cloud.destroy()
+    for e, g in zip(eps, gs):
+        p = copy.copy(params)
+        p.eps = e
+        ref = oracle_graph(X, p)
+        same_stages(g, ref, len(p.axes))
+        same_graph(g, ref)
 
 
 @pytest.mark.parametrize("seed", range(4))
