@@ -198,12 +198,12 @@ def main():
                           "ms_cc_each": [gg.stats["ms_cc"] for gg in gs4],
                           "nodes": [gg.n_nodes for gg in gs4]}), file=sys.stderr, flush=True)
         sub = ctx.cloud(np.ascontiguousarray(w.X[:100_000]))
-        sub.knn_d2(5, prec)
+        sub.knn_d2(5, 5)
         t0 = time.perf_counter()
-        kd, kst = sub.knn_d2(5, prec)
+        kd, kst = sub.knn_d2(5, 5)                          # screening precision chosen by the library (FP16)
         t1 = time.perf_counter()
         sub.destroy()
-        print(json.dumps({"sweep": f"knn k=5 100000x256 {args.precision}", "s": t1 - t0,
+        print(json.dumps({"sweep": "knn k=5 100000x256 auto", "s": t1 - t0, "screen_precision": PREC_NAME[kst["precision"]],
                           "ms_screen": kst["ms_tiles"], "ms_fp64": kst["ms_recheck"],
                           "candidates": kst["band_pairs"], "pairs": kst["pairs"],
                           "median_knn_d": float(np.sqrt(np.median(kd)))}), file=sys.stderr, flush=True)

@@ -191,7 +191,7 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
  * canonical squared distance D(x_i, x_j) over the other points j != i, ties
  * counted with multiplicity; D is the FP64 chain of the eps tiles (x_j - y_j
  * in FP64, fma in coordinate order), so the result is exact and does not
- * depend on `precision` (a MAPPER_PREC_*, AUTO = BF16X3), which only sets
+ * depend on `precision` (a MAPPER_PREC_*, AUTO = FP16), which only sets
  * the matrix-core screening pass.  1 <= k <= min(16, n - 1).  stats may be
  * NULL; ms_tiles is the two screening passes, ms_recheck the FP64 step,
  * band_pairs the candidate pairs it evaluated. */

@@ -600,7 +600,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         if (ax.kind == MAPPER_LENS_KNN_DISTANCE || ax.kind == MAPPER_LENS_ECCENTRICITY) {
             mapper_run_stats ks{};                          // whole-cloud lens: k-NN screening + FP64
             const bool ecc = ax.kind == MAPPER_LENS_ECCENTRICITY;
-            knn_device(ctx, cloud, ecc ? 1 : ax.column, ecc ? 1 : 0, P_BF16X3, f[a], ks, s);
+            knn_device(ctx, cloud, ecc ? 1 : ax.column, ecc ? 1 : 0, P_FP16, f[a], ks, s);
             HIPCHK(launch_sqrt(f[a], n, s));
         } else {
             HIPCHK(launch_lens(cloud->X, n, d, ax.kind, ax.column, dir, vals, f[a], s));
@@ -1226,7 +1226,10 @@ mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int3
     if (k < 1 || k > KNN_KMAX || (int64_t)k > cloud->n - 1)
         return fail(MAPPER_EINVAL, "k must be in [1, min(16, n - 1)]");
     if (precision < 0 || precision > MAPPER_PREC_AUTO) return fail(MAPPER_EINVAL, "bad precision");
-    const int prec = precision == MAPPER_PREC_AUTO ? P_BF16X3 : precision;
+    // screening precision: the result is exact either way; FP16 (one product
+    // per pair) was the fastest at 100k x 256 (35 ms against 56 for BF16x3,
+    // with 1.8x the candidates)
+    const int prec = precision == MAPPER_PREC_AUTO ? P_FP16 : precision;
     hipStream_t s = ctx->stream;
     try {
         HIPCHK(hipSetDevice(ctx->device));
