@@ -419,6 +419,31 @@ def test_serving_alone_vs_mix():
         ctx.close()
 
 
+def test_serving_new_features():
+    """Serving requests that use the balanced cover and the whole-cloud
+    lenses, mixed with plain ones, give the graphs of their solo runs and the
+    oracle's."""
+    from paper_2011_03209_amd import binding
+    ctx = binding.Context(arena_bytes=8 << 30, serving_streams=3)
+    try:
+        X = np.ascontiguousarray(synth.mixture_100k_d64(scale=0.02).X[:, :24])
+        cloud = ctx.cloud(X)
+        reqs = [synth.Params([synth.Axis(synth.LENS_L2, 6, 0.3, cover=1)], eps=6.5, min_pts=4),
+                synth.Params([synth.Axis(synth.LENS_ECCENTRICITY, 5, 0.4)], eps=6.5, min_pts=4),
+                synth.Params([synth.Axis(synth.LENS_KNN_DISTANCE, 4, 0.3, column=3)], eps=6.0, min_pts=3,
+                             precision=synth.PREC_FP16),
+                synth.Params([synth.Axis(synth.LENS_L2, 8, 0.25)], eps=6.5, min_pts=4)]
+        alone = [cloud.run(p) for p in reqs]
+        tickets = [cloud.submit(p) for p in reqs]
+        mixed = [binding.wait(ctx, tk) for tk in tickets]
+        for a, b, p in zip(alone, mixed, reqs):
+            same_graph(a, b)
+            same_graph(b, O.mapper(X, p))
+        cloud.destroy()
+    finally:
+        ctx.close()
+
+
 def test_errors(ctx):
     from paper_2011_03209_amd import binding
     X = np.random.default_rng(1).normal(size=(100, 4)).astype(np.float32)
