@@ -231,6 +231,7 @@ struct KnnArgs {
     int32_t *cand, *ccnt;              // pass 2: candidates of row i at i * cmax, their count
     int32_t cmax;
     int32_t mode;                      // 0: k-th smallest D; 1: largest D (values negated)
+    int32_t k;                         // the k of the k-th smallest (1 in mode 1)
 };
 
 hipError_t launch_knn_pass(int prec, int pass, const KnnArgs &a, hipStream_t s);

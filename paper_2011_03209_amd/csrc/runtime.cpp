@@ -493,6 +493,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     ka.t.dp = dp;
     ka.t.n_levels = 1;
     ka.mode = mode;
+    ka.k = k;
     ka.n = n;
     ka.T = T;
     ka.C = C;

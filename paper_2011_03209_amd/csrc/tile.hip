@@ -455,15 +455,19 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
 // thread t then scans row t % 128, columns 32 (t / 128) .. + 31.
 __device__ __forceinline__ int knn_off(int r, int c) { return r * TILE + ((c + r) & (TILE - 1)); }
 
-// b: the 16 smallest values seen, ascending; insert u (dropping the largest).
-__device__ __forceinline__ void top16_insert(float (&b)[KNN_KMAX], float u) {
+// b: the KM smallest values seen, ascending; insert u (dropping the largest).
+template <int KM>
+__device__ __forceinline__ void topk_insert(float (&b)[KM], float u) {
 #pragma unroll
-    for (int q = KNN_KMAX - 1; q > 0; --q) b[q] = fminf(b[q], fmaxf(b[q - 1], u));
+    for (int q = KM - 1; q > 0; --q) b[q] = fminf(b[q], fmaxf(b[q - 1], u));
     b[0] = fminf(b[0], u);
 }
 
-template <int PREC, int PASS>
-__global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
+// KM: the length of pass 1's sorted lists (8 when k <= 8: eight fewer
+// registers, so that two workgroups fit on a CU where the precision allows).
+template <int PREC, int PASS, int KM>
+__global__ void __launch_bounds__(NTG, ((PASS == 2 || KM <= 8) && Cfg<PREC>::PANELS == 1) ? 2 : 1)
+k_knn(KnnArgs a) {
     __shared__ __attribute__((aligned(1024))) char stages[2 * GSTAGE];   // also the bound tile
     __shared__ float hI[TILE], hJ[TILE];
     float *U = (float *)stages;
@@ -481,9 +485,9 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
     const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.t.dp);
     const int nst = (int)(panel_row_bytes(PREC, a.t.dp) / GROW);
     const uint32_t st_lds = lds_addr(stages);
-    float best[KNN_KMAX];
+    float best[KM];
 #pragma unroll
-    for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inff();
+    for (int q = 0; q < KM; ++q) best[q] = __builtin_inff();
     const float thr_r = PASS == 2 ? a.thr[rvalid ? grow : a.n - 1] : 0.f;
     if (threadIdx.x < TILE) {
         const int64_t gi = (int64_t)I * TILE + threadIdx.x;
@@ -545,7 +549,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
                 if (gcol >= a.n || gcol == grow) continue;
                 const float u = U[knn_off(r, col)];
                 if constexpr (PASS == 1) {
-                    if (u < best[KNN_KMAX - 1]) top16_insert(best, u);
+                    if (u < best[KM - 1]) topk_insert(best, u);
                 } else {
                     if (u <= thr_r) {
                         const int slot = atomicAdd(&a.ccnt[grow], 1);
@@ -560,7 +564,7 @@ __global__ void __launch_bounds__(NTG, 1) k_knn(KnnArgs a) {
         const int64_t rows = (int64_t)a.T * TILE;
         float *dst = a.part + (((int64_t)ch * rows + grow) * 4 + qtr) * KNN_KMAX;
 #pragma unroll
-        for (int q = 0; q < KNN_KMAX; ++q) dst[q] = best[q];
+        for (int q = 0; q < KNN_KMAX; ++q) dst[q] = q < KM ? best[q < KM ? q : KM - 1] : __builtin_inff();
     }
 }
 
@@ -577,7 +581,7 @@ __global__ void k_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
             const float *src = part + (((int64_t)c * rows + i) * 4 + qt) * KNN_KMAX;
             for (int q = 0; q < KNN_KMAX; ++q) {
                 const float u = src[q];
-                if (u < best[KNN_KMAX - 1]) top16_insert(best, u);
+                if (u < best[KNN_KMAX - 1]) topk_insert(best, u);
             }
         }
     float kth = best[0];
@@ -663,8 +667,9 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
 template <int PREC>
 hipError_t launch_knn_t(int pass, const KnnArgs &a, hipStream_t s) {
     const unsigned G = (unsigned)((int64_t)a.T * a.C);
-    if (pass == 1) k_knn<PREC, 1><<<dim3(G), dim3(NTG), 0, s>>>(a);
-    else k_knn<PREC, 2><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    if (pass == 1 && a.k <= 8) k_knn<PREC, 1, 8><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    else if (pass == 1) k_knn<PREC, 1, KNN_KMAX><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    else k_knn<PREC, 2, KNN_KMAX><<<dim3(G), dim3(NTG), 0, s>>>(a);
     return hipGetLastError();
 }
 
