@@ -124,20 +124,27 @@ __device__ __forceinline__ float round_dn_f(double v) {
     return f;
 }
 
+// Sixteen lanes per slot (four slots per wave): lane `sub` of a slot handles
+// coordinates j = sub, sub + 16, ..., so its loads and the split rows' stores
+// are contiguous runs per slot, and each cross-lane step of the FP64 sums
+// serves four slots at once.
+constexpr int PK_LANES = 16;
+
 __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (s >= a.n_slots) return;
-    const float *x = a.X + (int64_t)a.slot_point[s] * a.d;
+    const int sub = threadIdx.x & (PK_LANES - 1);
+    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / PK_LANES) + threadIdx.x / PK_LANES;
+    const bool live = s < a.n_slots;                       // lanes of absent slots still join the shuffles
+    const int64_t sl = live ? s : a.n_slots - 1;
+    const float *x = a.X + (int64_t)a.slot_point[sl] * a.d;
     const bool split = a.prec == P_BF16X3 || a.prec == P_FP16X3;
     const bool bf = a.prec == P_BF16 || a.prec == P_BF16X3;
     double nx = 0, hh = 0, ll = 0, xt = 0, rr = 0;
-    for (int j = lane; j < a.dp; j += WAVE) {
+    for (int j = sub; j < a.dp; j += PK_LANES) {
         const float xs = j < a.d ? (float)((double)x[j] * a.scale) : 0.0f;   // exact power-of-two scaling
         const double xd = (double)xs;
         nx += xd * xd;
         if (a.prec == P_FP32) {
-            ((float *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp)))[j] = xs;
+            if (live) ((float *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp)))[j] = xs;
             continue;
         }
         uint16_t hb, lb = 0;
@@ -145,12 +152,12 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
         // split rows interleave 16 hi and 16 lo values per group of 16 coordinates
         uint16_t *row16 = (uint16_t *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp));
         const int64_t at = split ? (int64_t)(j >> 4) * 32 + (j & 15) : j;
-        row16[at] = hb;
+        if (live) row16[at] = hb;
         double lo = 0.0;
         if (split) {
             const float rem = xs - h;            // exact in FP32
             lo = (double)(bf ? bf16_round(rem, &lb) : fp16_round(rem, &lb));
-            row16[at + 16] = lb;
+            if (live) row16[at + 16] = lb;
         }
         const double hd = (double)h, r = xd - hd - lo;   // exact in FP64
         hh += hd * hd;
@@ -159,14 +166,14 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
         rr += r * r;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = PK_LANES / 2; o > 0; o >>= 1) {            // within each slot's 16 lanes
         nx += __shfl_xor(nx, o, WAVE);
         hh += __shfl_xor(hh, o, WAVE);
         ll += __shfl_xor(ll, o, WAVE);
         xt += __shfl_xor(xt, o, WAVE);
         rr += __shfl_xor(rr, o, WAVE);
     }
-    if (lane != 0) return;
+    if (sub != 0 || !live) return;
     // Per-slot share e_s of the bound |g_ij - x_i.x_j| <= e_i + e_j on the tile's
     // Gram value (every product bound made separable with a*b <= (l a^2 + b^2/l)/2).
     const double K = (double)a.dp;
@@ -218,7 +225,7 @@ hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t
 
 hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
     if (a.n_slots <= 0) return hipSuccess;
-    const int64_t blocks = (a.n_slots + 3) / 4;
+    const int64_t blocks = (a.n_slots + 256 / PK_LANES - 1) / (256 / PK_LANES);
     k_pack<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
