@@ -63,18 +63,20 @@ def recorded_traffic(precision: str):
     """HBM bytes per launch of the tile kernel from the committed rocprofv3
     counter record (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
     calibration), or None when the record is missing or was taken from
-    another version of the kernel source."""
+    another version of the kernel source (tile.hip, and internal.h, which
+    holds the tile order and the panel layout)."""
     import hashlib
     rec = os.path.join(ROOT, "profiles", f"mapper_mix1m_d256_{precision}.txt")
-    src = os.path.join(ROOT, "paper_2011_03209_amd", "csrc", "tile.hip")
-    if not (os.path.exists(rec) and os.path.exists(src)):
+    csrc = os.path.join(ROOT, "paper_2011_03209_amd", "csrc")
+    srcs = [os.path.join(csrc, "tile.hip"), os.path.join(csrc, "internal.h")]
+    if not (os.path.exists(rec) and all(os.path.exists(s) for s in srcs)):
         return None
     kv = {}
     for line in open(rec):
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = hashlib.sha256(b"".join(open(s, "rb").read() for s in srcs)).hexdigest()[:16]
     if kv.get("tile_source_sha256_16") != sha:
         return None
     try:

@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
     tl.ne = tt.elem_off[e + 1] - tl.slot0;
     const int64_t T = (tl.ne + TILE - 1) / TILE;
     if (tl.ne <= 0 || tl.J >= T) return;
-    tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, 0, tl.J);
+    tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, tt.super, 0, tl.J);
     if (tl.J == 0) {
         cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
         return;

@@ -23,11 +23,11 @@ inline bool prec_is_bf16(int p) { return p == P_BF16 || p == P_BF16X3; }
 
 // Work table of the distance-tile launch.  Items are the tile pairs (I <= J)
 // of all elements, grouped by element in the order `order` (largest first).
-// Inside an element the tile pairs are visited in supertiles of SUPER x SUPER
-// pairs (upper triangle only), supertile columns left to right, supertiles of a
+// Inside an element the tile pairs are visited in supertiles of S x S pairs
+// (upper triangle only), supertile columns left to right, supertiles of a
 // column top to bottom, and inside a supertile row blocks fastest.  Workgroups
-// that run together on one XCD thus share a few row panels in its L2.
-constexpr int SUPER = 8;
+// that run together on one XCD thus share a few row panels in its L2.  S is
+// chosen per run (TileTable::super, supertile_size below).
 
 // One tile pair, decoded (32 bytes: one scalar load per workgroup or wave).
 struct __attribute__((aligned(32))) TileItem {
@@ -44,6 +44,7 @@ struct TileTable {
     const int64_t *cp_off;     // [E] start of the element's colpre entries
     const struct TileItem *items;   // decoded items, built by launch_build_items
     int32_t nord;
+    int32_t super;             // supertile size S
     int64_t n_items;
 };
 
@@ -67,7 +68,8 @@ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item)
     r.ne = t.elem_off[r.e + 1] - r.slot0;
     r.blk = t.blk_off[r.e] + p;
     const int64_t T = (r.ne + TILE - 1) / TILE;
-    const int64_t Ts = (T + SUPER - 1) / SUPER;
+    const int64_t S = t.super;
+    const int64_t Ts = (T + S - 1) / S;
     const int64_t *cp = t.colpre + t.cp_off[r.e];
     int64_t a = 0, b = Ts;                         // largest SJ with cp[SJ] <= p
     while (b - a > 1) {
@@ -76,19 +78,19 @@ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item)
     }
     const int64_t SJ = a;
     const int64_t q = p - cp[SJ];
-    const int64_t cols = (T - SJ * SUPER) < SUPER ? (T - SJ * SUPER) : SUPER;
-    const int64_t per = SUPER * cols;
+    const int64_t cols = (T - SJ * S) < S ? (T - SJ * S) : S;
+    const int64_t per = S * cols;
     if (q < SJ * per) {
         const int64_t SI = q / per, loc = q - SI * per;
-        r.I = (int)(SI * SUPER + loc % SUPER);
-        r.J = (int)(SJ * SUPER + loc / SUPER);
+        r.I = (int)(SI * S + loc % S);
+        r.J = (int)(SJ * S + loc / S);
     } else {
         const int64_t loc = q - SJ * per;
         int64_t j = (int64_t)((sqrt(8.0 * (double)loc + 1.0) - 1.0) * 0.5);
         while ((j + 1) * (j + 2) / 2 <= loc) ++j;
         while (j * (j + 1) / 2 > loc) --j;
-        r.I = (int)(SJ * SUPER + (loc - j * (j + 1) / 2));
-        r.J = (int)(SJ * SUPER + j);
+        r.I = (int)(SJ * S + (loc - j * (j + 1) / 2));
+        r.J = (int)(SJ * S + j);
     }
     return r;
 }
@@ -107,13 +109,15 @@ __device__ __forceinline__ TilePos tile_lookup(const TileTable &t, int64_t item)
 }
 
 // Inverse of tile_decode inside one element: the position p of tile pair
-// (I, J), I <= J < T, in the element's supertile order (cp = its colpre).
-__device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T, int64_t I, int64_t J) {
-    const int64_t SI = I / SUPER, SJ = J / SUPER;
-    const int64_t cols = (T - SJ * SUPER) < SUPER ? (T - SJ * SUPER) : SUPER;
-    const int64_t per = SUPER * cols;
-    if (SI < SJ) return cp[SJ] + SI * per + (I % SUPER) + SUPER * (J % SUPER);
-    const int64_t i = I % SUPER, j = J % SUPER;
+// (I, J), I <= J < T, in the element's order of supertiles of size S (cp = its
+// colpre).
+__device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T, int64_t S, int64_t I,
+                                                    int64_t J) {
+    const int64_t SI = I / S, SJ = J / S;
+    const int64_t cols = (T - SJ * S) < S ? (T - SJ * S) : S;
+    const int64_t per = S * cols;
+    if (SI < SJ) return cp[SJ] + SI * per + (I % S) + S * (J % S);
+    const int64_t i = I % S, j = J % S;
     return cp[SJ] + SJ * per + j * (j + 1) / 2 + i;
 }
 
@@ -186,6 +190,15 @@ __host__ __device__ inline int64_t panel_row_bytes(int prec, int dp) {
 __host__ __device__ inline int64_t panel_row_stride(int prec, int dp) {
     const int64_t b = panel_row_bytes(prec, dp);
     return ((b >> 7) & 1) ? b : b + 128;
+}
+
+// Supertile size of a tile launch.  The hi/lo splits read twice the bytes of
+// a single 16-bit product per pair; for them 24 x 24 supertiles (24 row
+// panels of at most 144 KB, about 3.4 MB, inside an XCD's 4 MB L2) were
+// measured 2-3% faster than 8 x 8 at 1M x 256, while 32 x 32 overflows the L2
+// and is slower.  Single products and longer rows keep 8 x 8.
+inline int supertile_size(int prec, int dp) {
+    return ((prec == P_BF16X3 || prec == P_FP16X3) && panel_row_stride(prec, dp) <= 1152) ? 24 : 8;
 }
 
 struct PackArgs {

@@ -372,17 +372,17 @@ void balanced_endpoints(Arena &arena, const double *f, int64_t n, int nint, doub
 }
 
 // Items before each supertile column of every element (see tile_decode).
-void build_supertile_columns(const std::vector<int64_t> &T, std::vector<int64_t> &colpre,
+void build_supertile_columns(const std::vector<int64_t> &T, int64_t S, std::vector<int64_t> &colpre,
                              std::vector<int64_t> &cp_off) {
     colpre.clear();
     for (size_t e = 0; e < T.size(); ++e) {
-        const int64_t Ts = (T[e] + SUPER - 1) / SUPER;
+        const int64_t Ts = (T[e] + S - 1) / S;
         cp_off[e] = (int64_t)colpre.size();
         int64_t acc = 0;
         colpre.push_back(0);
         for (int64_t SJ = 0; SJ < Ts; ++SJ) {
-            const int64_t cols = std::min<int64_t>(SUPER, T[e] - SJ * SUPER);
-            acc += SJ * SUPER * cols + cols * (cols + 1) / 2;
+            const int64_t cols = std::min<int64_t>(S, T[e] - SJ * S);
+            acc += SJ * S * cols + cols * (cols + 1) / 2;
             colpre.push_back(acc);
         }
         if (acc != T[e] * (T[e] + 1) / 2) throw std::runtime_error("supertile table mismatch");
@@ -679,8 +679,6 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         if (ne > 0) order.push_back((int32_t)e);
     }
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P_e[a] > P_e[b]; });
-    std::vector<int64_t> colpre, cp_off(E_count);
-    build_supertile_columns(T, colpre, cp_off);
     std::vector<int64_t> item_off(order.size() + 1, 0);
     for (size_t k = 0; k < order.size(); ++k) item_off[k + 1] = item_off[k] + P_e[order[k]];
     st.n_slots = S;
@@ -738,6 +736,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     st.precision = prec;
     st.tile_m = st.tile_n = TILE;
     st.split_terms = prec_is_split(prec) ? 3 : 1;
+    const int super = supertile_size(prec, panel_dp(prec, d));
+    std::vector<int64_t> colpre, cp_off(E_count);
+    build_supertile_columns(T, super, colpre, cp_off);
 
     // ---- device tables, panels, thresholds
     int64_t *d_item_off = mem.get<int64_t>(item_off.size());
@@ -758,6 +759,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     tt.colpre = d_colpre;
     tt.cp_off = d_cp_off;
     tt.nord = (int32_t)order.size();
+    tt.super = super;
     tt.n_items = nblocks;
     TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));
     HIPCHK(launch_build_items(tt, d_items, s));
@@ -1374,13 +1376,15 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.tt.elem_off = d_eo;
         ta.tt.blk_off = d_bo;
         std::vector<int64_t> colpre, cp_off(1);
-        build_supertile_columns(std::vector<int64_t>{T}, colpre, cp_off);
+        const int super = supertile_size(precision, dp);
+        build_supertile_columns(std::vector<int64_t>{T}, super, colpre, cp_off);
         int64_t *d_cp = mem.get<int64_t>(colpre.size()), *d_cpo = mem.get<int64_t>(1);
         h2d(d_cp, colpre.data(), (int64_t)colpre.size(), s);
         h2d(d_cpo, cp_off.data(), 1, s);
         ta.tt.colpre = d_cp;
         ta.tt.cp_off = d_cpo;
         ta.tt.nord = 1;
+        ta.tt.super = super;
         ta.tt.n_items = P;
         TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(P, 1));
         HIPCHK(launch_build_items(ta.tt, d_items, s));
