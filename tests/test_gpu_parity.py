@@ -91,6 +91,25 @@ def test_circle(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_elements_across_supertiles(ctx, prec):
+    """Two elements of 40-60 tile rows each, so the tile pairs of one element
+    span several supertile columns (24 x 24 for the hi/lo splits, 8 x 8
+    otherwise), the last one partial, with a ragged last tile: the tile order,
+    the bitmask block numbering and the components' block lookups are all
+    exercised off the diagonal supertiles, and the whole graph and every stage
+    are compared with the oracle."""
+    rng = np.random.default_rng(20110327)
+    X, _ = synth.gaussian_mixture(rng, 9001, 48, 12)
+    params = synth.Params([synth.Axis(synth.LENS_PROJECTION, 2, 0.4, direction=synth.unit_vector(rng, 48))],
+                          eps=10.0, min_pts=8, precision=prec)
+    g, ref = run_and_compare(ctx, X, params)
+    sizes = np.diff(ref.elem_offsets)
+    assert sizes.max() > 24 * 128 and sizes.min() > 8 * 128, sizes
+    assert all(s % 128 for s in sizes), sizes
+    assert g.n_nodes > 2
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_mixture_d64(ctx, prec):
     w = synth.mixture_100k_d64(scale=0.06)
     g, _ = run_and_compare(ctx, w.X, with_prec(w.params, prec))
