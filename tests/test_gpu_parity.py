@@ -510,6 +510,52 @@ def test_errors(ctx):
         small.close()
 
 
+def check_nerve(g):
+    """Edges are exactly the node pairs that share points, weighted by the
+    number of shared points (the nerve of the cover by clusters)."""
+    o = g.node_offsets
+    owner = {}
+    for v in range(g.n_nodes):
+        for p in g.node_members[o[v]:o[v + 1]].tolist():
+            owner.setdefault(p, []).append(v)
+    want = {}
+    for vs in owner.values():
+        for i in range(len(vs)):
+            for j in range(i + 1, len(vs)):
+                want[(vs[i], vs[j])] = want.get((vs[i], vs[j]), 0) + 1
+    got = {(int(a), int(b)): int(c) for (a, b), c in zip(g.edges, g.edge_weights)}
+    assert got == want
+
+
+def check_small_elements(g, X, params, f, lo, hi, count=6):
+    """The smallest non-empty elements: their members are exactly the points
+    inside them (per axis, closed intervals), and their neighbour counts and
+    clusters are the oracle's DBSCAN of those members."""
+    eo = g.stages["elem_offsets"]
+    sizes = np.diff(eo)
+    shape = [a.n_intervals for a in params.axes]
+    checked = 0
+    for e in np.argsort(sizes, kind="stable"):
+        if sizes[e] == 0:
+            continue
+        idx = np.unravel_index(int(e), shape)
+        inside = np.ones(X.shape[0], bool)
+        for a in range(len(shape)):
+            inside &= (lo[a][idx[a]] <= f[a]) & (f[a] <= hi[a][idx[a]])
+        mem = g.stages["elem_members"][eo[e]:eo[e + 1]]
+        want = np.nonzero(inside)[0]
+        assert np.array_equal(mem, want)
+        cnt, core, cid = O.dbscan(X, want, params.eps, params.min_pts)
+        assert np.array_equal(g.stages["slot_count"][eo[e]:eo[e + 1]], cnt)
+        node = g.stages["slot_node"][eo[e]:eo[e + 1]]
+        first = node[node >= 0].min() if (node >= 0).any() else 0
+        assert np.array_equal(np.where(node >= 0, node - first, -1), cid)
+        checked += 1
+        if checked == count:
+            break
+    assert checked > 0
+
+
 def test_full_size_1m_d256(ctx):
     """Paper-scale cloud (1,000,000 x 256) in the benchmark's launch
     configuration: the BF16 split path and the FP32 path give the identical
@@ -541,19 +587,7 @@ def test_full_size_1m_d256(ctx):
         node = gb.stages["slot_node"][eo[e]:eo[e + 1]]
         first = node[node >= 0].min() if (node >= 0).any() else 0
         assert np.array_equal(np.where(node >= 0, node - first, -1), cid)
-    # nerve invariants over the whole graph
-    o = gb.node_offsets
-    owner = {}
-    for v in range(gb.n_nodes):
-        for p in gb.node_members[o[v]:o[v + 1]].tolist():
-            owner.setdefault(p, []).append(v)
-    want = {}
-    for vs in owner.values():
-        for i in range(len(vs)):
-            for j in range(i + 1, len(vs)):
-                want[(vs[i], vs[j])] = want.get((vs[i], vs[j]), 0) + 1
-    got = {(int(a), int(b)): int(c) for (a, b), c in zip(gb.edges, gb.edge_weights)}
-    assert got == want
+    check_nerve(gb)
 
 
 def test_full_size_balanced_cover(ctx):
@@ -594,3 +628,70 @@ def test_full_size_eps_sweep(ctx):
             same_graph(g, cloud.run(p))
     finally:
         cloud.destroy()
+
+
+def test_full_size_100k_d64(ctx):
+    """The 100k x 64 configuration at full size: the whole graph and every
+    stage are the oracle's, in the plain FP32 path and in the matrix-core
+    precisions."""
+    w = synth.mixture_100k_d64()
+    for prec in (synth.PREC_FP32, synth.PREC_BF16X3, synth.PREC_FP16, synth.PREC_AUTO):
+        g, ref = run_and_compare(ctx, w.X, with_prec(w.params, prec))
+    assert g.n_nodes == ref.n_nodes > 20
+
+
+def test_full_size_grid_500k_d128(ctx):
+    """The 2-D configuration at full size (525,000 x 128, 15 x 15 cells, 225
+    elements of uneven sizes): FP16 single products (about 3e8 band pairs
+    re-decided in FP64), the FP16 split and the FP32 path give one graph; the
+    lens values and endpoints of both axes are the oracle's; the smallest
+    elements match the oracle's DBSCAN; the edges are the nerve."""
+    w = synth.mixture_500k_d128_2d()
+    cloud = ctx.cloud(w.X)
+    try:
+        g16 = cloud.run(with_prec(w.params, synth.PREC_FP16), debug=True)
+        gx = cloud.run(with_prec(w.params, synth.PREC_FP16X3))
+        gf = cloud.run(with_prec(w.params, synth.PREC_FP32))
+    finally:
+        cloud.destroy()
+    same_graph(g16, gf)
+    same_graph(gx, gf)
+    assert g16.stats["band_pairs"] > 10 ** 7
+    f = [O.lens(w.X, ax) for ax in w.params.axes]
+    assert np.array_equal(g16.stages["lens"], np.concatenate(f))
+    lo, hi = [], []
+    for a, ax in enumerate(w.params.axes):
+        l, h = O.cover(float(f[a].min()), float(f[a].max()), ax.n_intervals, ax.overlap)
+        lo.append(l)
+        hi.append(h)
+    assert np.array_equal(g16.stages["lo"], np.concatenate(lo))
+    assert np.array_equal(g16.stages["hi"], np.concatenate(hi))
+    check_small_elements(g16, w.X, w.params, f, lo, hi)
+    check_nerve(g16)
+
+
+def test_full_size_serving():
+    """The serving form at full size (the eight resident clouds of 10k to 500k
+    points, the benchmark's stream slots): requests submitted together give
+    the graphs of their solo runs, and the oracle agrees on the requests to
+    the 10k-point clouds."""
+    from paper_2011_03209_amd import binding, serve
+    ctx = binding.Context(arena_bytes=64 << 30, serving_streams=serve.SLOTS)
+    try:
+        raw = synth.serving_clouds()
+        clouds = [ctx.cloud(X) for X in raw]
+        reqs = synth.serving_requests(raw, 10, qps=0.0)
+        alone = [clouds[c].run(p) for (_, c, p) in reqs]
+        tickets = [clouds[c].submit(p) for (_, c, p) in reqs]
+        mixed = [binding.wait(ctx, t) for t in tickets]
+        for a, b in zip(alone, mixed):
+            same_graph(a, b)
+        small = [k for k, (_, c, _) in enumerate(reqs) if raw[c].shape[0] <= 10_000]
+        for k in small[:2]:
+            _, c, p = reqs[k]
+            same_graph(mixed[k], O.mapper(raw[c], p))
+        assert len({c for (_, c, _) in reqs}) >= 4
+        for c in clouds:
+            c.destroy()
+    finally:
+        ctx.close()
