@@ -3,8 +3,11 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include <cstddef>
+#include <stdexcept>
+#include <vector>
 
 namespace mgpu {
 
@@ -55,7 +58,7 @@ struct TilePos {
 
 // Item (global tile-pair index) -> element, row block I, column block J (I <= J)
 // and the bitmask block that stores it.
-__device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item) {
+__host__ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item) {
     int lo = 0, hi = t.nord;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -111,14 +114,34 @@ __device__ __forceinline__ TilePos tile_lookup(const TileTable &t, int64_t item)
 // Inverse of tile_decode inside one element: the position p of tile pair
 // (I, J), I <= J < T, in the element's order of supertiles of size S (cp = its
 // colpre).
-__device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T, int64_t S, int64_t I,
-                                                    int64_t J) {
+__host__ __device__ __forceinline__ int64_t tile_local_index(const int64_t *cp, int64_t T, int64_t S,
+                                                             int64_t I, int64_t J) {
     const int64_t SI = I / S, SJ = J / S;
     const int64_t cols = (T - SJ * S) < S ? (T - SJ * S) : S;
     const int64_t per = S * cols;
     if (SI < SJ) return cp[SJ] + SI * per + (I % S) + S * (J % S);
     const int64_t i = I % S, j = J % S;
     return cp[SJ] + SJ * per + j * (j + 1) / 2 + i;
+}
+
+// Items before each supertile column of every element (host; T[e] = tile
+// rows of element e, S = supertile size): the colpre table of tile_decode.
+inline void build_supertile_columns(const std::vector<int64_t> &T, int64_t S, std::vector<int64_t> &colpre,
+                                    std::vector<int64_t> &cp_off) {
+    colpre.clear();
+    for (size_t e = 0; e < T.size(); ++e) {
+        const int64_t Ts = (T[e] + S - 1) / S;
+        cp_off[e] = (int64_t)colpre.size();
+        int64_t acc = 0;
+        colpre.push_back(0);
+        for (int64_t SJ = 0; SJ < Ts; ++SJ) {
+            const int64_t cols = std::min<int64_t>(S, T[e] - SJ * S);
+            acc += SJ * S * cols + cols * (cols + 1) / 2;
+            colpre.push_back(acc);
+        }
+        if (acc != T[e] * (T[e] + 1) / 2) throw std::runtime_error("supertile table mismatch");
+    }
+    if (colpre.empty()) colpre.push_back(0);
 }
 
 // One pair whose tile distance fell inside the certified band of eps^2.

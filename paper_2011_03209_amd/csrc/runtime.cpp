@@ -371,25 +371,6 @@ void balanced_endpoints(Arena &arena, const double *f, int64_t n, int nint, doub
     hi.assign(val.begin() + nint, val.end());
 }
 
-// Items before each supertile column of every element (see tile_decode).
-void build_supertile_columns(const std::vector<int64_t> &T, int64_t S, std::vector<int64_t> &colpre,
-                             std::vector<int64_t> &cp_off) {
-    colpre.clear();
-    for (size_t e = 0; e < T.size(); ++e) {
-        const int64_t Ts = (T[e] + S - 1) / S;
-        cp_off[e] = (int64_t)colpre.size();
-        int64_t acc = 0;
-        colpre.push_back(0);
-        for (int64_t SJ = 0; SJ < Ts; ++SJ) {
-            const int64_t cols = std::min<int64_t>(S, T[e] - SJ * S);
-            acc += SJ * S * cols + cols * (cols + 1) / 2;
-            colpre.push_back(acc);
-        }
-        if (acc != T[e] * (T[e] + 1) / 2) throw std::runtime_error("supertile table mismatch");
-    }
-    if (colpre.empty()) colpre.push_back(0);
-}
-
 // ----------------------------------------------------------------- autotuner
 // Precision choice: predicted time = matrix-core time + (band fraction x FP64
 // recheck time).  The band fraction of each precision is measured on a

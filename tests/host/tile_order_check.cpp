@@ -1,0 +1,78 @@
+// Host check of the tile order that the tile launch, the item table and the
+// components kernels share (internal.h): for every supertile size the runtime
+// can choose, and for tables of three elements of up to tmax tile rows,
+// tile_decode maps the items one to one onto the tile pairs I <= J < T of
+// each element, item p of an element owns bitmask block blk_off[e] + p, and
+// tile_local_index inverts the decode.  A wrong order would make the kernels
+// write another element's bitmask blocks, so this runs on the host only.
+//
+// usage: tile_order_check [tmax]   prints "ok <items>" and exits 0, or names
+// the first failure and exits 1.
+#include "internal.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <set>
+
+using namespace mgpu;
+
+static int check(int64_t S, const std::vector<int64_t> &Trows, int64_t &items) {
+    const int64_t E = (int64_t)Trows.size();
+    // the runtime's table: elements largest first, bitmask blocks in element order
+    std::vector<int32_t> order;
+    std::vector<int64_t> P(E), blk_off(E), elem_off(E + 1, 0);
+    int64_t nblocks = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t ne = Trows[e] == 0 ? 0 : Trows[e] * TILE - (e % 3) * 37;   // ragged last tile
+        elem_off[e + 1] = elem_off[e] + ne;
+        P[e] = Trows[e] * (Trows[e] + 1) / 2;
+        blk_off[e] = nblocks;
+        nblocks += P[e];
+        if (ne > 0) order.push_back((int32_t)e);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P[a] > P[b]; });
+    std::vector<int64_t> item_off(order.size() + 1, 0);
+    for (size_t k = 0; k < order.size(); ++k) item_off[k + 1] = item_off[k] + P[order[k]];
+    std::vector<int64_t> colpre, cp_off(E);
+    build_supertile_columns(Trows, S, colpre, cp_off);
+    TileTable tt{};
+    tt.item_off = item_off.data();
+    tt.order = order.data();
+    tt.elem_off = elem_off.data();
+    tt.blk_off = blk_off.data();
+    tt.colpre = colpre.data();
+    tt.cp_off = cp_off.data();
+    tt.nord = (int32_t)order.size();
+    tt.super = (int32_t)S;
+    tt.n_items = nblocks;
+    std::vector<char> seen((size_t)nblocks, 0);
+    for (int64_t it = 0; it < nblocks; ++it) {
+        const TilePos r = tile_decode(tt, it);
+        const int64_t T = Trows[r.e];
+        const bool ok = r.e >= 0 && r.e < E && r.I >= 0 && r.I <= r.J && r.J < T && r.blk >= 0 &&
+                        r.blk < nblocks && !seen[r.blk] && r.slot0 == elem_off[r.e] &&
+                        r.ne == elem_off[r.e + 1] - elem_off[r.e] &&
+                        blk_off[r.e] + tile_local_index(colpre.data() + cp_off[r.e], T, S, r.I, r.J) == r.blk;
+        if (!ok) {
+            std::printf("FAIL S=%ld item=%ld e=%d I=%d J=%d blk=%ld\n", (long)S, (long)it, r.e, r.I, r.J,
+                        (long)r.blk);
+            return 1;
+        }
+        seen[r.blk] = 1;
+        ++items;
+    }
+    return 0;
+}
+
+int main(int argc, char **argv) {
+    const int64_t tmax = argc > 1 ? std::atoll(argv[1]) : 200;
+    std::set<int64_t> sizes = {1, 5, 8, 24};
+    for (int prec = 0; prec < 5; ++prec)
+        for (int d : {1, 32, 64, 200, 256, 257, 512, 2050}) sizes.insert(supertile_size(prec, panel_dp(prec, d)));
+    int64_t items = 0;
+    for (int64_t S : sizes)
+        for (int64_t t = 1; t <= tmax; ++t)
+            if (check(S, {t / 2 + 1, 0, t, (t * 7) % 13}, items)) return 1;
+    std::printf("ok %ld\n", (long)items);
+    return 0;
+}
