@@ -73,12 +73,16 @@ __device__ __forceinline__ WaveTile wave_decode(const TileTable &t, int64_t item
     return r;
 }
 
-// item for wave w of a 4-wave block, XCD-aware like the tile launch
-__device__ __forceinline__ int64_t wave_item(int w) {
-    const int64_t G = gridDim.x;
-    const int64_t per = (G + 7) / 8;
-    const int64_t b = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    return b * 4 + w;
+// Logical 4-wave blocks for n items (a multiple of 8); the item of wave w of
+// the block, XCD-aware like the tile launch (n: no item).
+__host__ __device__ inline int64_t wave_block_count(int64_t n) { return 8 * (((n + 3) / 4 + 7) / 8); }
+
+__device__ __forceinline__ int64_t wave_item(int64_t n, int w) {
+    const int64_t G = wave_block_count(n);
+    const int64_t bl = block_linear();
+    if (bl >= G) return n;
+    const int64_t per = G / 8;
+    return ((bl % 8) * per + bl / 8) * 4 + w;
 }
 
 // One wave per bitmask block; lane l holds the block's rows 2l and 2l+1 (8
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
                                                   int32_t *parent) {
     __shared__ int2 queue[4][CC_QCAP];
     const int w = threadIdx.x / WAVE;
-    const WaveTile tl = wave_decode(tt, wave_item(w));
+    const WaveTile tl = wave_decode(tt, wave_item(tt.n_items, w));
     if (!tl.ok) return;
     cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
 }
@@ -366,7 +370,7 @@ __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bi
     __shared__ uint32_t words[4][TILE_WORDS];
     __shared__ int32_t nid[4][2 * TILE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const WaveTile tl = wave_decode(tt, wave_item(w));
+    const WaveTile tl = wave_decode(tt, wave_item(tt.n_items, w));
     if (!tl.ok) return;
     if (!ncflag[rb_off[tl.e] + tl.I] && !ncflag[rb_off[tl.e] + tl.J]) return;   // all core
     uint64_t coreI[2], coreJ[2], ncI[2], ncJ[2];
@@ -532,10 +536,7 @@ __global__ void k_u32_to_i32(const uint32_t *in, int32_t *out, int64_t n) {
 
 inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-inline unsigned wave_blocks(int64_t items) {
-    const int64_t b = (items + 3) / 4;
-    return (unsigned)(8 * ((b + 7) / 8));
-}
+inline dim3 wave_blocks(int64_t items) { return grid_2d(wave_block_count(items)); }
 
 }  // namespace
 

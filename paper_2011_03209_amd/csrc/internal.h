@@ -20,6 +20,18 @@ constexpr int WAVE = 64;
 
 enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_BF16X3 = 2, P_FP16 = 3, P_FP16X3 = 4 };
 
+// One dimension of a dispatch covers at most 2^32 - 1 work-items, so the
+// launches with a workgroup (or a wave) per tile pair -- millions of them --
+// use a 2-D grid of GRID_ROW workgroups per row.  GRID_ROW is a multiple of
+// 8, so the hardware's round-robin of workgroups over the 8 XCDs follows the
+// linear index (block_linear) that those kernels map to their items.
+constexpr int64_t GRID_ROW = 1 << 16;
+inline dim3 grid_2d(int64_t blocks) {
+    const int64_t gx = blocks < GRID_ROW ? blocks : GRID_ROW;
+    return dim3((unsigned)gx, (unsigned)((blocks + gx - 1) / gx));
+}
+__device__ __forceinline__ int64_t block_linear() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+
 inline bool prec_is_split(int p) { return p == P_BF16X3 || p == P_FP16X3; }
 inline bool prec_is_16bit(int p) { return p != P_FP32; }
 inline bool prec_is_bf16(int p) { return p == P_BF16 || p == P_BF16X3; }
@@ -279,7 +291,6 @@ hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
 hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).
 hipError_t launch_build_items(const TileTable &tt, TileItem *items, hipStream_t s);
-int tile_grid_size(int prec, int64_t n_items);
 // band_n[g] = pairs in segment g (<= band_cap), nband their sum.
 hipError_t launch_recheck(const BandPair *band, const unsigned long long *band_n, int32_t nseg,
                           int64_t band_cap, int64_t nband, const float *X, int32_t d,

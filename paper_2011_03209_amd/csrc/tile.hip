@@ -424,10 +424,13 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     __shared__ EpiShared<LV> es;
     // XCD-aware order: the hardware deals workgroups round-robin to the 8
     // XCDs, so consecutive tile pairs (which share row panels) are mapped to
-    // one XCD and its L2.
-    const int64_t G = gridDim.x;
-    const int64_t per = (G + 7) / 8;
-    const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    // one XCD and its L2.  G: the logical workgroups, one per item, rounded
+    // up to a multiple of 8 (the 2-D grid may hold a few more).
+    const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
+    const int64_t bl = block_linear();
+    if (bl >= G) return;
+    const int64_t per = G / 8;
+    const int64_t item = (bl % 8) * per + bl / 8;
     if (item >= a.tt.n_items) return;
     const TilePos tl = tile_lookup(a.tt, item);
     process_tile<PREC, DEBUG, LV>(a, tl, stages, es);
@@ -638,20 +641,15 @@ __global__ void k_build_items(TileTable tt, TileItem *items) {
 template <int PREC>
 hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     if (a.tt.n_items <= 0) return hipSuccess;
-    const int64_t G = 8 * ((a.tt.n_items + 7) / 8);
+    const dim3 grid = grid_2d(8 * ((a.tt.n_items + 7) / 8));
     if (a.n_levels < 1 || a.n_levels > MAX_LEVELS || (a.debug_g && a.n_levels != 1)) return hipErrorInvalidValue;
-    if (a.debug_g) k_tiles<PREC, true, 1><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
-    else if (a.n_levels == 1) k_tiles<PREC, false, 1><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
-    else k_tiles<PREC, false, MAX_LEVELS><<<dim3((unsigned)G), dim3(NTG), 0, s>>>(a);
+    if (a.debug_g) k_tiles<PREC, true, 1><<<grid, dim3(NTG), 0, s>>>(a);
+    else if (a.n_levels == 1) k_tiles<PREC, false, 1><<<grid, dim3(NTG), 0, s>>>(a);
+    else k_tiles<PREC, false, MAX_LEVELS><<<grid, dim3(NTG), 0, s>>>(a);
     return hipGetLastError();
 }
 
 }  // namespace
-
-int tile_grid_size(int prec, int64_t n_items) {
-    (void)prec;
-    return (int)(8 * ((n_items + 7) / 8));
-}
 
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
     switch (prec) {

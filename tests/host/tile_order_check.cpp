@@ -64,7 +64,36 @@ static int check(int64_t S, const std::vector<int64_t> &Trows, int64_t &items) {
     return 0;
 }
 
+// The 2-D grid of the per-item launches: every dimension stays under 2^32
+// work-items (1024 per workgroup at most), rows of workgroups are a multiple
+// of 8 whenever there is more than one, the grid holds every logical
+// workgroup, and the XCD-aware map of the linear index onto items is one to
+// one over the logical workgroups.
+static int check_grid(int64_t blocks) {
+    const dim3 g = grid_2d(blocks);
+    const int64_t gx = g.x, gy = g.y;
+    if (gx < 1 || gx * 1024 >= (1ll << 32) || gy * 1024 >= (1ll << 32) || gx * gy < blocks ||
+        gx * (gy - 1) >= blocks || (gy > 1 && gx % 8)) {
+        std::printf("FAIL grid blocks=%ld gx=%ld gy=%ld\n", (long)blocks, (long)gx, (long)gy);
+        return 1;
+    }
+    if (blocks % 8 == 0 && blocks <= 3000000) {
+        const int64_t per = blocks / 8;
+        std::vector<char> hit((size_t)blocks, 0);
+        for (int64_t bl = 0; bl < blocks; ++bl) {
+            const int64_t item = (bl % 8) * per + bl / 8;
+            if (item < 0 || item >= blocks || hit[item]++) {
+                std::printf("FAIL xcd map blocks=%ld bl=%ld\n", (long)blocks, (long)bl);
+                return 1;
+            }
+        }
+    }
+    return 0;
+}
+
 int main(int argc, char **argv) {
+    for (int64_t blocks : {1ll, 7ll, 8ll, 65535ll, 65536ll, 65544ll, 2950000ll, 5206528ll, 1ll << 31})
+        if (check_grid(blocks)) return 1;
     const int64_t tmax = argc > 1 ? std::atoll(argv[1]) : 200;
     std::set<int64_t> sizes = {1, 5, 8, 24};
     for (int prec = 0; prec < 5; ++prec)

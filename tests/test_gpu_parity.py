@@ -463,6 +463,28 @@ def test_serving_new_features():
         ctx.close()
 
 
+def test_launch_beyond_2_32_work_items(ctx):
+    """One element of 540,000 points: 8.9M tile pairs, so the tile launch
+    (512 work-items per tile pair) exceeds the 2^32 work-items one grid
+    dimension can dispatch and runs as a 2-D grid.  With eps above the
+    cloud's diameter every pair is a neighbour, so every tile pair must have
+    run: each point's count is n, and the graph is one node of all points."""
+    rng = np.random.default_rng(20110330)
+    n = 540_000
+    X = rng.uniform(-1.0, 1.0, size=(n, 4)).astype(np.float32)
+    params = synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0)], eps=10.0, min_pts=2,
+                          precision=synth.PREC_FP16)
+    assert (-(-n // 128)) * (-(-n // 128) + 1) // 2 * 512 > 2 ** 32
+    cloud = ctx.cloud(X)
+    try:
+        g = cloud.run(params, debug=True)
+    finally:
+        cloud.destroy()
+    assert g.n_nodes == 1 and g.n_edges == 0
+    assert np.array_equal(g.node_members, np.arange(n, dtype=np.int32))
+    assert np.all(g.stages["slot_count"] == n)
+
+
 def test_errors(ctx):
     from paper_2011_03209_amd import binding
     X = np.random.default_rng(1).normal(size=(100, 4)).astype(np.float32)
