@@ -132,7 +132,7 @@ constexpr int PK_LANES = 16;
 
 __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
     const int sub = threadIdx.x & (PK_LANES - 1);
-    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / PK_LANES) + threadIdx.x / PK_LANES;
+    const int64_t s = block_linear() * (blockDim.x / PK_LANES) + threadIdx.x / PK_LANES;
     const bool live = s < a.n_slots;                       // lanes of absent slots still join the shuffles
     const int64_t sl = live ? s : a.n_slots - 1;
     const float *x = a.X + (int64_t)a.slot_point[sl] * a.d;
@@ -225,8 +225,10 @@ hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t
 
 hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
     if (a.n_slots <= 0) return hipSuccess;
+    // sixteen lanes per slot: past 268M slots one grid dimension would
+    // exceed 2^32 work-items
     const int64_t blocks = (a.n_slots + 256 / PK_LANES - 1) / (256 / PK_LANES);
-    k_pack<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a);
+    k_pack<<<grid_2d(blocks), dim3(256), 0, s>>>(a);
     return hipGetLastError();
 }
 

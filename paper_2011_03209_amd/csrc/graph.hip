@@ -325,12 +325,27 @@ __global__ void k_cc_compress(int32_t *parent, int64_t n) {
     }
 }
 
+// Root of x without writes.  After the last union the forest is fixed, and
+// k_cc_flatten must leave every core parent at its root: a path-halving store
+// of another thread (uf_find), computed from a pointer it read before this
+// thread's store, could otherwise land after it and put a non-root ancestor
+// back, and k_node_ids would then give the point the cluster id of another
+// root.
+__device__ __forceinline__ int32_t uf_root(const int32_t *P, int32_t x) {
+    int32_t p = ld_rel(&P[x]);
+    while (p != x) {
+        x = p;
+        p = ld_rel(&P[x]);
+    }
+    return x;
+}
+
 __global__ void k_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
                              uint8_t *isroot, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (count[i] >= min_pts) {
-        const int32_t r = uf_find(parent, (int32_t)i);
+        const int32_t r = uf_root(parent, (int32_t)i);
         parent[i] = r;
         isroot[i] = r == (int32_t)i;
     } else {

@@ -652,6 +652,24 @@ def test_full_size_eps_sweep(ctx):
         cloud.destroy()
 
 
+def test_full_size_repeatable(ctx):
+    """1M x 256 at eps = 20 (many small clusters, the most merging in the
+    components pass), run eight times: every graph is the same.  Components
+    are built with concurrent unions and path halving; the final labels must
+    not depend on their timing."""
+    import copy
+    w = synth.mixture_1m_d256()
+    p = copy.copy(w.params)
+    p.eps = 20.0
+    cloud = ctx.cloud(w.X)
+    try:
+        first = cloud.run(p)
+        for _ in range(7):
+            same_graph(cloud.run(p), first)
+    finally:
+        cloud.destroy()
+
+
 def test_full_size_100k_d64(ctx):
     """The 100k x 64 configuration at full size: the whole graph and every
     stage are the oracle's, in the plain FP32 path and in the matrix-core
