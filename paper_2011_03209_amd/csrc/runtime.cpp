@@ -22,6 +22,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -138,10 +139,18 @@ class Arena {
 };
 
 // Allocations of one run, released together.
+// s: the stream whose work uses the allocations.  Normal paths release a
+// scope only after synchronizing that stream.  When an exception unwinds a
+// scope (an arena allocation that fails mid-run, a HIP error), kernels queued
+// earlier may still be running: the stream is synchronized here first, so
+// that memory they use is not handed to another stream's request meanwhile.
 class Scope {
   public:
-    explicit Scope(Arena &a) : a_(a) {}
-    ~Scope() { release_all(); }
+    Scope(Arena &a, hipStream_t s) : a_(a), s_(s), exc_(std::uncaught_exceptions()) {}
+    ~Scope() {
+        if (!held_.empty() && std::uncaught_exceptions() > exc_) (void)hipStreamSynchronize(s_);
+        release_all();
+    }
     template <typename T>
     T *get(uint64_t count) {
         void *p = a_.alloc(count * sizeof(T) + 16);
@@ -159,6 +168,8 @@ class Scope {
 
   private:
     Arena &a_;
+    hipStream_t s_;
+    int exc_;
     std::vector<void *> held_;
     uint64_t bytes_ = 0;
 };
@@ -353,7 +364,7 @@ void balanced_endpoints(Arena &arena, const double *f, int64_t n, int nint, doub
         rank[k] = std::max<int64_t>(0, (int64_t)std::floor(rl[k]));
         rank[nint + k] = std::min<int64_t>(n - 1, (int64_t)std::ceil(rh[k]));
     }
-    Scope mem(arena);                                       // released on return, after the sync
+    Scope mem(arena, s);                                    // released on return, after the sync
     uint64_t *k1 = mem.get<uint64_t>(n), *k2 = mem.get<uint64_t>(n);
     uint32_t *v1 = mem.get<uint32_t>(n), *v2 = mem.get<uint32_t>(n);
     void *tmp = mem.get<char>(sort_temp_bytes(n));
@@ -436,7 +447,7 @@ int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneS
 // return.
 void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32_t mode, int prec,
                 double *dout, mapper_run_stats &st, hipStream_t s) {
-    Scope mem(ctx->arena);
+    Scope mem(ctx->arena, s);
     const int64_t n = cloud->n;
     const int32_t d = cloud->d;
     const int32_t T = (int32_t)((n + TILE - 1) / TILE);
@@ -492,7 +503,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     int32_t *ccnt = mem.get<int32_t>(n);
     int64_t ncand = 0;
     for (;;) {
-        Scope cm(ctx->arena);
+        Scope cm(ctx->arena, s);
         ka.cand = cm.get<int32_t>((uint64_t)n * cmax);
         ka.ccnt = ccnt;
         ka.cmax = cmax;
@@ -541,7 +552,7 @@ struct RunOut {
 Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
                    hipStream_t s, bool may_retry, RunOut &out, const double *eps_list = nullptr,
                    int n_levels = 1) {
-    Scope mem(ctx->arena);
+    Scope mem(ctx->arena, s);
     Events ev(s);
     const int64_t n = cloud->n;
     const int32_t d = cloud->d;
@@ -699,7 +710,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
                 pa[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
                 pb[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
             }
-            Scope tmp(ctx->arena);
+            Scope tmp(ctx->arena, s);
             int32_t *dpa = tmp.get<int32_t>(NS), *dpb = tmp.get<int32_t>(NS);
             double *dD = tmp.get<double>(NS), *dna = tmp.get<double>(NS), *dnb = tmp.get<double>(NS);
             h2d(dpa, pa.data(), NS, s);
@@ -836,7 +847,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
 
     // ---- one graph per level
     for (int lv = 0; lv < n_levels; ++lv) {
-    Scope lm(ctx->arena);                                           // this level's work arrays
+    Scope lm(ctx->arena, s);                                        // this level's work arrays
     Events lev(s);
     lev.mark();                                                     // 0
     int32_t *count = count_all + (int64_t)lv * Sa;
@@ -1217,7 +1228,7 @@ mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int3
     hipStream_t s = ctx->stream;
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        Scope mem(ctx->arena);
+        Scope mem(ctx->arena, s);
         double *dout = mem.get<double>(cloud->n);
         mapper_run_stats st{};
         knn_device(ctx, cloud, k, 0, prec, dout, st, s);
@@ -1317,7 +1328,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
     hipStream_t s = ctx->stream;
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        Scope mem(ctx->arena);
+        Scope mem(ctx->arena, s);
         const int32_t d = cloud->d;
         const int64_t T = (nrows + TILE - 1) / TILE, P = T * (T + 1) / 2;
         uint32_t *slot_point = mem.get<uint32_t>(nrows);
