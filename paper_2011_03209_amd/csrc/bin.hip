@@ -132,7 +132,9 @@ constexpr int PK_LANES = 16;
 
 __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
     const int sub = threadIdx.x & (PK_LANES - 1);
-    const int64_t s = block_linear() * (blockDim.x / PK_LANES) + threadIdx.x / PK_LANES;
+    const int64_t s0 = block_linear() * (blockDim.x / PK_LANES);
+    if (s0 >= a.n_slots) return;                           // a padding block of the 2-D grid
+    const int64_t s = s0 + threadIdx.x / PK_LANES;
     const bool live = s < a.n_slots;                       // lanes of absent slots still join the shuffles
     const int64_t sl = live ? s : a.n_slots - 1;
     const float *x = a.X + (int64_t)a.slot_point[sl] * a.d;

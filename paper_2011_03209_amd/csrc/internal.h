@@ -22,13 +22,17 @@ enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_BF16X3 = 2, P_FP16 = 3, P_FP16X3 = 4
 
 // One dimension of a dispatch covers at most 2^32 - 1 work-items, so the
 // launches with a workgroup (or a wave) per tile pair -- millions of them --
-// use a 2-D grid of GRID_ROW workgroups per row.  GRID_ROW is a multiple of
-// 8, so the hardware's round-robin of workgroups over the 8 XCDs follows the
-// linear index (block_linear) that those kernels map to their items.
+// use a 2-D grid of at most GRID_ROW workgroups per row.  Rows are as short
+// as the row count allows, rounded up to a multiple of 8: fewer than 8
+// padding workgroups per row (they exit at once), and the hardware's
+// round-robin of workgroups over the 8 XCDs follows the linear index
+// (block_linear) that those kernels map to their items.
 constexpr int64_t GRID_ROW = 1 << 16;
 inline dim3 grid_2d(int64_t blocks) {
-    const int64_t gx = blocks < GRID_ROW ? blocks : GRID_ROW;
-    return dim3((unsigned)gx, (unsigned)((blocks + gx - 1) / gx));
+    if (blocks <= GRID_ROW) return dim3((unsigned)blocks, 1u);
+    const int64_t gy = (blocks + GRID_ROW - 1) / GRID_ROW;
+    const int64_t gx = 8 * (((blocks + gy - 1) / gy + 7) / 8);
+    return dim3((unsigned)gx, (unsigned)gy);
 }
 __device__ __forceinline__ int64_t block_linear() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
 

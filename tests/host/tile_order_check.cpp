@@ -72,8 +72,8 @@ static int check(int64_t S, const std::vector<int64_t> &Trows, int64_t &items) {
 static int check_grid(int64_t blocks) {
     const dim3 g = grid_2d(blocks);
     const int64_t gx = g.x, gy = g.y;
-    if (gx < 1 || gx * 1024 >= (1ll << 32) || gy * 1024 >= (1ll << 32) || gx * gy < blocks ||
-        gx * (gy - 1) >= blocks || (gy > 1 && gx % 8)) {
+    if (gx < 1 || gx > GRID_ROW || gx * 1024 >= (1ll << 32) || gy * 1024 >= (1ll << 32) || gx * gy < blocks ||
+        gx * (gy - 1) >= blocks || (gy > 1 && (gx % 8 || gx * gy - blocks >= 8 * gy))) {
         std::printf("FAIL grid blocks=%ld gx=%ld gy=%ld\n", (long)blocks, (long)gx, (long)gy);
         return 1;
     }
@@ -92,7 +92,8 @@ static int check_grid(int64_t blocks) {
 }
 
 int main(int argc, char **argv) {
-    for (int64_t blocks : {1ll, 7ll, 8ll, 65535ll, 65536ll, 65544ll, 2950000ll, 5206528ll, 1ll << 31})
+    for (int64_t blocks : {1ll, 7ll, 8ll, 65535ll, 65536ll, 65537ll, 65544ll, 89375ll, 131071ll, 2950000ll,
+                           5206528ll, 8906040ll, 1ll << 31})
         if (check_grid(blocks)) return 1;
     const int64_t tmax = argc > 1 ? std::atoll(argv[1]) : 200;
     std::set<int64_t> sizes = {1, 5, 8, 24};
