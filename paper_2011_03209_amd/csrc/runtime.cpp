@@ -1020,7 +1020,14 @@ mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const 
         return MAPPER_OK;
     } catch (NoMem &nm) {
         (void)hipStreamSynchronize(s);
+        // a serving request retries if another request holds memory now (it
+        // may have started after this one), and fails only when it ran alone
+        bool others = false;
         if (may_retry) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            others = ctx->active > 1;
+        }
+        if (others) {
             *retry = true;
             return MAPPER_ENOMEM;
         }
@@ -1050,20 +1057,16 @@ void worker_main(mapper_context *ctx, hipStream_t s) {
         }
         mapper_graph *g = nullptr;
         bool retry = false;
-        uint64_t seen = ctx->arena.epoch();
         mapper_status st;
-        {
-            // only retry while another request holds memory that it will return
-            int others;
-            {
-                std::lock_guard<std::mutex> lk(ctx->mu);
-                others = ctx->active - 1;
-            }
-            st = run_guarded(ctx, r->cloud, &r->params.p, s, others > 0, &g, &retry);
-        }
+        // retried on a shortage of arena only while another request holds
+        // memory that it will return (checked when the shortage happens)
+        st = run_guarded(ctx, r->cloud, &r->params.p, s, true, &g, &retry);
         std::unique_lock<std::mutex> lk(ctx->mu);
         --ctx->active;
         if (retry) {
+            // the failed run has released its own memory by now: wait for
+            // another request's release (or 50 ms) before trying again
+            const uint64_t seen = ctx->arena.epoch();
             ctx->pending.push_front(r);
             lk.unlock();
             ctx->arena.wait_release(seen, 50);

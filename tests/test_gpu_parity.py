@@ -438,6 +438,38 @@ def test_serving_alone_vs_mix():
         ctx.close()
 
 
+def test_serving_under_memory_pressure():
+    """Serving with an arena that holds the clouds and about one and a half
+    of the largest request's work arrays, on three stream slots: requests that
+    run out of arena mid-run are queued again until memory is returned (their
+    queued kernels finish before their memory is released), and every graph
+    is the graph of its solo run."""
+    from paper_2011_03209_amd import binding
+    raw = synth.serving_clouds(scale=0.02)
+    reqs = synth.serving_requests(raw, 12, qps=0.0)
+    big = binding.Context(arena_bytes=8 << 30)
+    try:
+        clouds = [big.cloud(X) for X in raw]
+        alone = [clouds[c].run(p) for (_, c, p) in reqs]
+        peak = max(g.stats["arena_peak_bytes"] for g in alone)
+        for c in clouds:
+            c.destroy()
+    finally:
+        big.close()
+    cloud_bytes = sum(X.nbytes + (1 << 20) for X in raw)
+    ctx = binding.Context(arena_bytes=int(cloud_bytes + 1.5 * peak) + (16 << 20), serving_streams=3)
+    try:
+        clouds = [ctx.cloud(X) for X in raw]
+        tickets = [clouds[c].submit(p) for (_, c, p) in reqs]
+        mixed = [binding.wait(ctx, t) for t in tickets]
+        for a, b in zip(alone, mixed):
+            same_graph(a, b)
+        for c in clouds:
+            c.destroy()
+    finally:
+        ctx.close()
+
+
 def test_serving_new_features():
     """Serving requests that use the balanced cover and the whole-cloud
     lenses, mixed with plain ones, give the graphs of their solo runs and the
