@@ -204,11 +204,23 @@ def main():
         t0 = time.perf_counter()
         kd, kst = sub.knn_d2(5, 5)                          # screening precision chosen by the library (FP16)
         t1 = time.perf_counter()
-        sub.destroy()
         print(json.dumps({"sweep": "knn k=5 100000x256 auto", "s": t1 - t0, "screen_precision": PREC_NAME[kst["precision"]],
                           "ms_screen": kst["ms_tiles"], "ms_fp64": kst["ms_recheck"],
                           "candidates": kst["band_pairs"], "pairs": kst["pairs"],
                           "median_knn_d": float(np.sqrt(np.median(kd)))}), file=sys.stderr, flush=True)
+        # whole-cloud lenses on the same 100k x 256 points: the k-NN distance
+        # (k = 5, a density filter) and the eccentricity, 20 intervals
+        for name, kind in (("knn distance k=5", synth.LENS_KNN_DISTANCE), ("eccentricity", synth.LENS_ECCENTRICITY)):
+            pl = synth.Params([synth.Axis(kind, 20, 0.3, column=5)], eps=w.params.eps, min_pts=w.params.min_pts,
+                              precision=prec)
+            sub.run(pl)
+            t0 = time.perf_counter()
+            gl = sub.run(pl)
+            t1 = time.perf_counter()
+            print(json.dumps({"sweep": f"{name} lens mapper 100000x256 {args.precision}", "s_per_graph": t1 - t0,
+                              **{k: gl.stats[k] for k in ("ms_lens", "ms_tiles", "ms_recheck", "ms_cc", "pairs")},
+                              "nodes": gl.n_nodes, "edges": gl.n_edges}), file=sys.stderr, flush=True)
+        sub.destroy()
     g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}
