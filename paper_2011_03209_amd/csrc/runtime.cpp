@@ -209,7 +209,7 @@ struct mapper_context {
     bool stop = false;
     // autotuner cache: (d, eps bucket, norm bucket) -> precision
     std::mutex tune_mu;
-    std::map<std::tuple<int, int, int>, int> tune;
+    std::map<std::tuple<int, int, int>, int> tune;   // TuneKey -> precision
 };
 
 struct mapper_cloud {
@@ -219,6 +219,7 @@ struct mapper_cloud {
     int32_t d = 0;
     float maxabs = 0.f;
     std::atomic<int> inflight{0};
+    mutable double med_norm2 = -1.0;   // median squared row norm (autotuner key; under tune_mu)
 };
 
 struct mapper_graph {
@@ -391,20 +392,49 @@ struct TuneSample {
     std::vector<double> D, na, nb;
 };
 
-int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneSample &ts,
-                     double pairs) {
-    if (ts.D.empty()) return P_BF16X3;
-    std::vector<double> nn = ts.na;
-    nn.insert(nn.end(), ts.nb.begin(), ts.nb.end());
-    std::nth_element(nn.begin(), nn.begin() + nn.size() / 2, nn.end());
-    const double med = std::max(nn[nn.size() / 2], 1e-300);
-    const int eb = (int)std::floor(std::log2(std::max(E, 1e-300) / med) * 4.0);
-    const int nbk = (int)std::floor(std::log2(std::max((double)pairs, 1.0)));
+using TuneKey = std::tuple<int, int, int>;
+
+// The autotuner's cache key: d, eps^2 against the cloud's median squared row
+// norm (quarter octaves) and the pair count (octaves).
+TuneKey tune_key(int d, double E, double med_norm2, double pairs) {
+    const int eb = (int)std::floor(std::log2(std::max(E, 1e-300) / std::max(med_norm2, 1e-300)) * 4.0);
+    const int nbk = (int)std::floor(std::log2(std::max(pairs, 1.0)));
+    return TuneKey{d, eb, nbk};
+}
+
+// Median squared row norm of the cloud from 4096 evenly spaced rows, taken
+// once per cloud.
+double cloud_median_norm2(mapper_context *ctx, const mapper_cloud *cloud, hipStream_t s) {
     {
         std::lock_guard<std::mutex> lk(ctx->tune_mu);
-        auto it = ctx->tune.find({d, eb, nbk});
-        if (it != ctx->tune.end()) return it->second;
+        if (cloud->med_norm2 >= 0) return cloud->med_norm2;
     }
+    const int64_t ns = std::min<int64_t>(cloud->n, 4096);
+    std::vector<int32_t> rows((size_t)ns);
+    for (int64_t q = 0; q < ns; ++q) rows[(size_t)q] = (int32_t)(q * cloud->n / ns);
+    Scope tmp(ctx->arena, s);
+    int32_t *dr = tmp.get<int32_t>(ns);
+    double *dn = tmp.get<double>(ns);
+    h2d(dr, rows.data(), ns, s);
+    HIPCHK(launch_row_norm2(dr, ns, cloud->X, cloud->d, dn, s));
+    std::vector<double> nn;
+    d2h(nn, dn, ns, s);
+    HIPCHK(hipStreamSynchronize(s));
+    std::nth_element(nn.begin(), nn.begin() + nn.size() / 2, nn.end());
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    cloud->med_norm2 = nn[nn.size() / 2];
+    return cloud->med_norm2;
+}
+
+// The cached choice for key, or -1.
+int cached_precision(mapper_context *ctx, const TuneKey &key) {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    auto it = ctx->tune.find(key);
+    return it == ctx->tune.end() ? -1 : it->second;
+}
+
+int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneSample &ts, const TuneKey &key) {
+    if (ts.D.empty()) return P_BF16X3;
     const double u = std::ldexp(1.0, -23);
     auto gam = [&](double k) { return k * u / (1.0 - k * u); };
     const double K16 = dp16, K32 = 32.0 * std::ceil(d / 32.0);
@@ -437,7 +467,7 @@ int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneS
         if (t < tbest) { tbest = t; best = p; }
     }
     std::lock_guard<std::mutex> lk(ctx->tune_mu);
-    ctx->tune[{d, eb, nbk}] = best;
+    ctx->tune[key] = best;
     return best;
 }
 
@@ -683,7 +713,13 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     if (scale_src > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)scale_src));
     const int dp16 = 64 * ((d + 63) / 64);
     int prec = P->precision;
+    TuneKey key{};
     if (prec == MAPPER_PREC_AUTO) {
+        // a cached choice needs no sample (the key uses the cloud's median norm)
+        key = tune_key(d, E, cloud_median_norm2(ctx, cloud, s), (double)pairs);
+        prec = cached_precision(ctx, key);
+    }
+    if (prec < 0) {
         TuneSample ts;
         if (S > 1 && !order.empty()) {
             // sample pairs of elements in proportion to their pair counts
@@ -723,7 +759,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
             d2h(ts.nb, dnb, NS, s);
             HIPCHK(hipStreamSynchronize(s));
         }
-        prec = choose_precision(ctx, d, dp16, E, ts, (double)pairs);
+        prec = choose_precision(ctx, d, dp16, E, ts, key);
     }
     st.precision = prec;
     st.tile_m = st.tile_n = TILE;
