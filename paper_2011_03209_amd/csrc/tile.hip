@@ -289,7 +289,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
 }
 
 // The band pairs of tile row t (its band words bw) at level lv -> FP64
-// recheck list, in segment blockIdx % nseg (no single counter is shared by
+// recheck list, in segment blockIdx.x % nseg (no single counter is shared by
 // the whole launch).
 __device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw, int lv) {
     const int n = __popc(bw.x) + __popc(bw.y) + __popc(bw.z) + __popc(bw.w);
@@ -477,7 +477,9 @@ k_knn(KnnArgs a) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wm = w >> 2, wn = w & 3;
-    const int I = (int)(blockIdx.x / (unsigned)a.C), ch = (int)(blockIdx.x % (unsigned)a.C);
+    const int64_t bl = block_linear();
+    if (bl >= (int64_t)a.T * a.C) return;                  // a padding block of the 2-D grid
+    const int I = (int)(bl / a.C), ch = (int)(bl % a.C);
     const int J0 = (int)((int64_t)ch * a.T / a.C), J1 = (int)((int64_t)(ch + 1) * a.T / a.C);
     const int r = threadIdx.x & (TILE - 1), qtr = threadIdx.x >> 7;
     const int64_t grow = (int64_t)I * TILE + r;
@@ -664,10 +666,10 @@ hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
 
 template <int PREC>
 hipError_t launch_knn_t(int pass, const KnnArgs &a, hipStream_t s) {
-    const unsigned G = (unsigned)((int64_t)a.T * a.C);
-    if (pass == 1 && a.k <= 8) k_knn<PREC, 1, 8><<<dim3(G), dim3(NTG), 0, s>>>(a);
-    else if (pass == 1) k_knn<PREC, 1, KNN_KMAX><<<dim3(G), dim3(NTG), 0, s>>>(a);
-    else k_knn<PREC, 2, KNN_KMAX><<<dim3(G), dim3(NTG), 0, s>>>(a);
+    const dim3 G = grid_2d((int64_t)a.T * a.C);
+    if (pass == 1 && a.k <= 8) k_knn<PREC, 1, 8><<<G, dim3(NTG), 0, s>>>(a);
+    else if (pass == 1) k_knn<PREC, 1, KNN_KMAX><<<G, dim3(NTG), 0, s>>>(a);
+    else k_knn<PREC, 2, KNN_KMAX><<<G, dim3(NTG), 0, s>>>(a);
     return hipGetLastError();
 }
 
