@@ -411,9 +411,32 @@ __global__ void __launch_bounds__(256) k_border(TileTable tt, const uint32_t *bi
         ((uint4 *)W)[lane + 64] = src[lane + 64];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    // non-core rows r: the lowest node among their core neighbour columns
+    // non-core rows r: the lowest node among their core neighbour columns.
+    // Few of them: one pass per row (lane l checks columns l and l + 64);
+    // many: lane l takes rows l and l + 64 and walks the core columns among
+    // its row's own neighbours.
     const int64_t rowbase = tl.slot0 + (int64_t)tl.I * TILE;
-    if (rows_nc) {
+    if (rows_nc && __popcll(ncI[0]) + __popcll(ncI[1]) > 16) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if ((ncI[h] >> lane) & 1ull) {
+                const int r = 64 * h + lane;
+                const uint4 rw = ((const uint4 *)W)[r];   // the row's four words
+                uint64_t m0 = ((((uint64_t)rw.y) << 32) | rw.x) & coreJ[0];
+                uint64_t m1 = ((((uint64_t)rw.w) << 32) | rw.z) & coreJ[1];
+                int32_t m = NOISE;
+                while (m0) {
+                    m = min(m, N[TILE + __ffsll((long long)m0) - 1]);
+                    m0 &= m0 - 1;
+                }
+                while (m1) {
+                    m = min(m, N[TILE + 64 + __ffsll((long long)m1) - 1]);
+                    m1 &= m1 - 1;
+                }
+                if (m != NOISE) atomicMin(&node[rowbase + r], m);
+            }
+        }
+    } else if (rows_nc) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             uint64_t todo = ncI[h];
