@@ -85,14 +85,27 @@ def recorded_traffic(precision: str):
         return None
 
 
-def cpu_baseline(w, target_s: float = 15.0):
-    """The FP64 oracle on a bounded sample: whole cover elements drawn at
-    random until about target_s of oracle work, scaled to the full graph by
-    the number of in-element pairs (the oracle's cost is quadratic in the
-    element size and dominates everything else)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, min_pair_frac: float = 0.2, max_s: float = 240.0):
+    """The FP64 oracle timed on a stratified sample of whole cover elements.
+
+    The oracle's cost is quadratic in the element size, so the sample always
+    holds the largest element and then elements spread evenly over the size
+    range until at least `min_pair_frac` of the
+    in-element pairs have been timed (or `max_s` of DBSCAN time has passed).
+    Each element left out is charged the per-pair time of the timed element
+    closest to it in size; the lens and cover are timed in full."""
     from oracle import oracle as O
     X, p = w.X, w.params
-    ax = p.axes[0]
     t0 = time.perf_counter()
     f = [O.lens(X, a) for a in p.axes]
     los, his = [], []
@@ -100,7 +113,6 @@ def cpu_baseline(w, target_s: float = 15.0):
         lo, hi = O.cover(float(fa.min()), float(fa.max()), a.n_intervals, a.overlap)
         los.append(lo)
         his.append(hi)
-    t_lens = time.perf_counter() - t0
     shape = [a.n_intervals for a in p.axes]
     elems = []
     for e in range(int(np.prod(shape))):
@@ -109,30 +121,50 @@ def cpu_baseline(w, target_s: float = 15.0):
         for a in range(len(p.axes)):
             m &= (los[a][idx[a]] <= f[a]) & (f[a] <= his[a][idx[a]])
         elems.append(np.nonzero(m)[0].astype(np.int32))
-    total_pairs = sum(len(m) * (len(m) + 1) / 2 for m in elems)
-    rng = np.random.default_rng(0)
-    order = rng.permutation(len(elems))
-    done_pairs, t_db = 0.0, 0.0
-    used = 0
-    for e in order:
-        mem = elems[e]
-        if len(mem) == 0:
-            continue
-        if len(mem) > 40000:          # keep the sample bounded
-            continue
-        t1 = time.perf_counter()
-        O.dbscan(X, mem, p.eps, p.min_pts)
-        t_db += time.perf_counter() - t1
-        done_pairs += len(mem) * (len(mem) + 1) / 2
-        used += 1
-        if t_db >= target_s:
+    t_lens = time.perf_counter() - t0
+    pairs = np.array([len(m) * (len(m) + 1) / 2 for m in elems])
+    total_pairs = float(pairs.sum())
+    by_size = [int(e) for e in np.argsort(-pairs, kind="stable") if pairs[e] > 0]
+    # the largest element, then elements spread over the size range (van der
+    # Corput positions 1/2, 1/4, 3/4, 1/8, ... of the list sorted by size)
+    pick, L = [by_size[0]], len(by_size)
+    for k in range(1, 4 * L):
+        q, x, b = 0.0, k, 0.5
+        while x:
+            q += b * (x & 1)
+            x >>= 1
+            b *= 0.5
+        e = by_size[int(round(q * (L - 1)))]
+        if e not in pick:
+            pick.append(e)
+    pick += [e for e in by_size if e not in pick]
+    timed = {}
+    t_db = done_pairs = 0.0
+    for e in pick:
+        if done_pairs >= min_pair_frac * total_pairs or t_db >= max_s:
             break
-    est = t_lens + t_db * total_pairs / max(done_pairs, 1.0)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": f"{used} of {len(elems)} cover elements ({done_pairs:.3g} of {total_pairs:.3g} "
-                      f"in-element pairs, {t_db:.1f} s of DBSCAN) plus the full lens/cover, "
-                      f"scaled by pair count"}
+        t1 = time.perf_counter()
+        O.dbscan(X, elems[e], p.eps, p.min_pts)
+        dt = time.perf_counter() - t1
+        timed[e] = dt
+        t_db += dt
+        done_pairs += pairs[e]
+    sizes = {e: len(elems[e]) for e in timed}
+    est = t_lens + t_db
+    for e in by_size:
+        if e in timed:
+            continue
+        near = min(timed, key=lambda q: abs(sizes[q] - len(elems[e])))
+        est += timed[near] / pairs[near] * pairs[e]
+    largest = by_size[0]
+    return {"value": est, "unit": "s", "cores": O.threads(), "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "measured_pair_frac": done_pairs / total_pairs,
+            "sample": f"{len(timed)} of {len(by_size)} non-empty cover elements timed whole, the largest "
+                      f"({len(elems[largest])} points) included: {done_pairs:.3g} of {total_pairs:.3g} "
+                      f"in-element pairs ({100 * done_pairs / total_pairs:.1f}%), {t_db:.1f} s of DBSCAN; "
+                      f"lens and cover timed in full ({t_lens:.1f} s); every other element charged the "
+                      f"per-pair time of the timed element nearest in size"}
 
 
 def main():
@@ -144,7 +176,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3", "fp16", "fp16x3", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving form only (its own JSON line)")
+    ap.add_argument("--no-serve", action="store_true", help="leave the serving block out of the line")
     ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--sweep", action="store_true", help="time every tile precision (stderr)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -263,6 +296,9 @@ def main():
                    "min_pts": w.params.min_pts, "precision": used},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[used] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[used], "traffic": recorded_traffic(used),
+                     "traffic_source": (f"profiles/mapper_mix1m_d256_{used}.txt: rocprofv3 --pmc FETCH_SIZE, "
+                                        "WRITE_SIZE of this kernel source (matched by its SHA-256), scaled by "
+                                        "a 1 GiB copy; recorded, not measured in this run"),
                      "kernel": f"k_tiles<{used}>", "ms_per_launch": ms_tiles,
                      "algorithmic_flop": flops,
                      "issued_flop": flops * (3 if used.endswith("x3") else 1)},
@@ -273,9 +309,20 @@ def main():
         "paper_context": "about 3 minutes for 1M x 256 (202.87 s, NVIDIA Titan V; Cifar, 500 intervals)",
     }
     line.update(out)
+    ctx.close()
+    del ctx
+    if not args.no_serve and w.name == "mix1m_d256":
+        # the serving form (its own arena and stream slots): saturation
+        # throughput, then p50/p99 latency from arrival at fractions of it
+        from paper_2011_03209_amd import serve
+        T, points = serve.run(n_requests=256, arena_gb=96.0)
+        head = min(points, key=lambda q: abs(q["fraction_of_saturation"] - 0.7))
+        line["serving"] = {"workload": "serving_8clouds_poisson", "requests": 256, "slots": serve.SLOTS,
+                           "precision": "bf16x3", "saturation_graphs_per_s": T, "qps": head["qps"],
+                           "p50_s": head["p50_s"], "p99_s": head["p99_s"],
+                           "p99_submit_lag_s": head["p99_submit_lag_s"], "sweep": points}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
-    ctx.close()
     print(json.dumps(line))
 
 

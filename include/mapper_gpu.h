@@ -185,7 +185,7 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
                                    int32_t n_eps, mapper_graph **out);
 
 /* --- k-th nearest-neighbour distances, synchronous -----------------------
- * The eps-selection module of the CIFAR-10 use case (Case Studies section)
+ * The eps-selection module of the CIFAR-10 use case (Use Cases section)
  * plots the distribution of every point's distance to its k-th nearest
  * neighbour to choose eps.  out_d2[i] (host, n doubles) = the k-th smallest
  * canonical squared distance D(x_i, x_j) over the other points j != i, ties

@@ -49,6 +49,7 @@
  * Contraction is off so every expression rounds exactly as written.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -676,6 +677,12 @@ int orc_ecc_d2(const float *X, int64_t n, int32_t d, double *out)
     }
     free(XT);
     return fail ? ORC_ENOMEM : 0;
+}
+
+/* Threads an OpenMP region of the oracle runs on (for reporting timings). */
+int orc_threads(void)
+{
+    return omp_get_max_threads();
 }
 
 /* Squared distance of one pair by the canonical chain (for pins and for the

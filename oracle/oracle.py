@@ -106,6 +106,8 @@ def lib():
         L.orc_all_d2.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
         L.orc_all_d2.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -320,3 +322,8 @@ def all_d2(X: np.ndarray, rows) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"orc_all_d2 failed ({rc})")
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops run on."""
+    return int(lib().orc_threads())

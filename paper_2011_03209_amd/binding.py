@@ -246,6 +246,7 @@ class Context:
         if getattr(self, "h", None):
             self.L.mapper_context_destroy(self.h)
             self.h = None
+            self.arena = None          # the library no longer uses it: torch may reuse the memory
 
     def __del__(self):
         try:

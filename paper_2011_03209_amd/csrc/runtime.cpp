@@ -174,6 +174,36 @@ class Scope {
     uint64_t bytes_ = 0;
 };
 
+// HIP events for stage timings, kept for reuse: a run marks about a dozen
+// stage boundaries, and serving runs many small requests.
+class EventPool {
+  public:
+    ~EventPool() {
+        for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+    }
+    hipEvent_t get() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!free_.empty()) {
+                hipEvent_t e = free_.back();
+                free_.pop_back();
+                return e;
+            }
+        }
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        return e;
+    }
+    void put(hipEvent_t e) {
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.push_back(e);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<hipEvent_t> free_;
+};
+
 int bits_for(uint64_t maxval) {   // bits needed to hold values in [0, maxval]
     int b = 0;
     while (b < 64 && (maxval >> b) != 0) ++b;
@@ -207,6 +237,7 @@ struct mapper_context {
     uint64_t next_ticket = 1;
     int active = 0;
     bool stop = false;
+    EventPool events;
     // autotuner cache: (d, eps bucket, norm bucket) -> precision
     std::mutex tune_mu;
     std::map<std::tuple<int, int, int>, int> tune;   // TuneKey -> precision
@@ -332,18 +363,23 @@ void h2d(T *dst, const T *src, int64_t count, hipStream_t s) {
     if (count > 0) HIPCHK(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Events of one run.  An event goes back to the pool once the stream has
+// passed it, so a reused event is never still pending.
 struct Events {
     std::vector<hipEvent_t> ev;
     hipStream_t s;
-    explicit Events(hipStream_t st) : s(st) {}
+    EventPool &pool;
+    Events(hipStream_t st, EventPool &p) : s(st), pool(p) {}
     ~Events() {
-        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto e : ev) {
+            (void)hipEventSynchronize(e);
+            pool.put(e);
+        }
     }
     void mark() {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        HIPCHK(hipEventRecord(e, s));
+        hipEvent_t e = pool.get();
         ev.push_back(e);
+        HIPCHK(hipEventRecord(e, s));
     }
     double ms(size_t a, size_t b) {
         if (b >= ev.size()) return 0.0;
@@ -524,7 +560,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     ka.part = mem.get<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
     float *thr = mem.get<float>(n);
     ka.thr = thr;
-    Events ev(s);
+    Events ev(s, ctx->events);
     ev.mark();
     HIPCHK(launch_knn_pass(prec, 1, ka, s));
     HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
@@ -537,7 +573,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
         ka.cand = cm.get<int32_t>((uint64_t)n * cmax);
         ka.ccnt = ccnt;
         ka.cmax = cmax;
-        Events e2(s);
+        Events e2(s, ctx->events);
         e2.mark();
         HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
         HIPCHK(launch_knn_pass(prec, 2, ka, s));
@@ -583,7 +619,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
                    hipStream_t s, bool may_retry, RunOut &out, const double *eps_list = nullptr,
                    int n_levels = 1) {
     Scope mem(ctx->arena, s);
-    Events ev(s);
+    Events ev(s, ctx->events);
     const int64_t n = cloud->n;
     const int32_t d = cloud->d;
     const int na = P->n_axes;
@@ -854,7 +890,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         ta.n_levels = n_levels;
         ta.level_slots = Sa;
         ta.level_words = level_words;
-        Events kt(s);
+        Events kt(s, ctx->events);
         kt.mark();
         HIPCHK(launch_tiles(prec, ta, s));
         kt.mark();
@@ -884,7 +920,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     // ---- one graph per level
     for (int lv = 0; lv < n_levels; ++lv) {
     Scope lm(ctx->arena, s);                                        // this level's work arrays
-    Events lev(s);
+    Events lev(s, ctx->events);
     lev.mark();                                                     // 0
     int32_t *count = count_all + (int64_t)lv * Sa;
     uint32_t *bitmask = bitmask_all + (uint64_t)lv * level_words;

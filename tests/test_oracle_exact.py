@@ -217,3 +217,36 @@ def test_border_goes_to_lowest_cluster(b_first):
     first = set(range(5))            # whichever cluster comes first in index order
     sets = g.node_sets()
     assert sets[0] == first | {border} and border not in sets[1]
+
+
+def test_all_pairs_distances():
+    """orc_all_d2 (the checker of the GPU tile distances and of band
+    soundness) gives the canonical squared distance of every ordered pair of
+    the listed rows: exact on dyadic-grid points, where every FP64 step is
+    exact; bit-equal to the one-pair chain (a separate loop over the original
+    rows) on general data, within gamma_2d of the exact value; symmetric with
+    a zero diagonal; rows in any order, repeats allowed."""
+    rng = np.random.default_rng(11)
+    Xd = synth.dyadic_cloud(rng, 30, 5)
+    rows = rng.permutation(30)[:20].astype(np.int32)
+    rows[7] = rows[3]                                      # a repeated row
+    D = O.all_d2(Xd, rows)
+    assert D.shape == (20, 20)
+    for a in range(20):
+        for b in range(20):
+            x, y = Xd[rows[a]], Xd[rows[b]]
+            assert F(D[a, b]) == sum((F(float(p)) - F(float(q))) ** 2 for p, q in zip(x, y))
+    u = 2.0 ** -53
+    for d in (1, 3, 64, 257):
+        X = (rng.standard_normal((25, d)) * rng.uniform(0.5, 50)).astype(np.float32)
+        r = rng.integers(0, 25, size=17).astype(np.int32)
+        D = O.all_d2(X, r)
+        assert np.array_equal(D, D.T)
+        assert np.all(np.diag(D) == 0.0)
+        gam = 2 * d * u / (1 - 2 * d * u)
+        for a in range(17):
+            for b in range(17):
+                assert D[a, b] == O.pair_d2(X[r[a]], X[r[b]])
+        for a, b in ((0, 1), (5, 16), (16, 2)):
+            exact = sum((F(float(p)) - F(float(q))) ** 2 for p, q in zip(X[r[a]], X[r[b]]))
+            assert abs(F(D[a, b]) - exact) <= F(gam) * exact
