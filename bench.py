@@ -149,6 +149,8 @@ def cpu_baseline(w, min_pair_frac: float = 0.2, max_s: float = 240.0):
         timed[e] = dt
         t_db += dt
         done_pairs += pairs[e]
+        print(f"[cpu_baseline] element {e}: {len(elems[e])} points, {dt:.2f} s "
+              f"({100 * done_pairs / total_pairs:.1f}% of pairs timed)", file=sys.stderr, flush=True)
     sizes = {e: len(elems[e]) for e in timed}
     est = t_lens + t_db
     for e in by_size:
