@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving form only (its own JSON line)")
     ap.add_argument("--no-serve", action="store_true", help="leave the serving block out of the line")
     ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--tile-form", default="auto", choices=["auto", "pairs", "macro"],
+                    help="launch form of the distance tiles (auto: the library's choice)")
     ap.add_argument("--sweep", action="store_true", help="time every tile precision (stderr)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known "
@@ -256,7 +258,8 @@ def main():
                               **{k: gl.stats[k] for k in ("ms_lens", "ms_tiles", "ms_recheck", "ms_cc", "pairs")},
                               "nodes": gl.n_nodes, "edges": gl.n_edges}), file=sys.stderr, flush=True)
         sub.destroy()
-    g, times, stats = time_path(cloud, w.params, args.steps, args.warmup)
+    tflags = {"auto": 0, "pairs": binding.FLAG_TILE_PAIRS, "macro": binding.FLAG_TILE_MACRO}[args.tile_form]
+    g, times, stats = time_path(cloud, w.params, args.steps, args.warmup, flags=tflags)
     print(f"[bench] {args.precision}: {np.median(times):.4f} s/graph", file=sys.stderr, flush=True)
     out = {}
     if not args.no_fp32 and prec != 0:

@@ -121,6 +121,14 @@ typedef struct {
 } mapper_params;
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
+/* Launch form of the distance tiles (the graph is the same in every form).
+ * By default the library picks one: macro tiles (one workgroup per pair of
+ * 256-row blocks, up to four 128 x 128 tile pairs) for single 16-bit
+ * products, tile pairs (one workgroup per 128 x 128 tile pair) otherwise.
+ * These flags force a form; MACRO applies to MAPPER_PREC_BF16/FP16 and to
+ * AUTO when it picks one of them, and is ignored otherwise. */
+#define MAPPER_FLAG_TILE_PAIRS 2u
+#define MAPPER_FLAG_TILE_MACRO 4u
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;
@@ -235,6 +243,19 @@ void mapper_graph_destroy(mapper_graph *g);
 mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_cloud *cloud,
                                    const int32_t *rows, int32_t nrows, int32_t precision,
                                    double eps, double *out_d2, double *out_band);
+
+/* Lens values of one axis (the first stage of mapper_run, same kernels;
+ * n_intervals, overlap and cover are ignored): out (host, n doubles) gets the
+ * canonical FP64 lens of every point (Background section: the filter
+ * function).  Checks the lens, including the correctly rounded square root
+ * of the L2 filter, against the oracle at any size. */
+mapper_status mapper_debug_lens(mapper_context *ctx, const mapper_cloud *cloud, const mapper_axis *axis,
+                                double *out);
+
+/* The library's FP64 square root (the kernel that finishes the whole-cloud
+ * lenses) on n host doubles: out[i] = sqrt(in[i]), to be checked against the
+ * correctly rounded IEEE square root.  in and out are host memory. */
+mapper_status mapper_debug_sqrt(mapper_context *ctx, const double *in, int64_t n, double *out);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libmapper_gpu.so")
 MAPPER_OK, MAPPER_EINVAL, MAPPER_ENOMEM, MAPPER_EDEVICE = 0, -1, -2, -3
 MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
+FLAG_TILE_PAIRS = 2         # force one workgroup per 128 x 128 tile pair
+FLAG_TILE_MACRO = 4         # force macro tiles (single 16-bit products)
 MAX_EPS_VALUES = 4          # MAPPER_MAX_EPS_VALUES
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
@@ -94,6 +96,8 @@ EXPORTS = {
     "mapper_debug_tile_d2": ([_vp, _vp, _P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32,
                               ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double)],
                              ctypes.c_int),
+    "mapper_debug_lens": ([_vp, _vp, _vp, _P(ctypes.c_double)], ctypes.c_int),
+    "mapper_debug_sqrt": ([_vp, _P(ctypes.c_double), ctypes.c_int64, _P(ctypes.c_double)], ctypes.c_int),
 }
 
 
@@ -262,6 +266,13 @@ class Context:
     def cloud(self, X) -> "Cloud":
         return Cloud(self, X)
 
+    def debug_sqrt(self, x) -> np.ndarray:
+        """The library's FP64 square root kernel applied to host doubles."""
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.empty_like(a)
+        _check(self.L.mapper_debug_sqrt(self.h, _dptr(a), int(a.size), _dptr(out)))
+        return out
+
 
 class Cloud:
     """A point cloud resident in the context's arena."""
@@ -324,6 +335,17 @@ class Cloud:
         t = ctypes.c_uint64(0)
         _check(self.ctx.L.mapper_submit(self.ctx.h, self.h, ctypes.byref(p), ctypes.byref(t)))
         return int(t.value)
+
+    def debug_lens(self, axis) -> np.ndarray:
+        """Lens values of one axis (synth.Axis) computed on the GPU, host FP64."""
+        from . import synth
+        params = synth.Params([axis], eps=0.0, min_pts=1)
+        _check_axes(params, self.n, self.d)
+        keep: list = []
+        p = make_params(params, 0, keep)
+        out = np.empty(self.n, np.float64)
+        _check(self.ctx.L.mapper_debug_lens(self.ctx.h, self.h, _vp(ctypes.addressof(p.axis[0])), _dptr(out)))
+        return out
 
     def tile_d2(self, rows: Sequence[int], precision: int, eps: float):
         r = np.ascontiguousarray(rows, dtype=np.int32)

@@ -73,8 +73,9 @@ struct TilePos {
 };
 
 // Item (global tile-pair index) -> element, row block I, column block J (I <= J)
-// and the bitmask block that stores it.
-__host__ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item) {
+// and the bitmask block that stores it, for blocks of `tr` rows (TILE for the
+// tile pairs, MTILE for the macro tiles below).
+__host__ __device__ __forceinline__ TilePos tile_decode_rows(const TileTable &t, int64_t item, int64_t tr) {
     int lo = 0, hi = t.nord;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -86,7 +87,7 @@ __host__ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int6
     r.slot0 = t.elem_off[r.e];
     r.ne = t.elem_off[r.e + 1] - r.slot0;
     r.blk = t.blk_off[r.e] + p;
-    const int64_t T = (r.ne + TILE - 1) / TILE;
+    const int64_t T = (r.ne + tr - 1) / tr;
     const int64_t S = t.super;
     const int64_t Ts = (T + S - 1) / S;
     const int64_t *cp = t.colpre + t.cp_off[r.e];
@@ -112,6 +113,10 @@ __host__ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int6
         r.J = (int)(SJ * S + j);
     }
     return r;
+}
+
+__host__ __device__ __forceinline__ TilePos tile_decode(const TileTable &t, int64_t item) {
+    return tile_decode_rows(t, item, TILE);
 }
 
 // The decoded item from the table (one scalar load instead of the searches).
@@ -158,6 +163,43 @@ inline void build_supertile_columns(const std::vector<int64_t> &T, int64_t S, st
         if (acc != T[e] * (T[e] + 1) / 2) throw std::runtime_error("supertile table mismatch");
     }
     if (colpre.empty()) colpre.push_back(0);
+}
+
+// Macro tiles: pairs of 256-row blocks (P <= Q) of one element, each holding up
+// to four tile pairs (2P + a, 2Q + b), a, b in {0, 1}, kept when
+// 2P + a <= 2Q + b < T.  A macro table is a TileTable over blocks of MTILE
+// rows (its own supertile columns, the same element order); the tile pairs
+// keep their bitmask blocks in the tile table's order, so every consumer of
+// the bitmask reads the same layout whichever form computed it.
+constexpr int MTILE = 2 * TILE;
+
+struct __attribute__((aligned(64))) MacroItem {
+    int32_t e, P, Q, ne;       // element, macro row and column blocks, element size
+    int64_t slot0;             // first slot of the element
+    int64_t blk[4];            // bitmask block of tile pair (2P + a, 2Q + b) at [2a + b]; -1 if absent
+    int64_t pad;
+};
+
+// Macro item `item` of macro table mt, with the bitmask blocks of its tile
+// pairs from the tile table tt (both over the same elements).
+__host__ __device__ inline MacroItem macro_decode(const TileTable &mt, const TileTable &tt, int64_t item) {
+    const TilePos m = tile_decode_rows(mt, item, MTILE);
+    MacroItem r;
+    r.e = m.e;
+    r.P = m.I;
+    r.Q = m.J;
+    r.ne = (int32_t)m.ne;
+    r.slot0 = m.slot0;
+    r.pad = 0;
+    const int64_t T = (m.ne + TILE - 1) / TILE;
+    const int64_t *cp = tt.colpre + tt.cp_off[m.e];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int64_t I = 2 * (int64_t)m.I + a, J = 2 * (int64_t)m.J + b;
+            r.blk[2 * a + b] = (I < T && J < T && I <= J)
+                                   ? tt.blk_off[m.e] + tile_local_index(cp, T, tt.super, I, J) : -1;
+        }
+    return r;
 }
 
 // One pair whose tile distance fell inside the certified band of eps^2.
@@ -268,8 +310,17 @@ struct TileArgs {
     int32_t n_levels; int64_t level_slots; uint64_t level_words;
     float *debug_g;            // non-null: write raw Gram values (debug, one element)
     int64_t debug_ld;
+    const MacroItem *mitems;   // macro form: the decoded macro items (launch_build_macro_items)
+    int64_t n_mitems;
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
+// The same bitmask, counts and band records as launch_tiles, computed by one
+// workgroup per macro item (a.mitems); single 16-bit products (BF16, FP16),
+// one eps value, no debug output.
+hipError_t launch_tiles_macro(int prec, const TileArgs &a, hipStream_t s);
+// items[i] = macro item i of the macro table mt over the tile table tt.
+hipError_t launch_build_macro_items(const TileTable &mt, const TileTable &tt, MacroItem *items, int64_t n,
+                                    hipStream_t s);
 // k-th nearest-neighbour squared distances over the whole cloud (tile.hip).
 constexpr int KNN_KMAX = 16;         // largest k
 

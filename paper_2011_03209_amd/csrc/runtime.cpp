@@ -798,7 +798,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         prec = choose_precision(ctx, d, dp16, E, ts, key);
     }
     st.precision = prec;
-    st.tile_m = st.tile_n = TILE;
+    // launch form: macro tiles for single 16-bit products with one eps value
+    const bool macro_ok = (prec == P_BF16 || prec == P_FP16) && n_levels == 1 &&
+                          (uint64_t)panel_row_stride(prec, panel_dp(prec, d)) * MTILE < (1ull << 32);
+    const bool use_macro = macro_ok && !(P->flags & MAPPER_FLAG_TILE_PAIRS);
+    st.tile_m = st.tile_n = use_macro ? MTILE : TILE;
     st.split_terms = prec_is_split(prec) ? 3 : 1;
     const int super = supertile_size(prec, panel_dp(prec, d));
     std::vector<int64_t> colpre, cp_off(E_count);
@@ -828,6 +832,41 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));
     HIPCHK(launch_build_items(tt, d_items, s));
     tt.items = d_items;
+    // macro table: pairs of 256-row blocks, same element order, supertiles of
+    // 4 x 4 macro pairs (1024 rows a side, as the tile pairs' 8 x 8)
+    MacroItem *d_mitems = nullptr;
+    int64_t n_mitems = 0;
+    if (use_macro) {
+        std::vector<int64_t> T2(E_count), mblk_off(E_count, 0);
+        for (int64_t e = 0; e < E_count; ++e) T2[e] = (eoff[e + 1] - eoff[e] + MTILE - 1) / MTILE;
+        std::vector<int64_t> mitem_off(order.size() + 1, 0);
+        for (size_t k = 0; k < order.size(); ++k) {
+            const int64_t t2 = T2[order[k]];
+            mitem_off[k + 1] = mitem_off[k] + t2 * (t2 + 1) / 2;
+        }
+        n_mitems = mitem_off.back();
+        const int msuper = 4;
+        std::vector<int64_t> mcolpre, mcp_off(E_count);
+        build_supertile_columns(T2, msuper, mcolpre, mcp_off);
+        int64_t *d_mitem_off = mem.get<int64_t>(mitem_off.size());
+        int64_t *d_mcolpre = mem.get<int64_t>(mcolpre.size());
+        int64_t *d_mcp_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
+        int64_t *d_mblk_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
+        h2d(d_mitem_off, mitem_off.data(), (int64_t)mitem_off.size(), s);
+        h2d(d_mcolpre, mcolpre.data(), (int64_t)mcolpre.size(), s);
+        h2d(d_mcp_off, mcp_off.data(), E_count, s);
+        h2d(d_mblk_off, mblk_off.data(), E_count, s);
+        TileTable mt = tt;
+        mt.item_off = d_mitem_off;
+        mt.colpre = d_mcolpre;
+        mt.cp_off = d_mcp_off;
+        mt.blk_off = d_mblk_off;
+        mt.super = msuper;
+        mt.n_items = n_mitems;
+        mt.items = nullptr;
+        d_mitems = mem.get<MacroItem>(std::max<int64_t>(n_mitems, 1));
+        HIPCHK(launch_build_macro_items(mt, tt, d_mitems, n_mitems, s));
+    }
 
     const int dp = panel_dp(prec, d);
     void *panel = mem.get<char>((uint64_t)Sa * (uint64_t)panel_row_stride(prec, dp));
@@ -890,9 +929,12 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         ta.n_levels = n_levels;
         ta.level_slots = Sa;
         ta.level_words = level_words;
+        ta.mitems = d_mitems;
+        ta.n_mitems = n_mitems;
         Events kt(s, ctx->events);
         kt.mark();
-        HIPCHK(launch_tiles(prec, ta, s));
+        if (use_macro) HIPCHK(launch_tiles_macro(prec, ta, s));
+        else HIPCHK(launch_tiles(prec, ta, s));
         kt.mark();
         HIPCHK(hipMemcpyAsync(segn.data(), band_n, (size_t)nseg * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1495,3 +1537,78 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
     }
 }
+
+extern "C" mapper_status mapper_debug_lens(mapper_context *ctx, const mapper_cloud *cloud,
+                                           const mapper_axis *axis, double *out) {
+    if (!ctx || !cloud || !axis || !out) return fail(MAPPER_EINVAL, "null argument");
+    mapper_params p{};
+    p.n_axes = 1;
+    p.axis[0] = *axis;
+    p.axis[0].n_intervals = 1;
+    p.axis[0].overlap = 0.0;
+    p.axis[0].cover = MAPPER_COVER_UNIFORM;
+    p.eps = 0.0;
+    p.min_pts = 1;
+    p.precision = MAPPER_PREC_FP32;
+    mapper_status v = validate(cloud, &p);
+    if (v != MAPPER_OK) return v;
+    hipStream_t s = ctx->stream;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        Scope mem(ctx->arena, s);
+        const int64_t n = cloud->n;
+        const int32_t d = cloud->d;
+        double *f = mem.get<double>(std::max<int64_t>(n, 1));
+        const mapper_axis &ax = p.axis[0];
+        float *dir = nullptr;
+        double *vals = nullptr;
+        if (ax.kind == MAPPER_LENS_PROJECTION) {
+            dir = mem.get<float>(d);
+            h2d(dir, ax.direction, d, s);
+        }
+        if (ax.kind == MAPPER_LENS_VALUES) {
+            vals = mem.get<double>(n);
+            h2d(vals, ax.values, n, s);
+        }
+        if (ax.kind == MAPPER_LENS_KNN_DISTANCE || ax.kind == MAPPER_LENS_ECCENTRICITY) {
+            mapper_run_stats ks{};
+            const bool ecc = ax.kind == MAPPER_LENS_ECCENTRICITY;
+            knn_device(ctx, cloud, ecc ? 1 : ax.column, ecc ? 1 : 0, P_FP16, f, ks, s);
+            HIPCHK(launch_sqrt(f, n, s));
+        } else {
+            HIPCHK(launch_lens(cloud->X, n, d, ax.kind, ax.column, dir, vals, f, s));
+        }
+        HIPCHK(hipMemcpyAsync(out, f, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return MAPPER_OK;
+    } catch (NoMem &) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_ENOMEM, "arena too small for the lens");
+    } catch (DevError &de) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
+    }
+}
+
+extern "C" mapper_status mapper_debug_sqrt(mapper_context *ctx, const double *in, int64_t n, double *out) {
+    if (!ctx || (n > 0 && (!in || !out)) || n < 0) return fail(MAPPER_EINVAL, "null argument or negative count");
+    if (n == 0) return MAPPER_OK;
+    hipStream_t s = ctx->stream;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        Scope mem(ctx->arena, s);
+        double *f = mem.get<double>(n);
+        HIPCHK(hipMemcpyAsync(f, in, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_sqrt(f, n, s));
+        HIPCHK(hipMemcpyAsync(out, f, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return MAPPER_OK;
+    } catch (NoMem &) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_ENOMEM, "arena too small");
+    } catch (DevError &de) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
+    }
+}
+

@@ -436,6 +436,274 @@ __global__ void __launch_bounds__(NTG, 2) k_tiles(TileArgs a) {
     process_tile<PREC, DEBUG, LV>(a, tl, stages, es);
 }
 
+// ------------------------------------------------ one macro tile per workgroup
+// A macro item pairs 256-row blocks P <= Q of one element: up to four tile
+// pairs (2P + a, 2Q + b).  Eight waves; wave (wm, wn) owns rows 128 wm .. +127
+// and columns 64 wn .. + 63 of the 256 x 256 product, i.e. half of tile pair
+// (a, b) = (wm, wn / 2), as 4 x 2 blocks of 32 x 32 accumulators.  Per 16-wide
+// K step a wave reads six operands from LDS for eight products (the tile
+// pair form reads three for two), so the LDS traffic per product halves, and
+// the per-workgroup work of thresholds, counts and the output pass is spread
+// over four tile pairs.  Single 16-bit products only (128 accumulator
+// registers); one workgroup per CU (128 KB of stages).
+//
+// Stage layout as in the tile pair form (128 bytes of each row, the same
+// chunk swizzle): stage rows 0 .. 255 are the P side, 256 .. 511 the Q side.
+constexpr int MSTAGE = 2 * MTILE * GROW;       // 64 KB
+
+struct MacroShared {
+    __attribute__((aligned(16))) float thrA[2 * MTILE];
+    __attribute__((aligned(16))) float thrB[2 * MTILE];
+    __attribute__((aligned(16))) uint32_t words[4][TILE * 4];    // bitmask block of each tile pair
+    __attribute__((aligned(16))) uint32_t bwords[4][TILE * 4];   // its band pairs, same layout
+    uint8_t colcnt[4][2][TILE];   // column counts, one partial per half-wave (<= 64 each)
+};
+
+// LDS-direct plan of one wave for one stage: wave w fills stage rows
+// 64 w .. + 63 (side w / 4) with eight 1 KB loads of 8 rows; rows past the
+// element are clamped to its last row (masked in the epilogue).
+struct MacroFeed {
+    const char *sbase;
+    uint32_t vo[8];
+};
+
+__device__ __forceinline__ void macro_setup(const TileArgs &a, const MacroItem &mi, int w, int lane,
+                                            uint32_t stride, MacroFeed &f) {
+    const int side = w >> 2;
+    const int64_t r0 = (int64_t)(side ? mi.Q : mi.P) * MTILE;
+    const int64_t nrow = (int64_t)mi.ne - r0;                // rows of this side in the element (>= 1)
+    f.sbase = (const char *)a.panel + (mi.slot0 + r0) * (int64_t)stride;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int sr = (w & 3) * 64 + i * 8 + (lane >> 3);  // side row
+        const int lr = w * 64 + i * 8 + (lane >> 3);        // stage row
+        const int c = (lane & 7) ^ ((lr >> 1) & 7);
+        f.vo[i] = (uint32_t)(sr < nrow ? sr : (int)(nrow - 1)) * stride + (uint32_t)(c << 4);
+    }
+}
+
+__device__ __forceinline__ void macro_issue(const MacroFeed &f, uint32_t stage_lds, int w, uint32_t koff) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds_load16(stage_lds + (uint32_t)((w * 8 + i) * 1024), f.sbase + koff, f.vo[i]);
+}
+
+struct MacroAcc {
+    f32x16 c[4][2];
+};
+
+// One stage (four 16-wide K steps) of a wave's products.
+template <int PREC, bool FIRST>
+__device__ __forceinline__ void macro_mfma(const char *stage, MacroAcc &acc, int wm, int wn) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int li = lane & 31, lg = lane >> 5;
+    const f32x16 zero = {};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        u32x4 va[4], vb[2];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) va[rb] = *(const u32x4 *)(stage + goff(wm * 128 + rb * 32 + li, 2 * h + lg));
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+            vb[cb] = *(const u32x4 *)(stage + goff(MTILE + wn * 64 + cb * 32 + li, 2 * h + lg));
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const f32x16 c = FIRST && h == 0 ? zero : acc.c[rb][cb];
+                if constexpr (PREC == P_BF16)
+                    acc.c[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, va[rb]), __builtin_bit_cast(bf16x8, vb[cb]), c, 0, 0, 0);
+                else
+                    acc.c[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, va[rb]), __builtin_bit_cast(f16x8, vb[cb]), c, 0, 0, 0);
+            }
+    }
+}
+
+// acc + this lane's bit of a wave mask (the mask as the carry-in of an add):
+// one instruction, and the mask is consumed at once instead of being kept
+// until the block's end.
+__device__ __forceinline__ int add_lane_bit(int acc, uint64_t mask) {
+    int r;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, 0, %2, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(mask));
+    return r;
+}
+
+// Decisions of accumulator block (rb, cb) of wave (wm, wn) in tile pair
+// (I, J): row words of its bitmask and band pairs to LDS, the lane's column
+// count returned.  FULL: the tile pair lies inside the element and off the
+// diagonal (no masks).
+template <bool FULL>
+__device__ __forceinline__ int macro_block(MacroShared &ms, int sub, int I, int J, int64_t ne, const f32x16 &gv,
+                                           int rb, int cb, int wm, int wn) {
+    const int lane = lane_id_here();
+    const int li = lane & 31, lg = lane >> 5;
+    const bool diag = I == J;
+    const int cl = (wn & 1) * 64 + cb * 32 + li;            // column within the tile pair
+    const int64_t gc = (int64_t)J * TILE + cl;              // element-local column
+    const float Aj = ms.thrA[MTILE + wn * 64 + cb * 32 + li], Bj = ms.thrB[MTILE + wn * 64 + cb * 32 + li];
+    const int r0 = rb * 32 + 4 * lg;                        // register v holds row r0 + 8(v/4) + v%4
+    f32x4 TA[4], TB[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        TA[q] = *(const f32x4 *)&ms.thrA[wm * TILE + r0 + 8 * q];
+        TB[q] = *(const f32x4 *)&ms.thrB[wm * TILE + r0 + 8 * q];
+    }
+    int word = 0, bword = 0, colc = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const float g = gv[v];
+        bool in, band;
+        uint64_t cm;                                        // pairs counted for the column
+        if constexpr (FULL) {
+            in = g >= TA[v >> 2][v & 3] + Aj;
+            band = !(g < TB[v >> 2][v & 3] + Bj);
+            cm = __ballot(in);
+        } else {
+            const int rl = r0 + 8 * (v >> 2) + (v & 3);
+            const int64_t gr = (int64_t)I * TILE + rl;
+            const bool valid = gr < ne && gc < ne && (!diag || rl <= cl);
+            const bool self = diag && rl == cl;
+            in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
+            band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
+            cm = __ballot(in && !self);
+        }
+        colc = add_lane_bit(colc, cm);
+        const uint64_t ib = __ballot(in);
+        word = lane_write((int)(uint32_t)ib, 8 * (v >> 2) + (v & 3), word);
+        word = lane_write((int)(uint32_t)(ib >> 32), 8 * (v >> 2) + 4 + (v & 3), word);
+        const uint64_t bb = __ballot(band) & ~ib;
+        if (bb) {
+            bword = lane_write((int)(uint32_t)bb, 8 * (v >> 2) + (v & 3), bword);
+            bword = lane_write((int)(uint32_t)(bb >> 32), 8 * (v >> 2) + 4 + (v & 3), bword);
+        }
+    }
+    if (lane < 32) {
+        const int at = (rb * 32 + li) * 4 + (wn & 1) * 2 + cb;
+        ms.words[sub][at] = (uint32_t)word;
+        ms.bwords[sub][at] = (uint32_t)bword;
+    }
+    // one block at a time: interleaving the blocks' compares would keep many
+    // 64-bit ballot masks live and spill scalar registers
+    __builtin_amdgcn_sched_barrier(0);
+    return colc;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The workgroup's item in scalar registers (it is the same for every lane;
+// the LDS-direct loads need their base address in scalar registers).
+__device__ __forceinline__ MacroItem uniform_item(const MacroItem &m) {
+    MacroItem r;
+    r.e = __builtin_amdgcn_readfirstlane(m.e);
+    r.P = __builtin_amdgcn_readfirstlane(m.P);
+    r.Q = __builtin_amdgcn_readfirstlane(m.Q);
+    r.ne = __builtin_amdgcn_readfirstlane(m.ne);
+    r.slot0 = uniform64(m.slot0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.blk[k] = uniform64(m.blk[k]);
+    r.pad = 0;
+    return r;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NTG, 1) k_tiles_macro(TileArgs a) {
+    __shared__ __attribute__((aligned(1024))) char stages[2 * MSTAGE];
+    __shared__ MacroShared ms;
+    // XCD-aware order as in k_tiles: consecutive macro items on one XCD
+    const int64_t G = 8 * ((a.n_mitems + 7) / 8);
+    const int64_t bl = block_linear();
+    if (bl >= G) return;
+    const int64_t per = G / 8;
+    const int64_t item = (bl % 8) * per + bl / 8;
+    if (item >= a.n_mitems) return;
+    const MacroItem mi = uniform_item(a.mitems[item]);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wm = w >> 2, wn = w & 3;
+    const uint32_t stride = (uint32_t)panel_row_stride(PREC, a.dp);
+    const int nst = (int)(panel_row_bytes(PREC, a.dp) / GROW);   // >= 2
+    const uint32_t st_lds = lds_addr(stages);
+    MacroFeed feed;
+    macro_setup(a, mi, w, lane, stride, feed);
+    macro_issue(feed, st_lds, w, 0);
+    {   // thresholds of the macro rows (P side) and columns (Q side)
+        const int t = threadIdx.x;
+        const int64_t rw = (t < MTILE ? (int64_t)mi.P : (int64_t)mi.Q) * MTILE + (t & (MTILE - 1));
+        const int64_t slot = mi.slot0 + (rw < mi.ne ? rw : (int64_t)mi.ne - 1);
+        ms.thrA[t] = a.thrA[slot];
+        ms.thrB[t] = a.thrB[slot];
+    }
+    const int sub = wm * 2 + (wn >> 1);                     // this wave's tile pair
+    const bool active = (sub == 0 ? mi.blk[0] : sub == 1 ? mi.blk[1] : sub == 2 ? mi.blk[2] : mi.blk[3]) >= 0;
+    MacroAcc acc;
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+        vm_wait<0>();                                       // this wave's part of stage st has landed
+        lds_barrier();                                      // ... everyone's; stage st - 1 fully read
+        if (st + 1 < nst) macro_issue(feed, st_lds + (uint32_t)(((st + 1) & 1) * MSTAGE), w, (uint32_t)(st + 1) * GROW);
+        if (active) {
+            if (st == 0) macro_mfma<PREC, true>(stages, acc, wm, wn);
+            else macro_mfma<PREC, false>(stages + (st & 1) * MSTAGE, acc, wm, wn);
+        }
+    }
+    const int I = 2 * mi.P + wm, J = 2 * mi.Q + (wn >> 1);
+    if (active) {
+        const int li = lane & 31, lg = lane >> 5;
+        const bool full = I != J && (int64_t)(I + 1) * TILE <= mi.ne && (int64_t)(J + 1) * TILE <= mi.ne;
+        int colc[2] = {0, 0};
+        if (full) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    colc[cb] += macro_block<true>(ms, sub, I, J, mi.ne, acc.c[rb][cb], rb, cb, wm, wn);
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    colc[cb] += macro_block<false>(ms, sub, I, J, mi.ne, acc.c[rb][cb], rb, cb, wm, wn);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) ms.colcnt[sub][lg][(wn & 1) * 64 + cb * 32 + li] = (uint8_t)colc[cb];
+    }
+    lds_barrier();
+    // output: thread t serves row (and column) t % 128 of tile pair t / 128
+    const int t = threadIdx.x;
+    const int os = t >> 7, r = t & (TILE - 1);
+    const int64_t blk = os == 0 ? mi.blk[0] : os == 1 ? mi.blk[1] : os == 2 ? mi.blk[2] : mi.blk[3];
+    if (blk < 0) return;
+    TilePos tl;
+    tl.e = mi.e;
+    tl.I = 2 * mi.P + (os >> 1);
+    tl.J = 2 * mi.Q + (os & 1);
+    tl.ne = mi.ne;
+    tl.slot0 = mi.slot0;
+    tl.blk = blk;
+    const u32x4 wv = *(const u32x4 *)(ms.words[os] + 4 * r);
+    *(u32x4 *)(a.bitmask + (uint64_t)blk * TILE_WORDS + 4 * r) = wv;
+    const int64_t gr = (int64_t)tl.I * TILE + r;
+    const int rc = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
+    if (gr < tl.ne && rc) atomicAdd(&a.count[tl.slot0 + gr], rc);
+    const int64_t gc = (int64_t)tl.J * TILE + r;
+    const int cc = (int)ms.colcnt[os][0][r] + ms.colcnt[os][1][r];
+    if (gc < tl.ne && cc) atomicAdd(&a.count[tl.slot0 + gc], cc);
+    const u32x4 bw = *(const u32x4 *)(ms.bwords[os] + 4 * r);
+    if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, r, bw, 0);
+}
+
+__global__ void k_build_macro_items(TileTable mt, TileTable tt, MacroItem *items, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    items[i] = macro_decode(mt, tt, i);
+}
+
 // ------------------------------------------------------------------- k-NN
 // k-th nearest-neighbour squared distances over the whole cloud (the
 // eps-selection module of the CIFAR-10 use case plots their distribution).
@@ -651,7 +919,32 @@ hipError_t launch_t(const TileArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int PREC>
+hipError_t launch_macro_t(const TileArgs &a, hipStream_t s) {
+    if (a.n_mitems <= 0) return hipSuccess;
+    if (a.n_levels != 1 || a.debug_g || !a.mitems) return hipErrorInvalidValue;
+    // the stage offsets of a side's 256 rows are 32-bit
+    if ((uint64_t)panel_row_stride(PREC, a.dp) * MTILE >= (1ull << 32)) return hipErrorInvalidValue;
+    k_tiles_macro<PREC><<<grid_2d(8 * ((a.n_mitems + 7) / 8)), dim3(NTG), 0, s>>>(a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tiles_macro(int prec, const TileArgs &a, hipStream_t s) {
+    switch (prec) {
+    case P_BF16: return launch_macro_t<P_BF16>(a, s);
+    case P_FP16: return launch_macro_t<P_FP16>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_build_macro_items(const TileTable &mt, const TileTable &tt, MacroItem *items, int64_t n,
+                                    hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_build_macro_items<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(mt, tt, items, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s) {
     switch (prec) {

@@ -12,6 +12,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <set>
 
 using namespace mgpu;
@@ -60,6 +61,50 @@ static int check(int64_t S, const std::vector<int64_t> &Trows, int64_t &items) {
         }
         seen[r.blk] = 1;
         ++items;
+    }
+    // macro tiles (pairs of 256-row blocks) over the same elements: every tile
+    // pair's block is covered by exactly one macro item, at its own (I, J)
+    for (int64_t Sm : {1, 2, 4, 8}) {
+        std::vector<int64_t> T2(E), mitem_off(order.size() + 1, 0), mcolpre, mcp_off(E);
+        for (int64_t e = 0; e < E; ++e) T2[e] = (elem_off[e + 1] - elem_off[e] + MTILE - 1) / MTILE;
+        for (size_t k = 0; k < order.size(); ++k) mitem_off[k + 1] = mitem_off[k] + T2[order[k]] * (T2[order[k]] + 1) / 2;
+        build_supertile_columns(T2, Sm, mcolpre, mcp_off);
+        TileTable mt = tt;
+        mt.item_off = mitem_off.data();
+        mt.colpre = mcolpre.data();
+        mt.cp_off = mcp_off.data();
+        mt.super = (int32_t)Sm;
+        mt.n_items = mitem_off.back();
+        std::vector<char> mseen((size_t)nblocks, 0);
+        int64_t covered = 0;
+        for (int64_t it = 0; it < mt.n_items; ++it) {
+            const MacroItem m = macro_decode(mt, tt, it);
+            const int64_t T = Trows[m.e];
+            bool ok = m.e >= 0 && m.e < E && m.P <= m.Q && (int64_t)m.Q < T2[m.e] && m.slot0 == elem_off[m.e] &&
+                      m.ne == elem_off[m.e + 1] - elem_off[m.e];
+            for (int a = 0; a < 2 && ok; ++a)
+                for (int b = 0; b < 2 && ok; ++b) {
+                    const int64_t I = 2 * m.P + a, J = 2 * m.Q + b, blk = m.blk[2 * a + b];
+                    const bool present = I < T && J < T && I <= J;
+                    if (!present) { ok = blk == -1; continue; }
+                    ok = blk >= 0 && blk < nblocks && !mseen[blk];
+                    if (!ok) break;
+                    const TilePos r = tile_decode(tt, blk - blk_off[m.e] + item_off[std::find(order.begin(), order.end(), m.e) - order.begin()]);
+                    ok = r.e == m.e && r.I == I && r.J == J && r.blk == blk;
+                    mseen[blk] = 1;
+                    ++covered;
+                }
+            if (!ok) {
+                std::printf("FAIL macro S=%ld Sm=%ld item=%ld e=%d P=%d Q=%d\n", (long)S, (long)Sm, (long)it, m.e, m.P,
+                            m.Q);
+                return 1;
+            }
+        }
+        if (covered != nblocks) {
+            std::printf("FAIL macro S=%ld Sm=%ld covered %ld of %ld\n", (long)S, (long)Sm, (long)covered,
+                        (long)nblocks);
+            return 1;
+        }
     }
     return 0;
 }

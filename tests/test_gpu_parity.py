@@ -109,6 +109,48 @@ def test_elements_across_supertiles(ctx, prec):
     assert g.n_nodes > 2
 
 
+def _sized_elements(sizes, d, seed):
+    """A mixture cloud whose cover elements have exactly the given sizes: the
+    lens is the group index (VALUES), one interval per group, no overlap."""
+    rng = np.random.default_rng(seed)
+    X, _ = synth.gaussian_mixture(rng, int(sum(sizes)), d, 6)
+    f = np.repeat(np.arange(len(sizes), dtype=np.float64), sizes)
+    f = f[rng.permutation(f.shape[0])]
+    params = synth.Params([synth.Axis(synth.LENS_VALUES, len(sizes), 0.0, values=f)],
+                          eps=1.05 * float(np.sqrt(2.0 * d)), min_pts=6)
+    return X, params
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP16, synth.PREC_BF16])
+@pytest.mark.parametrize("d", [72, 256])
+def test_macro_tiles(ctx, prec, d):
+    """Macro tiles (pairs of 256-row blocks, up to four tile pairs per
+    workgroup) against the oracle and against the tile-pair form: elements
+    of one partial tile, of two tiles (one diagonal macro tile holding a
+    diagonal, an off-diagonal and an absent tile pair), odd tile counts (a
+    last macro row of one tile row), and enough macro rows to span several
+    4 x 4 macro supertile columns, all with ragged tails."""
+    from paper_2011_03209_amd import binding
+    sizes = [50, 200, 130, 657, 1100, 3033]
+    X, params = _sized_elements(sizes, d, 20110 + d)
+    params = with_prec(params, prec)
+    g, ref = run_and_compare(ctx, X, params)
+    assert np.array_equal(np.diff(ref.elem_offsets), sizes)
+    assert g.stats["tile_m"] == 256, g.stats["tile_m"]
+    cloud = ctx.cloud(X)
+    try:
+        gp = cloud.run(params, debug=True, flags=binding.FLAG_TILE_PAIRS)
+        gm = cloud.run(params, debug=True, flags=binding.FLAG_TILE_MACRO)
+    finally:
+        cloud.destroy()
+    assert gp.stats["tile_m"] == 128 and gm.stats["tile_m"] == 256
+    assert gp.stats["band_pairs"] == gm.stats["band_pairs"] == g.stats["band_pairs"]
+    for k in ("slot_count", "slot_core", "slot_node"):
+        assert np.array_equal(gp.stages[k], gm.stages[k]), k
+    same_graph(gp, ref)
+    same_graph(gm, ref)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_mixture_d64(ctx, prec):
     w = synth.mixture_100k_d64(scale=0.06)
