@@ -244,6 +244,28 @@ mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_cloud *clou
                                    const int32_t *rows, int32_t nrows, int32_t precision,
                                    double eps, double *out_d2, double *out_band);
 
+/* mapper_knn_d2 for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same k-th nearest-neighbour squared distances, bit for bit, with every
+ * device work array (panels, bounds, candidate lists, counters) in a static
+ * 64 MiB device array of the library, one per GPU, resolved when the first
+ * context on that GPU is created; no hipMalloc, hipFree or arena use, and no
+ * host allocation.
+ *   points  device, n x d FP32 row-major (caller-owned, read only);
+ *   out_d2  device, n doubles (caller-owned): the k-th smallest canonical
+ *           squared distance from each point to the others;
+ *   k in [1, min(16, n - 1)]; precision as mapper_knn_d2 (AUTO = FP16).
+ * Runs on the context's stream and returns when the result is written.
+ * Returns MAPPER_EINVAL, before any launch, when the work arrays of n x d
+ * exceed the 64 MiB (about n = 30,000 at d = 256; the message states the
+ * bytes needed), and when many equal distances make the candidate lists
+ * outgrow it.  Calls on one GPU share its array: the library serializes them
+ * (a lock held for the call), so two calls on one GPU never overlap; work of
+ * other entry points is not affected.  The array keeps the last call's
+ * contents; every piece a call relies on is cleared or rewritten first. */
+mapper_status mapper_knn_d2_noalloc(mapper_context *ctx, const float *points, int64_t n, int32_t d, int32_t k,
+                                    int32_t precision, double *out_d2);
+
 /* Lens values of one axis (the first stage of mapper_run, same kernels;
  * n_intervals, overlap and cover are ignored): out (host, n doubles) gets the
  * canonical FP64 lens of every point (Background section: the filter

@@ -97,6 +97,8 @@ EXPORTS = {
                               ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double)],
                              ctypes.c_int),
     "mapper_debug_lens": ([_vp, _vp, _vp, _P(ctypes.c_double)], ctypes.c_int),
+    "mapper_knn_d2_noalloc": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp],
+                              ctypes.c_int),
     "mapper_debug_sqrt": ([_vp, _P(ctypes.c_double), ctypes.c_int64, _P(ctypes.c_double)], ctypes.c_int),
 }
 
@@ -265,6 +267,22 @@ class Context:
 
     def cloud(self, X) -> "Cloud":
         return Cloud(self, X)
+
+    def knn_d2_noalloc(self, points, k: int, out, precision: int = 5):
+        """k-NN squared distances of a device tensor of points (n x d FP32,
+        contiguous) into the device tensor out (n float64), through the
+        entry point that allocates nothing."""
+        torch = self._torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float32
+                and points.dim() == 2 and points.is_contiguous()):
+            raise ValueError("points must be a contiguous n x d float32 CUDA tensor")
+        n, d = points.shape
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+                and out.is_contiguous() and out.numel() == n):
+            raise ValueError("out must be a contiguous float64 CUDA tensor of n elements")
+        _check(self.L.mapper_knn_d2_noalloc(self.h, _vp(points.data_ptr()), int(n), int(d), int(k),
+                                            int(precision), _vp(out.data_ptr())))
+        return out
 
     def debug_sqrt(self, x) -> np.ndarray:
         """The library's FP64 square root kernel applied to host doubles."""

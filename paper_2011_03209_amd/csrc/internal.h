@@ -242,6 +242,10 @@ size_t sort_temp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
                             uint32_t *vals_alt, int64_t n, int key_bits, void *temp,
                             bool *result_in_alt, hipStream_t s);
+// out[i] = i.
+hipError_t launch_iota_u32(uint32_t *out, int64_t n, hipStream_t s);
+// *out = max(*out, max of in[0..n)), for in[i] >= 0.
+hipError_t launch_max_i32(const int32_t *in, int64_t n, int32_t *out, hipStream_t s);
 // out[v] = first index i in sorted keys[0..n) with keys[i] >= v, v in [0, nv].
 hipError_t launch_lower_bounds(const uint64_t *keys, int64_t n, int64_t nv, int64_t *out,
                                hipStream_t s);

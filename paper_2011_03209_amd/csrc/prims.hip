@@ -250,6 +250,36 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
     return hipSuccess;
 }
 
+namespace {
+
+__global__ void k_iota_u32(uint32_t *out, int64_t n) {
+    const int64_t i = block_linear() * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (uint32_t)i;
+}
+
+// *out = max(*out, max_i in[i]) (in[i] >= 0): a wave maximum, then one
+// atomic per wave.
+__global__ void k_max_i32(const int32_t *in, int64_t n, int32_t *out) {
+    const int64_t i = block_linear() * blockDim.x + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    if ((threadIdx.x & (WAVE - 1)) == 0 && v > 0) atomicMax(out, v);
+}
+
+}  // namespace
+
+hipError_t launch_iota_u32(uint32_t *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_iota_u32<<<grid_2d((n + 255) / 256), dim3(256), 0, s>>>(out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_i32(const int32_t *in, int64_t n, int32_t *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_max_i32<<<grid_2d((n + 255) / 256), dim3(256), 0, s>>>(in, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_lower_bounds(const uint64_t *keys, int64_t n, int64_t nv, int64_t *out,
                                hipStream_t s) {
     const int64_t cnt = nv + 1;

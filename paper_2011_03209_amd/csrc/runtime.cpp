@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <exception>
@@ -1200,6 +1201,71 @@ void worker_main(mapper_context *ctx, hipStream_t s) {
 
 // ================================================================= C ABI
 
+// ------------------------------------------------- the no-alloc k-NN scratch
+// mapper_knn_d2_noalloc keeps all of its device work arrays in this array,
+// one copy per GPU (it is part of the library's code object, so every device
+// the library runs on holds it until the process ends).  In host code the
+// name is only a stand-in: the device address of each GPU's copy comes from
+// hipGetSymbolAddress with that GPU current, taken once per device when a
+// context is created there, and only that address is handed to kernels and
+// copies.
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;                      // guards g_scratch and serializes no-alloc calls per device
+void *g_scratch[MAX_DEVICES] = {};
+std::mutex g_noalloc_mu[MAX_DEVICES];
+
+// Resolve (once) this device's copy of the scratch array.
+hipError_t resolve_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[device] = ptr;
+    return hipSuccess;
+}
+
+void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (device >= 0 && device < MAX_DEVICES) ? g_scratch[device] : nullptr;
+}
+
+// Carves 256-byte aligned pieces off the scratch array; no allocation.
+struct ScratchCarve {
+    char *base;
+    uint64_t used, cap;
+    template <class T> T *take(uint64_t count) {
+        const uint64_t b = (count * sizeof(T) + 255) & ~(uint64_t)255;
+        if (used + b > cap) return nullptr;
+        T *p = (T *)(base + used);
+        used += b;
+        return p;
+    }
+};
+
+// Scratch bytes of a k-NN call with C column chunks and candidate lists of
+// cmax entries (the same arrays as knn_device).
+uint64_t knn_scratch_bytes(int64_t n, int32_t d, int prec, int32_t T, int32_t C, int32_t cmax) {
+    auto al = [](uint64_t b) { return (b + 255) & ~(uint64_t)255; };
+    const uint64_t stride = (uint64_t)panel_row_stride(prec, panel_dp(prec, d));
+    return al(256) + al((uint64_t)n * 4) + al((uint64_t)n * stride) + 2 * al((uint64_t)n * 4) +
+           al((uint64_t)C * T * TILE * 4 * KNN_KMAX * 4) + al((uint64_t)n * 4) + al((uint64_t)n * 4) +
+           al((uint64_t)n * cmax * 4);
+}
+}  // namespace
+
 extern "C" {
 
 const char *mapper_last_error(void) { return g_last_error.c_str(); }
@@ -1213,6 +1279,9 @@ mapper_status mapper_context_create(int device, void *arena, uint64_t arena_byte
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(MAPPER_EDEVICE, "no such HIP device");
+    if (device >= MAX_DEVICES) return fail(MAPPER_EDEVICE, "device ordinal beyond the library's table");
+    if (hipError_t e = resolve_scratch(device); e != hipSuccess)
+        return fail(MAPPER_EDEVICE, std::string("scratch array: ") + hipGetErrorString(e));
     auto *c = new mapper_context();
     c->device = device;
     if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus < 1)
@@ -1612,3 +1681,106 @@ extern "C" mapper_status mapper_debug_sqrt(mapper_context *ctx, const double *in
     }
 }
 
+extern "C" mapper_status mapper_knn_d2_noalloc(mapper_context *ctx, const float *points, int64_t n, int32_t d,
+                                               int32_t k, int32_t precision, double *out_d2) {
+    if (!ctx || !points || !out_d2) return fail(MAPPER_EINVAL, "null argument");
+    if (n < 2 || n > 0x7fffffff || d < 1 || d > (1 << 16))
+        return fail(MAPPER_EINVAL, "need 2 <= n < 2^31 and 1 <= d <= 65536");
+    if (k < 1 || k > KNN_KMAX || (int64_t)k > n - 1) return fail(MAPPER_EINVAL, "k must be in [1, min(16, n - 1)]");
+    if (precision < 0 || precision > MAPPER_PREC_AUTO) return fail(MAPPER_EINVAL, "bad precision");
+    const int prec = precision == MAPPER_PREC_AUTO ? P_FP16 : precision;
+    const int32_t T = (int32_t)((n + TILE - 1) / TILE);
+    int32_t C = (int32_t)std::max<int64_t>(1, std::min<int64_t>(T, (4 * ctx->cus + T - 1) / T));
+    int32_t cmax = 64;
+    while (C > 1 && knn_scratch_bytes(n, d, prec, T, C, cmax) > NOALLOC_SCRATCH_BYTES) --C;
+    const uint64_t need = knn_scratch_bytes(n, d, prec, T, C, cmax);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "n x d too large for the no-alloc scratch: needs %llu bytes, the array holds %llu",
+                      (unsigned long long)need, (unsigned long long)NOALLOC_SCRATCH_BYTES);
+        return fail(MAPPER_EINVAL, msg);
+    }
+    char *base = (char *)scratch_of(ctx->device);
+    if (!base) return fail(MAPPER_EDEVICE, "scratch array not resolved for this device");
+    std::lock_guard<std::mutex> serial(g_noalloc_mu[ctx->device]);   // calls on one device share the array
+    hipStream_t s = ctx->stream;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        ScratchCarve sc{base, 0, NOALLOC_SCRATCH_BYTES};
+        uint32_t *flags = sc.take<uint32_t>(64);              // [0] non-finite, [1] max |x| bits, [2] most candidates
+        uint32_t *ident = sc.take<uint32_t>(n);
+        const int dp = panel_dp(prec, d);
+        char *panel = sc.take<char>((uint64_t)n * (uint64_t)panel_row_stride(prec, dp));
+        float *hU = sc.take<float>(n), *hL = sc.take<float>(n);
+        float *part = sc.take<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
+        float *thr = sc.take<float>(n);
+        int32_t *ccnt = sc.take<int32_t>(n);
+        const uint64_t cand_off = sc.used;
+        int32_t *cand = sc.take<int32_t>((uint64_t)n * cmax);
+        if (!flags || !ident || !panel || !hU || !hL || !part || !thr || !ccnt || !cand)
+            return fail(MAPPER_EINVAL, "scratch layout does not fit");   // not reached: sized above
+        // finiteness and the largest magnitude (the panels' power-of-two scale)
+        HIPCHK(hipMemsetAsync(flags, 0, 16, s));
+        HIPCHK(launch_check_cloud(points, n * (int64_t)d, flags, s));
+        uint32_t h[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[0]) return fail(MAPPER_EINVAL, "points have non-finite coordinates");
+        float maxabs = 0.f;
+        std::memcpy(&maxabs, &h[1], 4);
+        double scale = 1.0;
+        if (maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)maxabs));
+        HIPCHK(launch_iota_u32(ident, n, s));
+        PackArgs pk{};
+        pk.X = points;
+        pk.d = d;
+        pk.dp = dp;
+        pk.slot_point = ident;
+        pk.n_slots = n;
+        pk.prec = prec;
+        pk.scale = scale;
+        pk.n_levels = 1;
+        pk.E_scaled[0] = 0.0;
+        pk.panel = panel;
+        pk.thrA = hU;
+        pk.thrB = hL;
+        HIPCHK(launch_pack(pk, s));
+        KnnArgs ka{};
+        ka.t.panel = panel;
+        ka.t.dp = dp;
+        ka.t.n_levels = 1;
+        ka.mode = 0;
+        ka.k = k;
+        ka.n = n;
+        ka.T = T;
+        ka.C = C;
+        ka.hU = hU;
+        ka.hL = hL;
+        ka.part = part;
+        ka.thr = thr;
+        HIPCHK(launch_knn_pass(prec, 1, ka, s));
+        HIPCHK(launch_knn_merge(part, C, T, n, k, thr, s));
+        for (;;) {
+            ka.cand = cand;
+            ka.ccnt = ccnt;
+            ka.cmax = cmax;
+            HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
+            HIPCHK(hipMemsetAsync(flags + 2, 0, 4, s));
+            HIPCHK(launch_knn_pass(prec, 2, ka, s));
+            HIPCHK(launch_knn_final(points, d, n, k, cand, ccnt, cmax, 0, out_d2, s));
+            HIPCHK(launch_max_i32(ccnt, n, (int32_t *)(flags + 2), s));
+            int32_t most = 0;
+            HIPCHK(hipMemcpyAsync(&most, flags + 2, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (most <= cmax) break;
+            // longer candidate lists: the rest of the array, or an error
+            if ((uint64_t)most * (uint64_t)n * 4 > NOALLOC_SCRATCH_BYTES - cand_off)
+                return fail(MAPPER_EINVAL, "candidate lists exceed the no-alloc scratch (many equal distances)");
+            cmax = most;
+        }
+        return MAPPER_OK;
+    } catch (DevError &de) {
+        (void)hipStreamSynchronize(s);
+        return fail(MAPPER_EDEVICE, std::string("HIP error: ") + hipGetErrorString(de.e));
+    }
+}
