@@ -122,13 +122,20 @@ typedef struct {
 
 #define MAPPER_FLAG_DEBUG_STAGES 1u   /* keep per-stage arrays in the graph */
 /* Launch form of the distance tiles (the graph is the same in every form).
- * By default the library picks one: macro tiles (one workgroup per pair of
- * 256-row blocks, up to four 128 x 128 tile pairs) for single 16-bit
- * products, tile pairs (one workgroup per 128 x 128 tile pair) otherwise.
- * These flags force a form; MACRO applies to MAPPER_PREC_BF16/FP16 and to
- * AUTO when it picks one of them, and is ignored otherwise. */
+ * By default the library picks one: tile pairs (one workgroup per 128 x 128
+ * tile pair) when the tile pairs are screened (MAPPER_FLAG_NO_SCREEN below),
+ * else macro tiles (one workgroup per pair of 256-row blocks, up to four
+ * tile pairs) for single 16-bit products and tile pairs otherwise.  These
+ * flags force a form; MACRO (which turns screening off) applies to
+ * MAPPER_PREC_BF16/FP16 and to AUTO when it picks one of them, and is
+ * ignored otherwise. */
 #define MAPPER_FLAG_TILE_PAIRS 2u
 #define MAPPER_FLAG_TILE_MACRO 4u
+/* Compute every tile pair of every element.  By default a tile pair whose
+ * rows' bounding balls lie more than eps apart is proven to hold no
+ * neighbour pair and skipped (clouds of at least 1024 points and d <= 2048,
+ * whose members are laid out in a locality order); the graph is the same. */
+#define MAPPER_FLAG_NO_SCREEN 8u
 
 typedef struct mapper_context mapper_context;
 typedef struct mapper_cloud mapper_cloud;
@@ -146,6 +153,12 @@ typedef struct {
     int32_t tile_m, tile_n, split_terms;
     int32_t tile_launches;   /* > 1 if the band list had to grow */
     double band_halfwidth;   /* largest FP32 half-width of the eps^2 band */
+    uint64_t reserved_bytes; /* workspace reserved in one block after binning */
+    uint64_t reserve_overflow_bytes;  /* taken beyond the reservation (a regrown band list) */
+    int32_t admission_waits; /* serving: times the request waited for its reservation */
+    int32_t tile_passes_redone;  /* serving: tile passes lost to a later shortage */
+    int64_t tiles_screened_out;  /* tile pairs proven empty by their balls, not computed */
+    int64_t pairs_computed;  /* in-element pairs of the tile pairs computed */
 } mapper_run_stats;
 
 /* --- context ------------------------------------------------------------

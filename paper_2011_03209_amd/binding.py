@@ -22,6 +22,7 @@ MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
 FLAG_TILE_PAIRS = 2         # force one workgroup per 128 x 128 tile pair
 FLAG_TILE_MACRO = 4         # force macro tiles (single 16-bit products)
+FLAG_NO_SCREEN = 8          # compute every tile pair (no ball screening)
 MAX_EPS_VALUES = 4          # MAPPER_MAX_EPS_VALUES
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
@@ -57,7 +58,10 @@ class RunStats(ctypes.Structure):
                 ("arena_peak_bytes", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
                 ("split_terms", ctypes.c_int32), ("tile_launches", ctypes.c_int32),
-                ("band_halfwidth", ctypes.c_double)]
+                ("band_halfwidth", ctypes.c_double),
+                ("reserved_bytes", ctypes.c_uint64), ("reserve_overflow_bytes", ctypes.c_uint64),
+                ("admission_waits", ctypes.c_int32), ("tile_passes_redone", ctypes.c_int32),
+                ("tiles_screened_out", ctypes.c_int64), ("pairs_computed", ctypes.c_int64)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapper_gpu.so")
-SOURCES = ["runtime.cpp", "prims.hip", "lens.hip", "bin.hip", "tile.hip", "recheck.hip", "graph.hip"]
+SOURCES = ["runtime.cpp", "prims.hip", "lens.hip", "bin.hip", "cells.hip", "tile.hip", "recheck.hip",
+           "graph.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

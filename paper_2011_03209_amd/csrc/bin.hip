@@ -38,39 +38,54 @@ __device__ __forceinline__ int last_le(const double *a, int n, double f) {
     return lo - 1;
 }
 
+// *out += the wave's sum of v (one atomic per wave; every lane of the wave
+// calls it).
+__device__ __forceinline__ void wave_pair_sum(unsigned long long v, unsigned long long *out) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && v) atomicAdd(out, v);
+}
+
+// Per point: its range of intervals on each axis, its number of elements,
+// and (pair_sum, optional) the sum over points of C(count, 2), which bounds
+// the node pairs that share a point and so the edge builder's work.
 __global__ void k_member_count(const double *f0, const double *f1, int64_t n,
                                const double *lo0, const double *hc0, int32_t n0,
                                const double *lo1, const double *hc1, int32_t n1,
-                               int32_t *range4, int32_t *count) {
+                               int32_t *range4, int32_t *count, unsigned long long *pair_sum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double a = f0[i];
-    const int kl0 = first_ge(hc0, n0, a), kh0 = last_le(lo0, n0, a);
-    int c = kh0 >= kl0 ? kh0 - kl0 + 1 : 0;
-    int kl1 = 0, kh1 = 0;
-    if (f1) {
-        const double b = f1[i];
-        kl1 = first_ge(hc1, n1, b);
-        kh1 = last_le(lo1, n1, b);
-        c *= kh1 >= kl1 ? kh1 - kl1 + 1 : 0;
+    int c = 0;
+    if (i < n) {
+        const double a = f0[i];
+        const int kl0 = first_ge(hc0, n0, a), kh0 = last_le(lo0, n0, a);
+        c = kh0 >= kl0 ? kh0 - kl0 + 1 : 0;
+        int kl1 = 0, kh1 = 0;
+        if (f1) {
+            const double b = f1[i];
+            kl1 = first_ge(hc1, n1, b);
+            kh1 = last_le(lo1, n1, b);
+            c *= kh1 >= kl1 ? kh1 - kl1 + 1 : 0;
+        }
+        range4[4 * i + 0] = kl0;
+        range4[4 * i + 1] = kh0;
+        range4[4 * i + 2] = kl1;
+        range4[4 * i + 3] = kh1;
+        count[i] = c;
     }
-    range4[4 * i + 0] = kl0;
-    range4[4 * i + 1] = kh0;
-    range4[4 * i + 2] = kl1;
-    range4[4 * i + 3] = kh1;
-    count[i] = c;
+    // every lane of the wave reaches this point (no early return)
+    if (pair_sum) wave_pair_sum((unsigned long long)c * (unsigned long long)(c > 0 ? c - 1 : 0) / 2, pair_sum);
 }
 
 __global__ void k_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, uint64_t *keys, uint32_t *vals) {
+                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t p = pos[i];
     const int kl0 = range4[4 * i], kh0 = range4[4 * i + 1];
     const int kl1 = two_d ? range4[4 * i + 2] : 0, kh1 = two_d ? range4[4 * i + 3] : 0;
+    const uint64_t c = cell ? (uint64_t)cell[i] : 0;
     for (int k0 = kl0; k0 <= kh0; ++k0)
         for (int k1 = kl1; k1 <= kh1; ++k1) {
-            keys[p] = (uint64_t)((int64_t)k0 * (two_d ? n1 : 1) + k1);
+            keys[p] = ((uint64_t)((int64_t)k0 * (two_d ? n1 : 1) + k1) << cell_bits) | c;
             vals[p] = (uint32_t)i;
             ++p;
         }
@@ -212,16 +227,17 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
 hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
                                const double *lo0, const double *hc0, int32_t n0,
                                const double *lo1, const double *hc1, int32_t n1,
-                               int32_t *range4, int32_t *count, hipStream_t s) {
+                               int32_t *range4, int32_t *count, unsigned long long *pair_sum, hipStream_t s) {
     k_member_count<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
-        f0, f1, n, lo0, hc0, n0, lo1, hc1, n1, range4, count);
+        f0, f1, n, lo0, hc0, n0, lo1, hc1, n1, range4, count, pair_sum);
     return hipGetLastError();
 }
 
 hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals,
+                              hipStream_t s) {
     k_member_emit<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(range4, pos, n, n1, two_d,
-                                                                         keys, vals);
+                                                                         cell, cell_bits, keys, vals);
     return hipGetLastError();
 }
 

@@ -9,8 +9,9 @@
 // lanes at once (see k_cc_tiles).
 //
 // Border points: a non-core point with core neighbours joins the lowest node
-// id among them (atomicMin over the same blocks).  Nodes are numbered by a
-// scan over root flags in slot order, i.e. by (element, smallest core index).
+// id among them (atomicMin over the same blocks).  Nodes are numbered by
+// (element, smallest core point id): the roots, listed by a scan over root
+// flags, are sorted by that key.
 //
 // Edges (nerve of the clusters): (node, point) pairs are sorted by point with
 // a stable radix sort, each point emits the node pairs it joins, and a sort
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
 // so nearly every block there passes its label check without merges.  One
 // wave per (element, J); `rb_off` numbers the column blocks of all elements.
 __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb_off, int64_t n_rb,
-                                                 int32_t n_elem, const uint32_t *bitmask,
+                                                 int32_t n_elem, const int64_t *row0_blk, const uint32_t *bitmask,
                                                  const int32_t *count, int32_t min_pts,
                                                  int32_t *parent) {
     __shared__ int2 queue[4][CC_QCAP];
@@ -267,7 +268,12 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
     tl.ne = tt.elem_off[e + 1] - tl.slot0;
     const int64_t T = (tl.ne + TILE - 1) / TILE;
     if (tl.ne <= 0 || tl.J >= T) return;
-    tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, tt.super, 0, tl.J);
+    if (row0_blk) {
+        tl.blk = row0_blk[k];                           // screened out: no neighbours to hook
+        if (tl.blk < 0) return;
+    } else {
+        tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, tt.super, 0, tl.J);
+    }
     if (tl.J == 0) {
         cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
         return;
@@ -353,18 +359,46 @@ __global__ void k_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *par
     }
 }
 
+// Canonical cluster numbering.  Slots are laid out by (element, cell), not
+// by point id, so the root of a component (its smallest slot) need not hold
+// its smallest core point: nodes are numbered by sorting the roots by
+// (element, smallest core point id), as the labelling rule asks.
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// minpt[r] = the smallest point id among the core slots whose root is r.
+__global__ void k_root_minpt(const int32_t *count, int32_t min_pts, const int32_t *parent,
+                             const uint32_t *slot_point, int32_t *minpt, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && count[i] >= min_pts) atomicMin(&minpt[parent[i]], (int32_t)slot_point[i]);
+}
+
+// Root of rank r (roots counted in slot order): key (element, minpt), value r.
+__global__ void k_root_keys(const uint8_t *isroot, const int64_t *rank, const uint64_t *slot_elem,
+                            const int32_t *minpt, uint64_t *keys, uint32_t *vals, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !isroot[i]) return;
+    const int64_t r = rank[i];
+    keys[r] = (slot_elem[i] << 32) | (uint64_t)(uint32_t)minpt[i];
+    vals[r] = (uint32_t)r;
+}
+
+// After the sort by key: the node id of root rank vals[p] is p.
+__global__ void k_root_order(const uint64_t *keys, const uint32_t *vals, int64_t N, int32_t *node_of_rank,
+                             int32_t *node_elem) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    node_of_rank[vals[p]] = (int32_t)p;
+    node_elem[p] = (int32_t)(keys[p] >> 32);
+}
+
 __global__ void k_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent,
-                           const int64_t *rank, const uint64_t *slot_elem, int32_t *node,
-                           int32_t *node_elem, int64_t n) {
+                           const int64_t *rank, const int32_t *node_of_rank, int32_t *node, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (count[i] >= min_pts) {
-        const int32_t r = parent[i];
-        node[i] = (int32_t)rank[r];
-        if (r == (int32_t)i) node_elem[rank[i]] = (int32_t)slot_elem[i];
-    } else {
-        node[i] = NOISE;
-    }
+    node[i] = count[i] >= min_pts ? node_of_rank[rank[parent[i]]] : NOISE;
 }
 
 // flag[rb] = 1 if the 128-slot row block rb (row blocks numbered per element,
@@ -499,11 +533,13 @@ __global__ void k_flag_labelled(const int32_t *node, uint8_t *flag, int64_t n) {
     if (i < n) flag[i] = node[i] != NOISE;
 }
 
+// (node, point) pairs keyed node << pbits | point: sorted, each node's
+// members come out in ascending point order whatever the slot order.
 __global__ void k_member_pairs(const int32_t *node, const uint32_t *slot_point, const int64_t *pos,
-                               int64_t n, uint64_t *keys, uint32_t *vals) {
+                               int64_t n, int pbits, uint64_t *keys, uint32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || node[i] == NOISE) return;
-    keys[pos[i]] = (uint64_t)node[i];
+    keys[pos[i]] = ((uint64_t)node[i] << pbits) | (uint64_t)slot_point[i];
     vals[pos[i]] = slot_point[i];
 }
 
@@ -598,10 +634,10 @@ hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const i
 }
 
 hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
-                          const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
+                          const int64_t *row0_blk, const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
                           int32_t *parent, hipStream_t s) {
     if (n_rb <= 0) return hipSuccess;
-    k_cc_hook<<<dim3((unsigned)((n_rb + 3) / 4)), 256, 0, s>>>(tt, rb_off, n_rb, n_elem, bitmask, count,
+    k_cc_hook<<<dim3((unsigned)((n_rb + 3) / 4)), 256, 0, s>>>(tt, rb_off, n_rb, n_elem, row0_blk, bitmask, count,
                                                                min_pts, parent);
     return hipGetLastError();
 }
@@ -613,11 +649,28 @@ hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *par
     return hipGetLastError();
 }
 
-hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent,
-                           const int64_t *root_rank, const uint64_t *slot_elem, int32_t *node,
-                           int32_t *node_elem, int64_t n, hipStream_t s) {
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_node_ids<<<nblk(n), 256, 0, s>>>(count, min_pts, parent, root_rank, slot_elem, node, node_elem, n);
+    k_fill_i32<<<nblk(n), 256, 0, s>>>(a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_keys(const int32_t *count, int32_t min_pts, const int32_t *parent,
+                           const uint32_t *slot_point, const uint8_t *isroot, const int64_t *rank,
+                           const uint64_t *slot_elem, int32_t *minpt, uint64_t *keys, uint32_t *vals,
+                           int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_i32<<<nblk(n), 256, 0, s>>>(minpt, n, 0x7fffffff);
+    k_root_minpt<<<nblk(n), 256, 0, s>>>(count, min_pts, parent, slot_point, minpt, n);
+    k_root_keys<<<nblk(n), 256, 0, s>>>(isroot, rank, slot_elem, minpt, keys, vals, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent, const int64_t *rank,
+                           const uint64_t *sorted_keys, const uint32_t *sorted_vals, int64_t N,
+                           int32_t *node_of_rank, int32_t *node, int32_t *node_elem, int64_t n, hipStream_t s) {
+    if (N > 0) k_root_order<<<nblk(N), 256, 0, s>>>(sorted_keys, sorted_vals, N, node_of_rank, node_elem);
+    if (n > 0) k_node_ids<<<nblk(n), 256, 0, s>>>(count, min_pts, parent, rank, node_of_rank, node, n);
     return hipGetLastError();
 }
 
@@ -644,9 +697,9 @@ hipError_t launch_flag_labelled(const int32_t *node, uint8_t *flag, int64_t n, h
 }
 
 hipError_t launch_member_pairs(const int32_t *node, const uint32_t *slot_point, const int64_t *pos,
-                               int64_t n, uint64_t *keys, uint32_t *vals, hipStream_t s) {
+                               int64_t n, int pbits, uint64_t *keys, uint32_t *vals, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_member_pairs<<<nblk(n), 256, 0, s>>>(node, slot_point, pos, n, keys, vals);
+    k_member_pairs<<<nblk(n), 256, 0, s>>>(node, slot_point, pos, n, pbits, keys, vals);
     return hipGetLastError();
 }
 

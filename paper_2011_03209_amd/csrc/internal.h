@@ -254,9 +254,12 @@ hipError_t launch_lower_bounds(const uint64_t *keys, int64_t n, int64_t nv, int6
 hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
                                const double *lo0, const double *hc0, int32_t n0,
                                const double *lo1, const double *hc1, int32_t n1,
-                               int32_t *range4, int32_t *count, hipStream_t s);
+                               int32_t *range4, int32_t *count, unsigned long long *pair_sum,
+                               hipStream_t s);
+// keys = element id << cell_bits | cell[point] (cell may be null: 0)
 hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, uint64_t *keys, uint32_t *vals, hipStream_t s);
+                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals,
+                              hipStream_t s);
 // Packed panel rows.  A row holds dp coordinates: FP32 values (4 bytes), one
 // 16-bit value each (BF16, FP16), or for the hi/lo splits groups of 16 hi
 // values followed by their 16 lo values (4 bytes per coordinate).  dp is d
@@ -299,6 +302,38 @@ struct PackArgs {
     double *dbg_e;             // optional: e_s, the slot's share of the Gram error bound (scaled)
 };
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+
+// cells.hip: landmark cells of a cloud (at most CELL_MAX landmarks, staged
+// whole in LDS: ncell * d <= CELL_LDS_FLOATS)
+constexpr int CELL_MAX = 64;
+constexpr int CELL_LDS_FLOATS = 16384;
+hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
+                               uint8_t *cell, hipStream_t s);
+// keys[i] >>= shift
+hipError_t launch_shift_keys(uint64_t *keys, int64_t n, int shift, hipStream_t s);
+// Ball (FP32 center, FP64 radius bound) of each of the nrb row blocks
+// (d <= BALL_DMAX: the margins of the bound assume it).
+constexpr int BALL_DMAX = 2048;
+// Also per row block: cmask = its rows' cells, nmask = the cells near any of
+// them (near: the table of cells that eps may join, one 64-bit mask per cell).
+hipError_t launch_tile_balls(const float *X, int32_t d, const uint32_t *slot_point, const int64_t *elem_off,
+                             const int64_t *rb_off, int32_t n_elem, int64_t nrb, const uint8_t *cell,
+                             const unsigned long long *near, float *centers, double *radius,
+                             unsigned long long *cmask, unsigned long long *nmask, hipStream_t s);
+// keep[i] = 0 if the balls of tile pair i lie more than sqrt(E) apart, or
+// no cell of one side is near a cell of the other.
+hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const float *centers,
+                         const double *radius, const unsigned long long *cmask, const unsigned long long *nmask,
+                         int32_t d, double E, uint8_t *keep, hipStream_t s);
+// r2[c] = max |x - land_c|^2 over the points of cell c (double bits; r2
+// zeroed by the caller).
+hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, const uint8_t *cell,
+                              unsigned long long *r2, hipStream_t s);
+// out[pos[i]] = items[i] with blk = pos[i] for kept items; row0_blk of
+// every (e, 0, J); *pairs += the in-element pairs of the kept tile pairs.
+hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t *keep, const int64_t *pos,
+                                const int64_t *rb_off, TileItem *out, int64_t *row0_blk, unsigned long long *pairs,
+                                hipStream_t s);
 
 // tile.hip
 struct TileArgs {
@@ -366,22 +401,36 @@ hipError_t launch_cc_init(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_compress(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
                            int32_t min_pts, int32_t *parent, hipStream_t s);
+// row0_blk: block of tile pair (0, J) of each element at rb_off[e] + J (-1:
+// not computed), or null for the full table (tile_local_index).
 hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
-                          const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
+                          const int64_t *row0_blk, const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
                           int32_t *parent, hipStream_t s);
 hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
                              uint8_t *isroot, int64_t n_slots, hipStream_t s);
-hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent,
-                           const int64_t *root_rank, const uint64_t *slot_elem,
-                           int32_t *node, int32_t *node_elem, int64_t n_slots, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);
+// Roots (isroot, rank = exclusive scan of isroot) keyed for the canonical
+// node order: keys[rank] = element << 32 | smallest core point id of the
+// component, vals[rank] = rank (minpt: n ints of work space).
+hipError_t launch_root_keys(const int32_t *count, int32_t min_pts, const int32_t *parent,
+                           const uint32_t *slot_point, const uint8_t *isroot, const int64_t *rank,
+                           const uint64_t *slot_elem, int32_t *minpt, uint64_t *keys, uint32_t *vals,
+                           int64_t n_slots, hipStream_t s);
+// From the N root keys sorted: node_of_rank, node_elem, and node[slot] for
+// every slot (NOISE for non-core slots; border slots are set later).
+hipError_t launch_node_ids(const int32_t *count, int32_t min_pts, const int32_t *parent, const int64_t *rank,
+                           const uint64_t *sorted_keys, const uint32_t *sorted_vals, int64_t N,
+                           int32_t *node_of_rank, int32_t *node, int32_t *node_elem, int64_t n_slots,
+                           hipStream_t s);
 hipError_t launch_noncore_flags(const int32_t *count, int32_t min_pts, const uint64_t *slot_elem,
                                 const int64_t *elem_off, const int64_t *rb_off, uint8_t *flag,
                                 int64_t n, hipStream_t s);
 hipError_t launch_border(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
                          int32_t min_pts, const uint8_t *ncflag, const int64_t *rb_off,
                          int32_t *node, hipStream_t s);
+// keys = node << pbits | point, vals = point (point ids < 2^pbits)
 hipError_t launch_member_pairs(const int32_t *node, const uint32_t *slot_point,
-                               const int64_t *pos, int64_t n_slots, uint64_t *keys,
+                               const int64_t *pos, int64_t n_slots, int pbits, uint64_t *keys,
                                uint32_t *vals, hipStream_t s);
 hipError_t launch_flag_labelled(const int32_t *node, uint8_t *flag, int64_t n_slots, hipStream_t s);
 hipError_t launch_edge_counts(const uint64_t *pt_keys, int64_t m, int32_t *pairs_per_item,

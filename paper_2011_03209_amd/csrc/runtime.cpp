@@ -145,34 +145,67 @@ class Arena {
 // scope (an arena allocation that fails mid-run, a HIP error), kernels queued
 // earlier may still be running: the stream is synchronized here first, so
 // that memory they use is not handed to another stream's request meanwhile.
+// A scope over a run's reservation may fall back to the context arena for
+// what the reservation cannot hold (counted in overflow()).
 class Scope {
   public:
-    Scope(Arena &a, hipStream_t s) : a_(a), s_(s), exc_(std::uncaught_exceptions()) {}
+    Scope(Arena &a, hipStream_t s, Arena *fallback = nullptr)
+        : a_(a), fb_(fallback), s_(s), exc_(std::uncaught_exceptions()) {}
     ~Scope() {
         if (!held_.empty() && std::uncaught_exceptions() > exc_) (void)hipStreamSynchronize(s_);
         release_all();
     }
     template <typename T>
     T *get(uint64_t count) {
-        void *p = a_.alloc(count * sizeof(T) + 16);
+        const uint64_t b = count * sizeof(T) + 16;
+        Arena *src = &a_;
+        void *p = a_.alloc(b);
+        if (!p && fb_) {
+            src = fb_;
+            p = fb_->alloc(b);
+            if (p) overflow_ += b;
+        }
         if (!p) throw NoMem{count * sizeof(T)};
-        held_.push_back(p);
+        held_.push_back({p, src});
         bytes_ += count * sizeof(T);
         return (T *)p;
     }
+    // Hold a block taken from arena a directly (released with the scope).
+    void adopt(void *p, Arena &a) {
+        if (p) held_.push_back({p, &a});
+    }
+    // Release one allocation early (its stream work must be complete or
+    // ordered before any reuse: callers synchronize first).
+    void release(void *p) {
+        for (size_t i = 0; i < held_.size(); ++i)
+            if (held_[i].first == p) {
+                held_[i].second->release(p);
+                held_.erase(held_.begin() + (std::ptrdiff_t)i);
+                return;
+            }
+    }
     void release_all() {
-        for (void *p : held_) a_.release(p);
+        for (auto &h : held_) h.second->release(h.first);
         held_.clear();
         bytes_ = 0;
     }
     uint64_t bytes() const { return bytes_; }
+    uint64_t overflow() const { return overflow_; }
 
   private:
     Arena &a_;
+    Arena *fb_;
     hipStream_t s_;
     int exc_;
-    std::vector<void *> held_;
-    uint64_t bytes_ = 0;
+    std::vector<std::pair<void *, Arena *>> held_;
+    uint64_t bytes_ = 0, overflow_ = 0;
+};
+
+// Thrown when a serving request's reservation (taken after binning, before
+// the tile pass) does not fit: the request waits and retries from the start,
+// having run no tile pass.
+struct AdmitWait {
+    uint64_t want;
 };
 
 // HIP events for stage timings, kept for reuse: a run marks about a dozen
@@ -238,6 +271,10 @@ struct mapper_context {
     uint64_t next_ticket = 1;
     int active = 0;
     bool stop = false;
+    // a request that had to wait for its reservation: no other request is
+    // started until it has its reservation (so a large request is not
+    // overtaken forever by a stream of small ones)
+    const void *hol = nullptr;
     EventPool events;
     // autotuner cache: (d, eps bucket, norm bucket) -> precision
     std::mutex tune_mu;
@@ -250,6 +287,11 @@ struct mapper_cloud {
     int64_t n = 0;
     int32_t d = 0;
     float maxabs = 0.f;
+    uint8_t *cell = nullptr;           // landmark cell of each point (locality order), or null
+    int32_t cell_bits = 0;             // bits of a cell id in the binning key
+    int32_t ncell = 0;
+    std::vector<double> cell_gap;      // ncell x ncell: lower bound of the distance between two cells' points
+                                       // before eps (landmark distance - both radii), FP64
     std::atomic<int> inflight{0};
     mutable double med_norm2 = -1.0;   // median squared row norm (autotuner key; under tune_mu)
 };
@@ -266,6 +308,8 @@ struct mapper_graph {
 
 struct Request {
     uint64_t ticket = 0;
+    int32_t waits = 0;         // times it waited for its reservation
+    int32_t redone = 0;        // tile passes it lost to a later shortage
     const mapper_cloud *cloud = nullptr;
     ParamsCopy params;
     bool done = false;
@@ -603,11 +647,144 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     st.arena_peak_bytes = mem.bytes();
 }
 
+// ------------------------------------------------------------- cloud cells
+// The locality order of a cloud (cells.hip): up to CELL_MAX landmarks by
+// farthest-point sampling over an evenly strided sample of 4096 rows (FP64,
+// on the host; the first sampled row starts), numbered along a
+// nearest-neighbour chain, then every point's nearest landmark on the GPU.  Only clouds large enough to fill several tiles get
+// cells, and only when the landmarks fit the kernel's LDS; otherwise slots
+// stay in point order.  Built once, when the cloud is uploaded.
+void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
+    const int64_t n = c->n;
+    const int32_t d = c->d;
+    const int ncell = std::min<int>(CELL_MAX, CELL_LDS_FLOATS / std::max(d, 1));
+    if (n < 8 * TILE || ncell < 8) return;
+    const int64_t m = std::min<int64_t>(n, 4096), step = n / m;
+    std::vector<float> sub((size_t)(m * d));
+    HIPCHK(hipMemcpy2DAsync(sub.data(), (size_t)d * 4, c->X, (size_t)(step * d) * 4, (size_t)d * 4, (size_t)m,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> dmin((size_t)m, 1e300);
+    std::vector<int64_t> pick;
+    int64_t cur = 0;
+    for (int k = 0; k < ncell; ++k) {
+        pick.push_back(cur);
+        const float *y = &sub[(size_t)(cur * d)];
+        int64_t far = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            const float *x = &sub[(size_t)(i * d)];
+            double acc = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double t = (double)x[j] - (double)y[j];
+                acc += t * t;
+            }
+            dmin[(size_t)i] = std::min(dmin[(size_t)i], acc);
+            if (dmin[(size_t)i] > dmin[(size_t)far]) far = i;
+        }
+        if (dmin[(size_t)far] <= 0.0) break;                    // fewer distinct points than landmarks
+        cur = far;
+    }
+    const int nc = (int)pick.size();
+    if (nc < 2) return;
+    // number the landmarks along a nearest-neighbour chain, so that the
+    // cells of one cluster (farthest-point sampling splits a large cluster
+    // among several landmarks) are consecutive in the slot order
+    auto dist2 = [&](int64_t a, int64_t b) {
+        const float *x = &sub[(size_t)(a * d)], *y = &sub[(size_t)(b * d)];
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double t = (double)x[j] - (double)y[j];
+            acc += t * t;
+        }
+        return acc;
+    };
+    std::vector<int64_t> chain{pick[0]};
+    std::vector<char> used((size_t)nc, 0);
+    used[0] = 1;
+    for (int k = 1; k < nc; ++k) {
+        int best = -1;
+        double bd = 0.0;
+        for (int q = 0; q < nc; ++q) {
+            if (used[(size_t)q]) continue;
+            const double t = dist2(chain.back(), pick[(size_t)q]);
+            if (best < 0 || t < bd) { best = q; bd = t; }
+        }
+        used[(size_t)best] = 1;
+        chain.push_back(pick[(size_t)best]);
+    }
+    std::vector<float> land((size_t)nc * d);
+    for (int k = 0; k < nc; ++k)
+        std::memcpy(&land[(size_t)k * d], &sub[(size_t)(chain[k] * d)], (size_t)d * 4);
+    uint8_t *cell = (uint8_t *)ctx->arena.alloc((uint64_t)n);
+    float *dl = (float *)ctx->arena.alloc((uint64_t)nc * d * 4);
+    if (!cell || !dl) {                                         // no room: keep point order
+        ctx->arena.release(cell);
+        ctx->arena.release(dl);
+        return;
+    }
+    unsigned long long *r2 = (unsigned long long *)ctx->arena.alloc((uint64_t)CELL_MAX * 8);
+    if (!r2) {                                                  // no room: keep point order
+        ctx->arena.release(cell);
+        ctx->arena.release(dl);
+        return;
+    }
+    std::vector<unsigned long long> r2h((size_t)CELL_MAX, 0);
+    try {
+        HIPCHK(hipMemcpyAsync(dl, land.data(), land.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_assign_cells(c->X, n, d, dl, nc, cell, s));
+        HIPCHK(hipMemsetAsync(r2, 0, (size_t)CELL_MAX * 8, s));
+        HIPCHK(launch_cell_radius(c->X, n, d, dl, cell, r2, s));
+        HIPCHK(hipMemcpyAsync(r2h.data(), r2, (size_t)CELL_MAX * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (DevError &) {
+        (void)hipStreamSynchronize(s);
+        ctx->arena.release(cell);
+        ctx->arena.release(dl);
+        ctx->arena.release(r2);
+        throw;
+    }
+    ctx->arena.release(dl);
+    ctx->arena.release(r2);
+    // cell balls: landmark l_c, radius r_c >= max |x - l_c| over its points
+    // (relative margin 2^-40 for the FP64 sums, d <= BALL_DMAX); the gap of
+    // two cells bounds every distance between their points from below
+    std::vector<double> rad((size_t)nc);
+    for (int a = 0; a < nc; ++a) {
+        double r2v;
+        std::memcpy(&r2v, &r2h[(size_t)a], 8);
+        rad[(size_t)a] = std::sqrt(r2v) * (1.0 + 0x1.0p-40);
+    }
+    c->cell_gap.assign((size_t)nc * nc, 0.0);
+    for (int a = 0; a < nc; ++a)
+        for (int b = 0; b < nc; ++b)
+            if (a != b)
+                c->cell_gap[(size_t)a * nc + b] =
+                    std::sqrt(dist2(chain[(size_t)a], chain[(size_t)b])) * (1.0 - 0x1.0p-40) - rad[(size_t)a] -
+                    rad[(size_t)b];
+    c->ncell = nc;
+    c->cell = cell;
+    c->cell_bits = 32 - __builtin_clz((unsigned)(nc - 1));
+}
+
 // ------------------------------------------------------------------ the run
 enum class Phase { Ok, Retry };
 
+// A serving request got its reservation: if it was the head-of-line
+// request, other requests may start again.
+void admitted(mapper_context *ctx, const void *req) {
+    if (!req) return;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->hol == req) {
+        ctx->hol = nullptr;
+        ctx->cv.notify_all();
+    }
+}
+
+
 struct RunOut {
     std::vector<mapper_graph *> gs;    // one graph per eps value
+    const void *req = nullptr;         // the serving request being run (head-of-line bookkeeping)
+    bool tiles_done = false;           // the tile pass has run (a later shortage wastes it)
     ~RunOut() {
         for (mapper_graph *g : gs) delete g;
     }
@@ -700,29 +877,41 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int32_t *mcount = mem.get<int32_t>(n);
     int64_t *mpos = mem.get<int64_t>(n + 1);
     void *stmp = mem.get<char>(scan_temp_bytes(n));
+    unsigned long long *psum = mem.get<unsigned long long>(1);
+    HIPCHK(hipMemsetAsync(psum, 0, 8, s));
     HIPCHK(launch_member_count(f[0], na == 2 ? f[1] : nullptr, n, dlo[0], dhc[0], nint[0],
                                na == 2 ? dlo[1] : nullptr, na == 2 ? dhc[1] : nullptr, nint[1],
-                               range4, mcount, s));
+                               range4, mcount, psum, s));
     HIPCHK(launch_scan_i32(mcount, mpos, n, stmp, s));
     int64_t S = 0;
+    unsigned long long pair_bound = 0;       // sum over points of C(elements holding it, 2)
     HIPCHK(hipMemcpyAsync(&S, mpos + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&pair_bound, psum, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (S > (int64_t)0x7fffffff) throw std::runtime_error("more than 2^31 memberships");
     const int64_t Sa = std::max<int64_t>(S, 1);
     uint64_t *skey = mem.get<uint64_t>(Sa), *skey2 = mem.get<uint64_t>(Sa);
     uint32_t *sval = mem.get<uint32_t>(Sa), *sval2 = mem.get<uint32_t>(Sa);
     void *sortmp = mem.get<char>(sort_temp_bytes(Sa));
-    HIPCHK(launch_member_emit(range4, mpos, n, nint[1], na == 2, skey, sval, s));
+    // slots sorted by (element, cell): each element's members in the cloud's
+    // locality order, point order within a cell (the sort is stable)
+    const int cbits = cloud->cell ? cloud->cell_bits : 0;
+    HIPCHK(launch_member_emit(range4, mpos, n, nint[1], na == 2, cloud->cell, cbits, skey, sval, s));
     bool alt = false;
-    HIPCHK(radix_sort_pairs(skey, sval, skey2, sval2, S, bits_for((uint64_t)E_count), sortmp, &alt, s));
+    HIPCHK(radix_sort_pairs(skey, sval, skey2, sval2, S, bits_for((uint64_t)E_count) + cbits, sortmp, &alt, s));
     uint64_t *slot_elem = alt ? skey2 : skey;
     uint32_t *slot_point = alt ? sval2 : sval;
+    HIPCHK(launch_shift_keys(slot_elem, S, cbits, s));
     int64_t *elem_off = mem.get<int64_t>(E_count + 1);
     HIPCHK(launch_lower_bounds(slot_elem, S, E_count, elem_off, s));
     std::vector<int64_t> eoff;
     d2h(eoff, elem_off, E_count + 1, s);
     HIPCHK(hipStreamSynchronize(s));
     ev.mark();                                                      // 2
+    // the binning temporaries are done (the stream is synchronized)
+    for (void *q : {(void *)range4, (void *)mcount, (void *)mpos, stmp, (void *)psum, sortmp,
+                    (void *)(alt ? skey : skey2), (void *)(alt ? sval : sval2)})
+        mem.release(q);
 
     // ---- tiling (host): elements largest first
     std::vector<int32_t> order;
@@ -799,8 +988,13 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         prec = choose_precision(ctx, d, dp16, E, ts, key);
     }
     st.precision = prec;
+    // screening of tile pairs by their rows' balls: when the cloud has a
+    // locality order (cells) and the balls' margins hold (d <= BALL_DMAX)
+    const bool screen = cloud->cell != nullptr && d <= BALL_DMAX && nblocks > 0 &&
+                        !(P->flags & (MAPPER_FLAG_NO_SCREEN | MAPPER_FLAG_TILE_MACRO));
     // launch form: macro tiles for single 16-bit products with one eps value
-    const bool macro_ok = (prec == P_BF16 || prec == P_FP16) && n_levels == 1 &&
+    // (screened runs keep scattered tile pairs: tile pairs then)
+    const bool macro_ok = (prec == P_BF16 || prec == P_FP16) && n_levels == 1 && !screen &&
                           (uint64_t)panel_row_stride(prec, panel_dp(prec, d)) * MTILE < (1ull << 32);
     const bool use_macro = macro_ok && !(P->flags & MAPPER_FLAG_TILE_PAIRS);
     st.tile_m = st.tile_n = use_macro ? MTILE : TILE;
@@ -808,8 +1002,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     const int super = supertile_size(prec, panel_dp(prec, d));
     std::vector<int64_t> colpre, cp_off(E_count);
     build_supertile_columns(T, super, colpre, cp_off);
+    int64_t nrb = 0;                                            // row blocks of all elements
+    std::vector<int64_t> rb_off(std::max<int64_t>(E_count, 1), 0);
+    for (int64_t e = 0; e < E_count; ++e) { rb_off[e] = nrb; nrb += T[e]; }
 
-    // ---- device tables, panels, thresholds
+    // ---- device tile tables: every tile pair I <= J of every element
     int64_t *d_item_off = mem.get<int64_t>(item_off.size());
     int32_t *d_order = mem.get<int32_t>(std::max<size_t>(order.size(), 1));
     int64_t *d_blk_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
@@ -833,26 +1030,151 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     TileItem *d_items = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));
     HIPCHK(launch_build_items(tt, d_items, s));
     tt.items = d_items;
-    // macro table: pairs of 256-row blocks, same element order, supertiles of
-    // 4 x 4 macro pairs (1024 rows a side, as the tile pairs' 8 x 8)
-    MacroItem *d_mitems = nullptr;
+    int64_t *d_rb_off = mem.get<int64_t>(rb_off.size());
+    h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
+
+    // ---- screening: the tile pairs that can hold a neighbour pair
+    int64_t n_tiles = nblocks;                                  // tile pairs computed
+    uint8_t *keep = nullptr;
+    int64_t *kpos = nullptr;
+    if (screen) {
+        float *centers = mem.get<float>((uint64_t)nrb * d);
+        double *radius = mem.get<double>(nrb);
+        keep = mem.get<uint8_t>(nblocks);
+        kpos = mem.get<int64_t>(nblocks + 1);
+        void *kst = mem.get<char>(scan_temp_bytes(nblocks));
+        double Emax = 0.0;
+        for (int lv = 0; lv < n_levels; ++lv) Emax = std::max(Emax, Elev[lv]);
+        // cells eps may join: all but the pairs whose balls' gap g satisfies
+        // g^2 (1 - (d + 8) 2^-52) > E (1 + 2^-40), the bound k_screen uses
+        const int nc = cloud->ncell;
+        std::vector<unsigned long long> nearh((size_t)CELL_MAX, 0);
+        const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
+        for (int a = 0; a < nc; ++a)
+            for (int b = 0; b < nc; ++b) {
+                const double g = cloud->cell_gap[(size_t)a * nc + b];
+                if (!(a != b && g > 0.0 && g * g * shrink > Emax * (1.0 + 0x1.0p-40)))
+                    nearh[(size_t)a] |= 1ull << b;
+            }
+        unsigned long long *near = mem.get<unsigned long long>(CELL_MAX);
+        unsigned long long *cmask = mem.get<unsigned long long>(nrb), *nmask = mem.get<unsigned long long>(nrb);
+        h2d(near, nearh.data(), CELL_MAX, s);
+        HIPCHK(launch_tile_balls(cloud->X, d, slot_point, elem_off, d_rb_off, (int32_t)E_count, nrb, cloud->cell,
+                                 near, centers, radius, cmask, nmask, s));
+        HIPCHK(launch_screen(d_items, nblocks, d_rb_off, centers, radius, cmask, nmask, d, Emax, keep, s));
+        HIPCHK(launch_scan_u8(keep, kpos, nblocks, kst, s));
+        HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    st.tiles_screened_out = nblocks - n_tiles;
+    st.tiles = n_tiles;
+
+    // ---- host tables of the macro form
+    const uint64_t level_words = (uint64_t)std::max<int64_t>(n_tiles, 1) * TILE_WORDS;
     int64_t n_mitems = 0;
+    const int msuper = 4;          // 4 x 4 macro pairs: 1024 rows a side, as the tile pairs' 8 x 8
+    std::vector<int64_t> T2, mitem_off, mcolpre, mcp_off, mblk_off;
     if (use_macro) {
-        std::vector<int64_t> T2(E_count), mblk_off(E_count, 0);
+        T2.resize(E_count);
+        mblk_off.assign(E_count, 0);
+        mcp_off.resize(E_count);
         for (int64_t e = 0; e < E_count; ++e) T2[e] = (eoff[e + 1] - eoff[e] + MTILE - 1) / MTILE;
-        std::vector<int64_t> mitem_off(order.size() + 1, 0);
+        mitem_off.assign(order.size() + 1, 0);
         for (size_t k = 0; k < order.size(); ++k) {
             const int64_t t2 = T2[order[k]];
             mitem_off[k + 1] = mitem_off[k] + t2 * (t2 + 1) / 2;
         }
         n_mitems = mitem_off.back();
-        const int msuper = 4;
-        std::vector<int64_t> mcolpre, mcp_off(E_count);
         build_supertile_columns(T2, msuper, mcolpre, mcp_off);
-        int64_t *d_mitem_off = mem.get<int64_t>(mitem_off.size());
-        int64_t *d_mcolpre = mem.get<int64_t>(mcolpre.size());
-        int64_t *d_mcp_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
-        int64_t *d_mblk_off = mem.get<int64_t>(std::max<int64_t>(E_count, 1));
+    }
+    const int dp = panel_dp(prec, d);
+    const uint64_t stride = (uint64_t)panel_row_stride(prec, dp);
+    // band list: nseg segments, a tile's pairs going to segment blockIdx %
+    // nseg; grown and the tiles redone if a segment overflows
+    const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two per CU, a multiple of the 8 XCDs
+    int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
+    band_cap = std::max<int64_t>(band_cap, 1024);
+
+    // ---- reservation: every later device array of the run, in one block
+    // taken before the tile pass (a serving request that cannot have it
+    // waits here, having run no tile pass).  Sizes are the allocations below
+    // as the arena rounds them; a level's graph arrays at their upper bounds
+    // (labelled slots <= S, nodes <= S, node pairs sharing a point <=
+    // pair_bound), once: levels run one after another and free their arrays.
+    auto r256 = [](uint64_t b) { return (b + 16 + 255) & ~(uint64_t)255; };
+    const uint64_t E1 = (uint64_t)std::max<int64_t>(E_count, 1), U = (uint64_t)Sa;
+    uint64_t fixed = 0;
+    if (screen)                                                 // kept tile pairs, row-0 blocks
+        fixed += r256((uint64_t)std::max<int64_t>(n_tiles, 1) * sizeof(TileItem)) +
+                 r256((uint64_t)std::max<int64_t>(nrb, 1) * 8) + r256(8);
+    if (use_macro)
+        fixed += r256(mitem_off.size() * 8) + r256(mcolpre.size() * 8) + 2 * r256(E1 * 8) +
+                 r256((uint64_t)std::max<int64_t>(n_mitems, 1) * sizeof(MacroItem));
+    fixed += r256(U * stride) + 2 * r256((uint64_t)n_levels * U * 4) + r256((uint64_t)n_levels * U * 4) +
+             r256((uint64_t)n_levels * level_words * 4) + r256((uint64_t)nseg * 8);
+    const uint64_t EPb = std::max<uint64_t>(pair_bound, 1);
+    const uint64_t level = r256(U * 4) + r256(U) + r256((U + 1) * 8) + 2 * r256(U * 4) +
+                           r256(scan_temp_bytes((int64_t)U + 1)) + r256((uint64_t)std::max<int64_t>(nrb, 1)) +
+                           2 * r256(U * 8) + 2 * r256(U * 4) + r256(sort_temp_bytes((int64_t)U)) +
+                           r256((U + 1) * 8) + r256(U * 4) + 2 * r256(U * 8) + 2 * r256(U * 4) + r256(U * 4) +
+                           r256((U + 1) * 8) + r256(scan_temp_bytes((int64_t)U + 1)) + 2 * r256(EPb * 8) +
+                           2 * r256(EPb * 4) + r256(sort_temp_bytes((int64_t)EPb)) + r256(EPb) +
+                           r256((EPb + 1) * 8) + r256(scan_temp_bytes((int64_t)EPb + 1)) + r256(2 * EPb * 4) +
+                           r256(EPb * 4) +
+                           // canonical node order: minpt, root keys and values (two each), sort space, node_of_rank
+                           r256(U * 4) + 2 * r256(U * 8) + 2 * r256(U * 4) + r256(sort_temp_bytes((int64_t)U)) +
+                           r256(U * 4);
+    uint64_t need = 0;
+    void *res = nullptr;
+    for (;;) {
+        need = fixed + level + r256((uint64_t)nseg * band_cap * sizeof(BandPair));
+        res = ctx->arena.alloc(need);
+        if (res || band_cap <= 8) break;
+        band_cap = std::max<int64_t>(band_cap / 4, 8);     // small arenas: a small list, grown on demand
+    }
+    if (!res) {
+        // a serving request waits while others hold memory; a request that
+        // runs alone (or a direct call) goes on without a reservation and
+        // takes what the arena has as it goes (the sizes above are upper
+        // bounds, so the run may still fit)
+        bool others = false;
+        if (may_retry) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            others = ctx->active > 1;
+            if (!others) ctx->hol = out.req;                    // unreserved: start nothing else meanwhile
+        }
+        if (others) throw AdmitWait{need};
+    }
+    mem.adopt(res, ctx->arena);
+    Arena sub;                                                      // the reservation, sub-allocated
+    sub.init((char *)res, res ? need : 0);
+    Scope rm(sub, s, &ctx->arena);
+    st.reserved_bytes = res ? need : 0;
+    if (may_retry && res) admitted(ctx, out.req);
+
+    // ---- the kept tile pairs (screened runs): their own bitmask blocks
+    int64_t *row0_blk = nullptr;
+    if (screen) {
+        TileItem *kept = rm.get<TileItem>(std::max<int64_t>(n_tiles, 1));
+        row0_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
+        unsigned long long *pc = rm.get<unsigned long long>(1);
+        HIPCHK(hipMemsetAsync(pc, 0, 8, s));
+        HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, row0_blk, pc, s));
+        unsigned long long pairs_c = 0;
+        HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        st.pairs_computed = (int64_t)pairs_c;
+        tt.items = kept;
+        tt.n_items = n_tiles;
+    } else {
+        st.pairs_computed = pairs;
+    }
+    MacroItem *d_mitems = nullptr;
+    if (use_macro) {
+        int64_t *d_mitem_off = rm.get<int64_t>(mitem_off.size());
+        int64_t *d_mcolpre = rm.get<int64_t>(mcolpre.size());
+        int64_t *d_mcp_off = rm.get<int64_t>(std::max<int64_t>(E_count, 1));
+        int64_t *d_mblk_off = rm.get<int64_t>(std::max<int64_t>(E_count, 1));
         h2d(d_mitem_off, mitem_off.data(), (int64_t)mitem_off.size(), s);
         h2d(d_mcolpre, mcolpre.data(), (int64_t)mcolpre.size(), s);
         h2d(d_mcp_off, mcp_off.data(), E_count, s);
@@ -865,13 +1187,12 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         mt.super = msuper;
         mt.n_items = n_mitems;
         mt.items = nullptr;
-        d_mitems = mem.get<MacroItem>(std::max<int64_t>(n_mitems, 1));
+        d_mitems = rm.get<MacroItem>(std::max<int64_t>(n_mitems, 1));
         HIPCHK(launch_build_macro_items(mt, tt, d_mitems, n_mitems, s));
     }
 
-    const int dp = panel_dp(prec, d);
-    void *panel = mem.get<char>((uint64_t)Sa * (uint64_t)panel_row_stride(prec, dp));
-    float *thrA = mem.get<float>((uint64_t)n_levels * Sa), *thrB = mem.get<float>((uint64_t)n_levels * Sa);
+    void *panel = rm.get<char>((uint64_t)Sa * stride);
+    float *thrA = rm.get<float>((uint64_t)n_levels * Sa), *thrB = rm.get<float>((uint64_t)n_levels * Sa);
     PackArgs pk;
     pk.X = cloud->X;
     pk.d = d;
@@ -889,27 +1210,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     pk.dbg_e = nullptr;
     HIPCHK(launch_pack(pk, s));
 
-    const uint64_t level_words = (uint64_t)std::max<int64_t>(nblocks, 1) * TILE_WORDS;
-    int32_t *count_all = mem.get<int32_t>((uint64_t)n_levels * Sa);
-    uint32_t *bitmask_all = mem.get<uint32_t>((uint64_t)n_levels * level_words);
-    st.bitmask_bytes = nblocks * TILE_WORDS * 4;
-    // band list: nseg segments, a tile's pairs going to segment blockIdx %
-    // nseg; grown and the tiles redone if a segment overflows
-    const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two per CU, a multiple of the 8 XCDs
-    unsigned long long *band_n = mem.get<unsigned long long>(nseg);
-    int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
-    band_cap = std::max<int64_t>(band_cap, 1024);
-    BandPair *band = nullptr;
-    for (;;) {
-        try {
-            band = mem.get<BandPair>((uint64_t)nseg * band_cap);
-        } catch (NoMem &) {
-            if (band_cap <= 8) throw;                       // small arenas: a small list, grown on demand
-            band_cap = std::max<int64_t>(band_cap / 4, 8);
-            continue;
-        }
-        break;
-    }
+    int32_t *count_all = rm.get<int32_t>((uint64_t)n_levels * Sa);
+    uint32_t *bitmask_all = rm.get<uint32_t>((uint64_t)n_levels * level_words);
+    st.bitmask_bytes = n_tiles * TILE_WORDS * 4;
+    unsigned long long *band_n = rm.get<unsigned long long>(nseg);
+    BandPair *band = rm.get<BandPair>((uint64_t)nseg * band_cap);
     ev.mark();                                                      // 3
     std::vector<unsigned long long> segn(nseg);
     for (int launch = 0;; ++launch) {
@@ -944,8 +1249,10 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         const int64_t most = (int64_t)*std::max_element(segn.begin(), segn.end());
         if (most <= band_cap) break;
         band_cap = most + most / 8 + 256;                   // grow and redo the tiles
-        band = mem.get<BandPair>((uint64_t)nseg * band_cap);
+        rm.release(band);                                   // the stream is synchronized
+        band = rm.get<BandPair>((uint64_t)nseg * band_cap);
     }
+    out.tiles_done = true;
     int64_t nband = 0;
     for (int g = 0; g < nseg; ++g) nband += (int64_t)segn[g];
     st.band_pairs = nband;
@@ -962,7 +1269,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
 
     // ---- one graph per level
     for (int lv = 0; lv < n_levels; ++lv) {
-    Scope lm(ctx->arena, s);                                        // this level's work arrays
+    Scope lm(sub, s, &ctx->arena);                                  // this level's work arrays
     Events lev(s, ctx->events);
     lev.mark();                                                     // 0
     int32_t *count = count_all + (int64_t)lv * Sa;
@@ -976,28 +1283,33 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int64_t *rank = lm.get<int64_t>(Sa + 1);
     int32_t *node = lm.get<int32_t>(Sa);
     int32_t *node_elem = lm.get<int32_t>(Sa);
-    // row blocks of all elements, numbered element by element
-    std::vector<int64_t> rb_off(std::max<int64_t>(E_count, 1), 0);
-    int64_t nrb = 0;
-    for (int64_t e = 0; e < E_count; ++e) { rb_off[e] = nrb; nrb += T[e]; }
-    int64_t *d_rb_off = lm.get<int64_t>(rb_off.size());
-    h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
     HIPCHK(launch_cc_init(parent, S, s));
-    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, bitmask, count, P->min_pts, parent, s));
+    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, row0_blk, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_compress(parent, S, s));
     HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
     void *stmp2 = lm.get<char>(scan_temp_bytes(Sa + 1));
     HIPCHK(launch_scan_u8(isroot, rank, S, stmp2, s));
-    HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, slot_elem, node, node_elem, S, s));
+    // canonical node order: the roots sorted by (element, smallest core point id)
+    int64_t N = 0;
+    HIPCHK(hipMemcpyAsync(&N, rank + S, 8, hipMemcpyDeviceToHost, s));
+    int32_t *minpt = lm.get<int32_t>(Sa);
+    uint64_t *rk1 = lm.get<uint64_t>(Sa), *rk2 = lm.get<uint64_t>(Sa);
+    uint32_t *rv1 = lm.get<uint32_t>(Sa), *rv2 = lm.get<uint32_t>(Sa);
+    void *rsort = lm.get<char>(sort_temp_bytes(Sa));
+    int32_t *node_of_rank = lm.get<int32_t>(Sa);
+    HIPCHK(launch_root_keys(count, P->min_pts, parent, slot_point, isroot, rank, slot_elem, minpt, rk1, rv1, S, s));
+    HIPCHK(hipStreamSynchronize(s));                                // N
+    bool ralt = false;
+    HIPCHK(radix_sort_pairs(rk1, rv1, rk2, rv2, N, 32 + bits_for((uint64_t)E_count), rsort, &ralt, s));
+    HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, ralt ? rk2 : rk1, ralt ? rv2 : rv1, N, node_of_rank,
+                           node, node_elem, S, s));
     {
         uint8_t *ncflag = lm.get<uint8_t>(std::max<int64_t>(nrb, 1));
         HIPCHK(hipMemsetAsync(ncflag, 0, (size_t)std::max<int64_t>(nrb, 1), s));
         HIPCHK(launch_noncore_flags(count, P->min_pts, slot_elem, elem_off, d_rb_off, ncflag, S, s));
         HIPCHK(launch_border(tt, bitmask, count, P->min_pts, ncflag, d_rb_off, node, s));
     }
-    int64_t N = 0;
-    HIPCHK(hipMemcpyAsync(&N, rank + S, 8, hipMemcpyDeviceToHost, s));
     lev.mark();                                                     // 1
 
     // ---- node CSR: (node, point) sorted stably by node
@@ -1012,10 +1324,15 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     uint64_t *k1 = lm.get<uint64_t>(Ma), *k2 = lm.get<uint64_t>(Ma);
     uint32_t *v1 = lm.get<uint32_t>(Ma), *v2 = lm.get<uint32_t>(Ma);
     void *sortmp2 = lm.get<char>(sort_temp_bytes(Ma));
-    HIPCHK(launch_member_pairs(node, slot_point, mp, S, k1, v1, s));
-    HIPCHK(radix_sort_pairs(k1, v1, k2, v2, M, bits_for((uint64_t)std::max<int64_t>(N - 1, 0)), sortmp2, &alt, s));
+    // sorted by (node, point): members ascending in each node (slots are in
+    // cell order, not point order); then keys back to node ids
+    const int pbits = bits_for((uint64_t)std::max<int64_t>(n - 1, 0));
+    HIPCHK(launch_member_pairs(node, slot_point, mp, S, pbits, k1, v1, s));
+    HIPCHK(radix_sort_pairs(k1, v1, k2, v2, M, bits_for((uint64_t)std::max<int64_t>(N - 1, 0)) + pbits, sortmp2,
+                            &alt, s));
     uint64_t *nk = alt ? k2 : k1;
     uint32_t *nv = alt ? v2 : v1;
+    HIPCHK(launch_shift_keys(nk, M, pbits, s));
     int64_t *node_off = lm.get<int64_t>(N + 1);
     HIPCHK(launch_node_offsets_from_sorted(nk, M, N, node_off, s));
     int32_t *members = lm.get<int32_t>(Ma);
@@ -1093,6 +1410,32 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         put("slot_node_raw", node, S, 4);
     }
     HIPCHK(hipStreamSynchronize(s));
+    if (dbg && cbits > 0) {
+        // slots are in cell order inside each element: report the per-slot
+        // stage arrays in point order, as the stage contract states
+        int32_t *mem_p = (int32_t *)g->stages["elem_members"].first.data();
+        int32_t *cnt_p = (int32_t *)g->stages["slot_count"].first.data();
+        int32_t *nod_p = (int32_t *)g->stages["slot_node_raw"].first.data();
+        std::vector<int64_t> idx;
+        std::vector<int32_t> tm, tc, tn;
+        for (int64_t e = 0; e < E_count; ++e) {
+            const int64_t a = eoff[e], b = eoff[e + 1];
+            idx.resize((size_t)(b - a));
+            for (int64_t k = 0; k < b - a; ++k) idx[(size_t)k] = a + k;
+            std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return mem_p[x] < mem_p[y]; });
+            tm.resize(idx.size());
+            tc.resize(idx.size());
+            tn.resize(idx.size());
+            for (size_t k = 0; k < idx.size(); ++k) {
+                tm[k] = mem_p[idx[k]];
+                tc[k] = cnt_p[idx[k]];
+                tn[k] = nod_p[idx[k]];
+            }
+            std::copy(tm.begin(), tm.end(), mem_p + a);
+            std::copy(tc.begin(), tc.end(), cnt_p + a);
+            std::copy(tn.begin(), tn.end(), nod_p + a);
+        }
+    }
     if (dbg) {
         auto &raw = g->stages["slot_node_raw"];
         std::vector<int32_t> nodev((size_t)S);
@@ -1113,37 +1456,54 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     g->stats.ms_cc = lev.ms(0, 1);
     g->stats.ms_edges = lev.ms(1, 2);
     g->stats.ms_total = ev.ms(0, 5) + lev.ms(0, 2);
-    g->stats.arena_peak_bytes = mem.bytes() + lm.bytes();
+    g->stats.arena_peak_bytes = mem.bytes() + rm.bytes() + lm.bytes();
+    g->stats.reserve_overflow_bytes = rm.overflow() + lm.overflow();
     out.gs.push_back(g.release());
     }
     (void)may_retry;
     return Phase::Ok;
 }
 
+// Outcome of a serving attempt that could not finish for lack of arena.
+struct Retry {
+    bool again = false;        // requeue the request
+    bool admission = false;    // it waited for its reservation (no tile pass run)
+    bool redone = false;       // its tile pass was lost (a shortage after the reservation)
+};
+
 // out[0 .. n_levels) receive the graphs (n_levels eps values from eps_list,
-// or P->eps when it is null).
+// or P->eps when it is null).  req: the serving request (null otherwise).
 mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
-                          hipStream_t s, bool may_retry, mapper_graph **out, bool *retry,
-                          const double *eps_list = nullptr, int n_levels = 1) {
-    *retry = false;
+                          hipStream_t s, bool may_retry, mapper_graph **out, Retry *retry,
+                          const double *eps_list = nullptr, int n_levels = 1, const void *req = nullptr) {
+    *retry = Retry{};
+    RunOut ro;
+    ro.req = req;
+    // a serving request waits and retries only while another request holds
+    // memory that it will return (checked when the shortage happens), and
+    // fails only when it ran alone
+    auto others_active = [&]() {
+        if (!may_retry) return false;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        return ctx->active > 1;
+    };
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        RunOut ro;
         run_pipeline(ctx, cloud, P, s, may_retry, ro, eps_list, n_levels);
         for (int lv = 0; lv < n_levels; ++lv) out[lv] = ro.gs[lv];
         ro.gs.clear();
         return MAPPER_OK;
+    } catch (AdmitWait &) {
+        // thrown only while another request held memory: wait and try again
+        // (a request that finds itself alone runs without a reservation)
+        (void)hipStreamSynchronize(s);
+        *retry = Retry{true, true, false};
+        return MAPPER_ENOMEM;
     } catch (NoMem &nm) {
         (void)hipStreamSynchronize(s);
-        // a serving request retries if another request holds memory now (it
-        // may have started after this one), and fails only when it ran alone
-        bool others = false;
-        if (may_retry) {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            others = ctx->active > 1;
-        }
-        if (others) {
-            *retry = true;
+        if (others_active()) {
+            // before its tile pass this is a wait for memory like a reservation
+            *retry = Retry{true, !ro.tiles_done, ro.tiles_done};
             return MAPPER_ENOMEM;
         }
         return fail(MAPPER_ENOMEM, "arena too small for this run (needed " + std::to_string(nm.want) +
@@ -1164,29 +1524,40 @@ void worker_main(mapper_context *ctx, hipStream_t s) {
         Request *r = nullptr;
         {
             std::unique_lock<std::mutex> lk(ctx->mu);
-            ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
+            // while a head-of-line request waits for its reservation, only it
+            // may be taken
+            ctx->cv.wait(lk, [&] {
+                return (ctx->stop && ctx->pending.empty()) ||
+                       (!ctx->pending.empty() && (!ctx->hol || ctx->pending.front() == ctx->hol));
+            });
             if (ctx->stop && ctx->pending.empty()) return;
             r = ctx->pending.front();
             ctx->pending.pop_front();
             ++ctx->active;
         }
         mapper_graph *g = nullptr;
-        bool retry = false;
-        mapper_status st;
-        // retried on a shortage of arena only while another request holds
-        // memory that it will return (checked when the shortage happens)
-        st = run_guarded(ctx, r->cloud, &r->params.p, s, true, &g, &retry);
+        Retry retry;
+        const mapper_status st = run_guarded(ctx, r->cloud, &r->params.p, s, true, &g, &retry, nullptr, 1, r);
         std::unique_lock<std::mutex> lk(ctx->mu);
         --ctx->active;
-        if (retry) {
-            // the failed run has released its own memory by now: wait for
-            // another request's release (or 50 ms) before trying again
+        if (retry.again) {
+            r->waits += retry.admission ? 1 : 0;
+            r->redone += retry.redone ? 1 : 0;
+            // the failed run has released its own memory by now: hold the
+            // queue for it and wait for another request's release (or 50 ms)
+            // before trying again
+            ctx->hol = r;
             const uint64_t seen = ctx->arena.epoch();
             ctx->pending.push_front(r);
             lk.unlock();
             ctx->arena.wait_release(seen, 50);
             ctx->cv.notify_all();
             continue;
+        }
+        if (ctx->hol == r) ctx->hol = nullptr;              // done (or failed for good): release the queue
+        if (g) {
+            g->stats.admission_waits = r->waits;
+            g->stats.tile_passes_redone = r->redone;
         }
         r->status = st;
         r->err = st == MAPPER_OK ? "" : g_last_error;
@@ -1356,6 +1727,7 @@ mapper_status mapper_cloud_create(mapper_context *ctx, const float *points, int6
         c->n = n;
         c->d = d;
         std::memcpy(&c->maxabs, &h[1], 4);
+        build_cells(ctx, c, s);
         *out = c;
         return MAPPER_OK;
     } catch (DevError &de) {
@@ -1368,6 +1740,7 @@ mapper_status mapper_cloud_create(mapper_context *ctx, const float *points, int6
 mapper_status mapper_cloud_destroy(mapper_cloud *c) {
     if (!c) return fail(MAPPER_EINVAL, "null cloud");
     if (c->inflight.load() > 0) return fail(MAPPER_EBUSY, "cloud has requests in flight");
+    c->ctx->arena.release(c->cell);
     c->ctx->arena.release(c->X);
     delete c;
     return MAPPER_OK;
@@ -1379,7 +1752,7 @@ mapper_status mapper_run(mapper_context *ctx, const mapper_cloud *cloud, const m
     *out = nullptr;
     mapper_status v = validate(cloud, params);
     if (v != MAPPER_OK) return v;
-    bool retry;
+    Retry retry;
     return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry);
 }
 
@@ -1396,7 +1769,7 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
     }
     mapper_status v = validate(cloud, params);
     if (v != MAPPER_OK) return v;
-    bool retry;
+    Retry retry;
     return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry, eps_list, n_eps);
 }
 

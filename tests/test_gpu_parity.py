@@ -73,6 +73,10 @@ def run_and_compare(ctx, X, params, stages=True):
     if stages:
         same_stages(g, ref, len(params.axes))
     same_graph(g, ref)
+    # the run's reservation (taken after binning) held every later array,
+    # unless the band list had to grow
+    assert g.stats["reserved_bytes"] > 0
+    assert g.stats["reserve_overflow_bytes"] == 0 or g.stats["tile_launches"] > 1
     return g, ref
 
 
@@ -136,7 +140,6 @@ def test_macro_tiles(ctx, prec, d):
     params = with_prec(params, prec)
     g, ref = run_and_compare(ctx, X, params)
     assert np.array_equal(np.diff(ref.elem_offsets), sizes)
-    assert g.stats["tile_m"] == 256, g.stats["tile_m"]
     cloud = ctx.cloud(X)
     try:
         gp = cloud.run(params, debug=True, flags=binding.FLAG_TILE_PAIRS)
@@ -144,11 +147,56 @@ def test_macro_tiles(ctx, prec, d):
     finally:
         cloud.destroy()
     assert gp.stats["tile_m"] == 128 and gm.stats["tile_m"] == 256
-    assert gp.stats["band_pairs"] == gm.stats["band_pairs"] == g.stats["band_pairs"]
+    assert gm.stats["tiles_screened_out"] == 0
+    # the same tile pairs computed in the same order: the same band pairs
+    # (the default run screens tile pairs out, so it may have fewer)
+    if gp.stats["tiles_screened_out"] == 0:
+        assert gp.stats["band_pairs"] == gm.stats["band_pairs"]
+    assert g.stats["band_pairs"] <= gm.stats["band_pairs"]
     for k in ("slot_count", "slot_core", "slot_node"):
         assert np.array_equal(gp.stages[k], gm.stages[k]), k
     same_graph(gp, ref)
     same_graph(gm, ref)
+
+
+@pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3, synth.PREC_FP16])
+def test_screening_exact_at_eps(ctx, prec):
+    """Tile pairs are skipped only when their balls prove them empty.  Groups
+    of 300 identical points (balls of radius 0) on the first axis at 0, 2,
+    4 + 2^-20 and 100 with eps = 2: the first two are exactly eps apart
+    (D = eps^2, neighbours, one cluster), the third lies just beyond eps of
+    the second (its own cluster), the fourth is far (its tile pairs are
+    screened out).  The graph is the oracle's and the unscreened one's."""
+    from paper_2011_03209_amd import binding
+    d = 16
+    X = np.zeros((1200, d), np.float32)
+    for g, x0 in enumerate((0.0, 2.0, 4.0 + 2.0 ** -20, 100.0)):
+        X[300 * g:300 * (g + 1), 0] = x0
+    X = X[np.random.default_rng(5).permutation(1200)]
+    params = synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=1)], eps=2.0, min_pts=5, precision=prec)
+    g, ref = run_and_compare(ctx, X, params)
+    assert g.n_nodes == 3, g.n_nodes
+    assert g.stats["tiles_screened_out"] > 0
+    cloud = ctx.cloud(X)
+    try:
+        gn = cloud.run(params, flags=binding.FLAG_NO_SCREEN)
+    finally:
+        cloud.destroy()
+    assert gn.stats["tiles_screened_out"] == 0
+    same_graph(gn, ref)
+
+
+def test_screening_on_blobs(ctx):
+    """Well separated blobs (R^32, 4 blobs 40 sigma apart, 20,000 points, one
+    interval): most tile pairs join two blobs and are screened out (tiles
+    that straddle two blobs in the locality order are kept); the graph is
+    the oracle's."""
+    rng = np.random.default_rng(31)
+    X, _ = synth.blobs(rng, 20000, 32, 4, 40.0)
+    params = synth.Params([synth.Axis(synth.LENS_L2, 1, 0.0)], eps=9.0, min_pts=6, precision=synth.PREC_BF16X3)
+    g, ref = run_and_compare(ctx, X, params)
+    assert g.stats["tiles_screened_out"] > g.stats["tiles"], (g.stats["tiles_screened_out"], g.stats["tiles"])
+    assert g.stats["pairs_computed"] < g.stats["pairs"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -482,33 +530,103 @@ def test_serving_alone_vs_mix():
 
 def test_serving_under_memory_pressure():
     """Serving with an arena that holds the clouds and about one and a half
-    of the largest request's work arrays, on three stream slots: requests that
-    run out of arena mid-run are queued again until memory is returned (their
-    queued kernels finish before their memory is released), and every graph
-    is the graph of its solo run."""
+    of the largest request's reservation, on three stream slots.  A request
+    reserves its whole workspace in one block after binning, before its tile
+    pass; one that cannot have it waits (and holds the queue) until memory is
+    returned, so no tile pass is ever thrown away, and every graph is the
+    graph of its solo run."""
     from paper_2011_03209_amd import binding
     raw = synth.serving_clouds(scale=0.02)
     reqs = synth.serving_requests(raw, 12, qps=0.0)
     big = binding.Context(arena_bytes=8 << 30)
     try:
         clouds = [big.cloud(X) for X in raw]
+        cloud_bytes = big.memory()[0]                   # the resident clouds
         alone = [clouds[c].run(p) for (_, c, p) in reqs]
-        peak = max(g.stats["arena_peak_bytes"] for g in alone)
+        res = sorted((g.stats["reserved_bytes"] for g in alone), reverse=True)
+        assert all(g.stats["reserve_overflow_bytes"] == 0 for g in alone)
         for c in clouds:
             c.destroy()
     finally:
         big.close()
-    cloud_bytes = sum(X.nbytes + (1 << 20) for X in raw)
-    ctx = binding.Context(arena_bytes=int(cloud_bytes + 1.5 * peak) + (16 << 20), serving_streams=3)
+    # the largest requests first (they start together on the three slots),
+    # with room beside the largest reservation for half of the second one
+    # (plus what three requests keep from their lens and binning stages: the
+    # lens values and the slot arrays, 8 bytes per point and 12 per slot)
+    order = sorted(range(len(reqs)), key=lambda k: -alone[k].stats["reserved_bytes"])
+    phase_a = max(8 * raw[c].shape[0] + 12 * alone[k].stats["n_slots"] + 4096 for k, (_, c, _) in enumerate(reqs))
+    ctx = binding.Context(arena_bytes=int(cloud_bytes + res[0] + 0.5 * res[1] + 3 * phase_a) + (1 << 20),
+                          serving_streams=3)
     try:
         clouds = [ctx.cloud(X) for X in raw]
-        tickets = [clouds[c].submit(p) for (_, c, p) in reqs]
-        mixed = [binding.wait(ctx, t) for t in tickets]
+        tickets = {k: clouds[reqs[k][1]].submit(reqs[k][2]) for k in order}
+        mixed = [binding.wait(ctx, tickets[k]) for k in range(len(reqs))]
         for a, b in zip(alone, mixed):
             same_graph(a, b)
+        assert all(g.stats["tile_passes_redone"] == 0 for g in mixed)
+        assert sum(g.stats["admission_waits"] for g in mixed) > 0     # the arena did run short
         for c in clouds:
             c.destroy()
     finally:
+        ctx.close()
+
+
+def test_serving_large_request_among_a_stream_of_small_ones():
+    """A large request submitted into a continuing stream of small ones, with
+    an arena that holds the large request's reservation only when few small
+    ones run: once it has waited, no new request starts before it has its
+    reservation, so it finishes while the small ones keep arriving."""
+    import threading
+    import time
+    from paper_2011_03209_amd import binding
+    rng = np.random.default_rng(9)
+    Xs, _ = synth.gaussian_mixture(rng, 3000, 32, 5)
+    Xl, _ = synth.gaussian_mixture(rng, 60000, 64, 8)
+    ps = synth.Params([synth.Axis(synth.LENS_L2, 5, 0.3)], eps=8.4, min_pts=5, precision=synth.PREC_BF16X3)
+    pl = synth.Params([synth.Axis(synth.LENS_L2, 2, 0.3)], eps=11.9, min_pts=8, precision=synth.PREC_BF16X3)
+    probe = binding.Context(arena_bytes=8 << 30)
+    try:
+        cs, cl = probe.cloud(Xs), probe.cloud(Xl)
+        gs_alone, gl_alone = cs.run(ps), cl.run(pl)
+        t0 = time.perf_counter()
+        cl.run(pl)
+        solo_s = time.perf_counter() - t0
+        rs, rl = gs_alone.stats["reserved_bytes"], gl_alone.stats["reserved_bytes"]
+        cs.destroy()
+        cl.destroy()
+    finally:
+        probe.close()
+    assert rl > 8 * rs
+    # room for the large reservation beside one small one, not two
+    ctx = binding.Context(arena_bytes=int(Xs.nbytes + Xl.nbytes + rl + 1.5 * rs) + (16 << 20), serving_streams=3)
+    stop = threading.Event()
+    small = []
+    try:
+        cs, cl = ctx.cloud(Xs), ctx.cloud(Xl)
+
+        def feed():
+            while not stop.is_set():
+                small.append(cs.submit(ps))
+                time.sleep(0.002)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        time.sleep(0.2)
+        tl = cl.submit(pl)
+        budget = 1.0 + 20 * solo_s
+        gl = binding.wait(ctx, tl, timeout_us=int(budget * 1e6))   # raises if the large one starves
+        stop.set()
+        th.join()
+        same_graph(gl, gl_alone)
+        assert gl.stats["tile_passes_redone"] == 0
+        for t in small:
+            g = binding.wait(ctx, t)
+            assert g.stats["tile_passes_redone"] == 0
+        same_graph(g, gs_alone)
+        cs.destroy()
+        cl.destroy()
+    finally:
+        stop.set()
         ctx.close()
 
 
