@@ -38,11 +38,17 @@ __device__ __forceinline__ int last_le(const double *a, int n, double f) {
     return lo - 1;
 }
 
-// *out += the wave's sum of v (one atomic per wave; every lane of the wave
-// calls it).
-__device__ __forceinline__ void wave_pair_sum(unsigned long long v, unsigned long long *out) {
+// *out += the workgroup's sum of v (one atomic per 256-thread workgroup;
+// every thread of the workgroup calls it).
+__device__ __forceinline__ void block_pair_sum(unsigned long long v, unsigned long long *out) {
+    __shared__ unsigned long long part[4];
     for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && v) atomicAdd(out, v);
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(out, t);
+    }
 }
 
 // Per point: its range of intervals on each axis, its number of elements,
@@ -71,8 +77,8 @@ __global__ void k_member_count(const double *f0, const double *f1, int64_t n,
         range4[4 * i + 3] = kh1;
         count[i] = c;
     }
-    // every lane of the wave reaches this point (no early return)
-    if (pair_sum) wave_pair_sum((unsigned long long)c * (unsigned long long)(c > 0 ? c - 1 : 0) / 2, pair_sum);
+    // every thread of the workgroup reaches this point (no early return)
+    if (pair_sum) block_pair_sum((unsigned long long)c * (unsigned long long)(c > 0 ? c - 1 : 0) / 2, pair_sum);
 }
 
 __global__ void k_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,

@@ -216,19 +216,20 @@ __global__ void __launch_bounds__(256) k_screen(const TileItem *__restrict__ ite
 }
 
 // The kept tile pairs, in their launch order, each with its own bitmask
-// block (its position); row0_blk[rb_off[e] + J] = the block of kept pair
-// (0, J) of element e, -1 if it was screened out.
+// block (its position); diag_blk / next_blk[rb_off[e] + I] = the blocks of
+// kept pairs (I, I) and (I, I + 1) of element e (for the hooking pass).
 __global__ void k_compact_items(const TileItem *__restrict__ items, int64_t n, const uint8_t *__restrict__ keep,
                                 const int64_t *__restrict__ pos, const int64_t *__restrict__ rb_off,
-                                TileItem *__restrict__ out, int64_t *__restrict__ row0_blk,
-                                unsigned long long *__restrict__ pairs) {
+                                TileItem *__restrict__ out, int64_t *__restrict__ diag_blk,
+                                int64_t *__restrict__ next_blk, unsigned long long *__restrict__ pairs) {
     const int64_t i = block_linear() * blockDim.x + threadIdx.x;
     unsigned long long np = 0;                 // in-element pairs of the kept tile pair
     if (i < n) {
         TileItem it = items[i];
         const int64_t p = pos[i];
         const bool k = keep[i] != 0;
-        if (it.I == 0) row0_blk[rb_off[it.e] + it.J] = k ? p : -1;
+        if (it.J == it.I) diag_blk[rb_off[it.e] + it.I] = p;          // diagonal pairs are always kept
+        if (it.J == it.I + 1) next_blk[rb_off[it.e] + it.I] = k ? p : -1;
         if (k) {
             const int64_t ri = min((int64_t)TILE, (int64_t)it.ne - (int64_t)it.I * TILE);
             const int64_t rj = min((int64_t)TILE, (int64_t)it.ne - (int64_t)it.J * TILE);
@@ -266,11 +267,11 @@ hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off
 }
 
 hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t *keep, const int64_t *pos,
-                                const int64_t *rb_off, TileItem *out, int64_t *row0_blk, unsigned long long *pairs,
-                                hipStream_t s) {
+                                const int64_t *rb_off, TileItem *out, int64_t *diag_blk, int64_t *next_blk,
+                                unsigned long long *pairs, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_compact_items<<<grid_2d((n + 255) / 256), dim3(256), 0, s>>>(items, n, keep, pos, rb_off, out, row0_blk,
-                                                                    pairs);
+    k_compact_items<<<grid_2d((n + 255) / 256), dim3(256), 0, s>>>(items, n, keep, pos, rb_off, out, diag_blk,
+                                                                    next_blk, pairs);
     return hipGetLastError();
 }
 

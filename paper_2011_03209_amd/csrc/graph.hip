@@ -239,15 +239,19 @@ __global__ void __launch_bounds__(256) k_cc_tiles(TileTable tt, const uint32_t *
     cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
 }
 
-// Hooking pass before k_cc_tiles (the sampling idea of Afforest, Sutton et al.):
-// for every element, each core point of column block J is hung under its
-// first core neighbour in row block 0 (block (0, J)), and block (0, 0) is
-// merged completely.  Dense clusters then reach k_cc_tiles as single trees,
-// so nearly every block there passes its label check without merges.  One
-// wave per (element, J); `rb_off` numbers the column blocks of all elements.
+// Hooking pass before k_cc_tiles (the sampling idea of Afforest, Sutton et
+// al.): for every row block I of every element, the diagonal block (I, I) is
+// merged completely, and each core point of row block I + 1 is hung under
+// its first core neighbour in row block I (block (I, I + 1)).  Consecutive
+// row blocks of one cluster are chained, so dense clusters reach k_cc_tiles
+// as single trees and nearly every block there passes its label check
+// without merges, in point order and in the cells' locality order alike.
+// One wave per row block; `rb_off` numbers the row blocks of all elements.
+// diag_blk / next_blk: the blocks of (I, I) and (I, I + 1) at rb_off[e] + I
+// (-1: not computed), or null to locate them in the full table.
 __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb_off, int64_t n_rb,
-                                                 int32_t n_elem, const int64_t *row0_blk, const uint32_t *bitmask,
-                                                 const int32_t *count, int32_t min_pts,
+                                                 int32_t n_elem, const int64_t *diag_blk, const int64_t *next_blk,
+                                                 const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
                                                  int32_t *parent) {
     __shared__ int2 queue[4][CC_QCAP];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -262,23 +266,22 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
     WaveTile tl;
     tl.ok = true;
     tl.e = e;
-    tl.I = 0;
-    tl.J = (int)(k - rb_off[e]);
+    tl.I = (int)(k - rb_off[e]);
+    tl.J = tl.I;
     tl.slot0 = tt.elem_off[e];
     tl.ne = tt.elem_off[e + 1] - tl.slot0;
     const int64_t T = (tl.ne + TILE - 1) / TILE;
-    if (tl.ne <= 0 || tl.J >= T) return;
-    if (row0_blk) {
-        tl.blk = row0_blk[k];                           // screened out: no neighbours to hook
-        if (tl.blk < 0) return;
-    } else {
-        tl.blk = tt.blk_off[e] + tile_local_index(tt.colpre + tt.cp_off[e], T, tt.super, 0, tl.J);
-    }
-    if (tl.J == 0) {
-        cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
-        return;
-    }
-    // block (0, J): lane holds rows 2l, 2l+1 (words) and columns l, l+64
+    if (tl.ne <= 0 || tl.I >= T) return;
+    const int64_t *cp = tt.colpre + tt.cp_off[e];
+    // (I, I): merged completely
+    tl.blk = diag_blk ? diag_blk[k] : tt.blk_off[e] + tile_local_index(cp, T, tt.super, tl.I, tl.I);
+    if (tl.blk >= 0) cc_block(tl, bitmask, count, min_pts, parent, queue[w]);
+    if (tl.I + 1 >= T) return;
+    // (I, I + 1): each core column point hung under its first core row neighbour
+    tl.J = tl.I + 1;
+    tl.blk = next_blk ? next_blk[k] : tt.blk_off[e] + tile_local_index(cp, T, tt.super, tl.I, tl.J);
+    if (tl.blk < 0) return;                           // screened out: no neighbours to hook
+    // lane holds rows 2l, 2l+1 (words) and columns l, l+64
     uint32_t wd[8];
     {
         const uint4 *src = (const uint4 *)(bitmask + (uint64_t)tl.blk * TILE_WORDS) + 2 * lane;
@@ -286,12 +289,13 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
         wd[0] = u0.x; wd[1] = u0.y; wd[2] = u0.z; wd[3] = u0.w;
         wd[4] = u1.x; wd[5] = u1.y; wd[6] = u1.z; wd[7] = u1.w;
     }
+    const int64_t rowbase = (int64_t)tl.I * TILE, colloc = (int64_t)tl.J * TILE;
     bool rc[2], ccore[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int64_t r = 2 * lane + q;
+        const int64_t r = rowbase + 2 * lane + q;
         rc[q] = r < tl.ne && count[tl.slot0 + r] >= min_pts;
-        const int64_t c = (int64_t)tl.J * TILE + lane + 64 * q;
+        const int64_t c = colloc + lane + 64 * q;
         ccore[q] = c < tl.ne && count[tl.slot0 + c] >= min_pts;
     }
     const uint64_t rc0 = __ballot(rc[0]), rc1 = __ballot(rc[1]);   // rows 2l and 2l+1
@@ -312,9 +316,9 @@ __global__ void __launch_bounds__(256) k_cc_hook(TileTable tt, const int64_t *rb
         if (first1 < 0 && ((hw >> (lane & 31)) & 1u)) first1 = r;
         if (__ballot((ccore[0] && first0 < 0) || (ccore[1] && first1 < 0)) == 0) break;
     }
-    const int64_t colbase = tl.slot0 + (int64_t)tl.J * TILE;
-    if (ccore[0] && first0 >= 0) uf_union(parent, (int32_t)(tl.slot0 + first0), (int32_t)(colbase + lane));
-    if (ccore[1] && first1 >= 0) uf_union(parent, (int32_t)(tl.slot0 + first1), (int32_t)(colbase + lane + 64));
+    const int64_t rowslot = tl.slot0 + rowbase, colslot = tl.slot0 + colloc;
+    if (ccore[0] && first0 >= 0) uf_union(parent, (int32_t)(rowslot + first0), (int32_t)(colslot + lane));
+    if (ccore[1] && first1 >= 0) uf_union(parent, (int32_t)(rowslot + first1), (int32_t)(colslot + lane + 64));
 }
 
 __global__ void k_cc_init(int32_t *parent, int64_t n) {
@@ -369,10 +373,17 @@ __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
 }
 
 // minpt[r] = the smallest point id among the core slots whose root is r.
+// A core slot whose predecessor is a core slot of the same component with a
+// smaller point id cannot hold the minimum (points ascend within a cell's
+// run of slots), so only the other slots take part: far fewer atomics on
+// the same root.
 __global__ void k_root_minpt(const int32_t *count, int32_t min_pts, const int32_t *parent,
                              const uint32_t *slot_point, int32_t *minpt, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && count[i] >= min_pts) atomicMin(&minpt[parent[i]], (int32_t)slot_point[i]);
+    if (i >= n || count[i] < min_pts) return;
+    const int32_t r = parent[i];
+    if (i > 0 && count[i - 1] >= min_pts && parent[i - 1] == r && slot_point[i - 1] < slot_point[i]) return;
+    atomicMin(&minpt[r], (int32_t)slot_point[i]);
 }
 
 // Root of rank r (roots counted in slot order): key (element, minpt), value r.
@@ -634,11 +645,11 @@ hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const i
 }
 
 hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
-                          const int64_t *row0_blk, const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
-                          int32_t *parent, hipStream_t s) {
+                          const int64_t *diag_blk, const int64_t *next_blk, const uint32_t *bitmask,
+                          const int32_t *count, int32_t min_pts, int32_t *parent, hipStream_t s) {
     if (n_rb <= 0) return hipSuccess;
-    k_cc_hook<<<dim3((unsigned)((n_rb + 3) / 4)), 256, 0, s>>>(tt, rb_off, n_rb, n_elem, row0_blk, bitmask, count,
-                                                               min_pts, parent);
+    k_cc_hook<<<dim3((unsigned)((n_rb + 3) / 4)), 256, 0, s>>>(tt, rb_off, n_rb, n_elem, diag_blk, next_blk,
+                                                               bitmask, count, min_pts, parent);
     return hipGetLastError();
 }
 

@@ -329,11 +329,13 @@ hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off
 // zeroed by the caller).
 hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, const uint8_t *cell,
                               unsigned long long *r2, hipStream_t s);
-// out[pos[i]] = items[i] with blk = pos[i] for kept items; row0_blk of
-// every (e, 0, J); *pairs += the in-element pairs of the kept tile pairs.
+// out[pos[i]] = items[i] with blk = pos[i] for kept items; diag_blk and
+// next_blk (the blocks of (I, I) and (I, I + 1) at rb_off[e] + I, -1 if
+// screened out; next_blk preset to -1 by the caller); *pairs += the
+// in-element pairs of the kept tile pairs.
 hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t *keep, const int64_t *pos,
-                                const int64_t *rb_off, TileItem *out, int64_t *row0_blk, unsigned long long *pairs,
-                                hipStream_t s);
+                                const int64_t *rb_off, TileItem *out, int64_t *diag_blk, int64_t *next_blk,
+                                unsigned long long *pairs, hipStream_t s);
 
 // tile.hip
 struct TileArgs {
@@ -401,11 +403,12 @@ hipError_t launch_cc_init(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_compress(int32_t *parent, int64_t n_slots, hipStream_t s);
 hipError_t launch_cc_tiles(const TileTable &tt, const uint32_t *bitmask, const int32_t *count,
                            int32_t min_pts, int32_t *parent, hipStream_t s);
-// row0_blk: block of tile pair (0, J) of each element at rb_off[e] + J (-1:
-// not computed), or null for the full table (tile_local_index).
+// diag_blk / next_blk: blocks of tile pairs (I, I) and (I, I + 1) of each
+// element at rb_off[e] + I (-1: not computed), or null for the full table
+// (tile_local_index).
 hipError_t launch_cc_hook(const TileTable &tt, const int64_t *rb_off, int64_t n_rb, int32_t n_elem,
-                          const int64_t *row0_blk, const uint32_t *bitmask, const int32_t *count, int32_t min_pts,
-                          int32_t *parent, hipStream_t s);
+                          const int64_t *diag_blk, const int64_t *next_blk, const uint32_t *bitmask,
+                          const int32_t *count, int32_t min_pts, int32_t *parent, hipStream_t s);
 hipError_t launch_cc_flatten(const int32_t *count, int32_t min_pts, int32_t *parent,
                              uint8_t *isroot, int64_t n_slots, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);

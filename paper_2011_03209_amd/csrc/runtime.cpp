@@ -1104,9 +1104,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     auto r256 = [](uint64_t b) { return (b + 16 + 255) & ~(uint64_t)255; };
     const uint64_t E1 = (uint64_t)std::max<int64_t>(E_count, 1), U = (uint64_t)Sa;
     uint64_t fixed = 0;
-    if (screen)                                                 // kept tile pairs, row-0 blocks
+    if (screen)                                                 // kept tile pairs, hook blocks
         fixed += r256((uint64_t)std::max<int64_t>(n_tiles, 1) * sizeof(TileItem)) +
-                 r256((uint64_t)std::max<int64_t>(nrb, 1) * 8) + r256(8);
+                 2 * r256((uint64_t)std::max<int64_t>(nrb, 1) * 8) + r256(8);
     if (use_macro)
         fixed += r256(mitem_off.size() * 8) + r256(mcolpre.size() * 8) + 2 * r256(E1 * 8) +
                  r256((uint64_t)std::max<int64_t>(n_mitems, 1) * sizeof(MacroItem));
@@ -1153,13 +1153,15 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     if (may_retry && res) admitted(ctx, out.req);
 
     // ---- the kept tile pairs (screened runs): their own bitmask blocks
-    int64_t *row0_blk = nullptr;
+    int64_t *diag_blk = nullptr, *next_blk = nullptr;
     if (screen) {
         TileItem *kept = rm.get<TileItem>(std::max<int64_t>(n_tiles, 1));
-        row0_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
+        diag_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
+        next_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
         unsigned long long *pc = rm.get<unsigned long long>(1);
         HIPCHK(hipMemsetAsync(pc, 0, 8, s));
-        HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, row0_blk, pc, s));
+        HIPCHK(hipMemsetAsync(next_blk, 0xff, (size_t)std::max<int64_t>(nrb, 1) * 8, s));   // -1: no pair (I, I + 1)
+        HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, diag_blk, next_blk, pc, s));
         unsigned long long pairs_c = 0;
         HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1284,7 +1286,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int32_t *node = lm.get<int32_t>(Sa);
     int32_t *node_elem = lm.get<int32_t>(Sa);
     HIPCHK(launch_cc_init(parent, S, s));
-    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, row0_blk, bitmask, count, P->min_pts, parent, s));
+    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, diag_blk, next_blk, bitmask, count, P->min_pts,
+                          parent, s));
     HIPCHK(launch_cc_compress(parent, S, s));
     HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
     HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
