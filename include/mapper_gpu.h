@@ -159,6 +159,10 @@ typedef struct {
     int32_t tile_passes_redone;  /* serving: tile passes lost to a later shortage */
     int64_t tiles_screened_out;  /* tile pairs proven empty by their balls, not computed */
     int64_t pairs_computed;  /* in-element pairs of the tile pairs computed */
+    int32_t tune_sampled;    /* MAPPER_PREC_AUTO: 1 if this run timed the precisions (else a cached choice) */
+    int32_t tune_pad;
+    double tune_pred_ms[5];  /* ... the predicted tile + recheck ms of each precision (FP32, BF16, BF16X3,
+                                FP16, FP16X3); the smallest was chosen */
 } mapper_run_stats;
 
 /* --- context ------------------------------------------------------------

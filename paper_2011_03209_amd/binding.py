@@ -61,10 +61,14 @@ class RunStats(ctypes.Structure):
                 ("band_halfwidth", ctypes.c_double),
                 ("reserved_bytes", ctypes.c_uint64), ("reserve_overflow_bytes", ctypes.c_uint64),
                 ("admission_waits", ctypes.c_int32), ("tile_passes_redone", ctypes.c_int32),
-                ("tiles_screened_out", ctypes.c_int64), ("pairs_computed", ctypes.c_int64)]
+                ("tiles_screened_out", ctypes.c_int64), ("pairs_computed", ctypes.c_int64),
+                ("tune_sampled", ctypes.c_int32), ("tune_pad", ctypes.c_int32),
+                ("tune_pred_ms", ctypes.c_double * 5)]
 
     def as_dict(self) -> Dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["tune_pred_ms"] = list(self.tune_pred_ms)
+        return d
 
 
 _P = ctypes.POINTER

@@ -23,11 +23,12 @@ constexpr int CB = 256;       // points per block (one per thread)
 constexpr int CC = 32;        // columns per LDS slab
 
 // cell[i] = the landmark nearest to point i (smallest |l|^2 - 2 x.l, FP32;
-// the order is a heuristic, so rounding does not matter).  Landmarks are
-// staged whole in LDS (ncell * d <= CELL_LDS_FLOATS).
+// the order is a heuristic, so rounding does not matter), or the outlier
+// cell ncell when the point lies farther from it than limit2 (squared).
+// Landmarks are staged whole in LDS (ncell * d <= CELL_LDS_FLOATS).
 __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X, int64_t n, int32_t d,
                                                      const float *__restrict__ land, int32_t ncell,
-                                                     uint8_t *__restrict__ cell) {
+                                                     const float *__restrict__ limit2, uint8_t *__restrict__ cell) {
     __shared__ float L[CELL_LDS_FLOATS];
     __shared__ float tile[CB][CC + 1];
     __shared__ float lnorm[CELL_MAX];
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
         lnorm[threadIdx.x] = s;
     }
     const int64_t row0 = (int64_t)blockIdx.x * CB;
-    float acc[CELL_MAX];
+    float acc[CELL_MAX], nx = 0.f;
 #pragma unroll
     for (int c = 0; c < CELL_MAX; ++c) acc[c] = 0.f;
     for (int32_t c0 = 0; c0 < d; c0 += CC) {
@@ -54,6 +55,7 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
         __syncthreads();
         for (int j = 0; j < cw; ++j) {
             const float x = tile[threadIdx.x][j];
+            nx += x * x;
 #pragma unroll
             for (int c = 0; c < CELL_MAX; ++c)
                 if (c < ncell) acc[c] += x * L[c * d + c0 + j];
@@ -69,17 +71,40 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
             const float v = lnorm[c] - 2.f * acc[c];
             if (v < bv) { bv = v; best = c; }
         }
-    cell[my] = (uint8_t)best;
+    // |x|^2 + bv is the squared distance to the landmark: beyond the cell's
+    // limit the point goes to the outlier cell (id ncell)
+    cell[my] = (uint8_t)(nx + bv > limit2[best] ? ncell : best);
+}
+
+// out[i] = min over j != i of |x_i - x_j|^2 among the m sample rows (FP32;
+// it only separates isolated rows from rows in dense regions).
+__global__ void k_sample_nn2(const float *__restrict__ sub, int32_t m, int32_t d, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const float *x = sub + (int64_t)i * d;
+    float best = 3.0e38f;
+    for (int j = 0; j < m; ++j) {
+        if (j == i) continue;
+        const float *y = sub + (int64_t)j * d;
+        float acc = 0.f;
+        for (int k = 0; k < d; ++k) {
+            const float t = x[k] - y[k];
+            acc += t * t;
+        }
+        best = acc < best ? acc : best;
+    }
+    out[i] = best;
 }
 
 // r2[c] = max over the points of cell c of |x - l_c|^2 (FP64 sums of
 // squares of FP32 differences), as the bits of a non-negative double, which
 // order like the values.
 __global__ void k_cell_radius(const float *__restrict__ X, int64_t n, int32_t d, const float *__restrict__ land,
-                              const uint8_t *__restrict__ cell, unsigned long long *__restrict__ r2) {
+                              int32_t ncell, const uint8_t *__restrict__ cell, unsigned long long *__restrict__ r2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = cell[i];
+    if (c >= ncell) return;                          // the outlier cell has no ball
     const float *x = X + i * (int64_t)d, *l = land + (int64_t)c * d;
     double acc = 0.0;
     for (int j = 0; j < d; ++j) {
@@ -243,7 +268,21 @@ __global__ void k_compact_items(const TileItem *__restrict__ items, int64_t n, c
     if ((threadIdx.x & (WAVE - 1)) == 0 && np) atomicAdd(pairs, np);
 }
 
+__global__ void k_sample_items(const TileItem *__restrict__ items, int64_t n, int64_t m, TileItem *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    TileItem it = items[i * n / m];                  // i < m <= 8192: no overflow
+    it.blk = i;
+    out[i] = it;
+}
+
 }  // namespace
+
+hipError_t launch_sample_items(const TileItem *items, int64_t n, int64_t m, TileItem *out, hipStream_t s) {
+    if (m <= 0 || n <= 0 || m > n) return m <= 0 ? hipSuccess : hipErrorInvalidValue;
+    k_sample_items<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(items, n, m, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_tile_balls(const float *X, int32_t d, const uint32_t *slot_point, const int64_t *elem_off,
                              const int64_t *rb_off, int32_t n_elem, int64_t nrb, const uint8_t *cell,
@@ -276,17 +315,23 @@ hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t 
 }
 
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
-                               uint8_t *cell, hipStream_t s) {
+                               const float *limit2, uint8_t *cell, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (ncell < 1 || ncell > CELL_MAX || (int64_t)ncell * d > CELL_LDS_FLOATS) return hipErrorInvalidValue;
-    k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, land, ncell, cell);
+    if (ncell < 1 || ncell >= CELL_MAX || (int64_t)ncell * d > CELL_LDS_FLOATS) return hipErrorInvalidValue;
+    k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, land, ncell, limit2, cell);
     return hipGetLastError();
 }
 
-hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, const uint8_t *cell,
-                              unsigned long long *r2, hipStream_t s) {
+hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    k_sample_nn2<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(sub, m, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
+                              const uint8_t *cell, unsigned long long *r2, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_cell_radius<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, d, land, cell, r2);
+    k_cell_radius<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, d, land, ncell, cell, r2);
     return hipGetLastError();
 }
 

@@ -280,14 +280,14 @@ __host__ __device__ inline int64_t panel_row_stride(int prec, int dp) {
     return ((b >> 7) & 1) ? b : b + 128;
 }
 
-// Supertile size of a tile launch.  The hi/lo splits read twice the bytes of
-// a single 16-bit product per pair; for them 24 x 24 supertiles (24 row
-// panels of at most 144 KB, about 3.4 MB, inside an XCD's 4 MB L2) were
-// measured 2-3% faster than 8 x 8 at 1M x 256, while 32 x 32 overflows the L2
-// and is slower.  Single products and longer rows keep 8 x 8.
-inline int supertile_size(int prec, int dp) {
-    return ((prec == P_BF16X3 || prec == P_FP16X3) && panel_row_stride(prec, dp) <= 1152) ? 24 : 8;
-}
+// Supertile size of a tile launch, the same for every precision (the tile
+// order is fixed before the precision is chosen).  For the hi/lo splits,
+// which read twice the bytes of a single 16-bit product per pair, 24 x 24
+// supertiles (24 row panels of at most 144 KB, about 3.4 MB, inside an XCD's
+// 4 MB L2) were measured 2-3% faster than 8 x 8 at 1M x 256, while 32 x 32
+// overflows the L2 and is slower; single products were within 1% from 4 x 4
+// to 24 x 24.  Rows longer than 256 coordinates keep 8 x 8.
+inline int supertile_size(int d) { return d <= 256 ? 24 : 8; }
 
 struct PackArgs {
     const float *X; int32_t d; int32_t dp;
@@ -307,8 +307,15 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 // whole in LDS: ncell * d <= CELL_LDS_FLOATS)
 constexpr int CELL_MAX = 64;
 constexpr int CELL_LDS_FLOATS = 16384;
+// cell[i] = nearest landmark, or ncell (the outlier cell) past limit2[c]
+// (squared distance); ncell < CELL_MAX.
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
-                               uint8_t *cell, hipStream_t s);
+                               const float *limit2, uint8_t *cell, hipStream_t s);
+// out[i] = squared distance from sample row i to its nearest other row.
+hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out, hipStream_t s);
+// out[i] = items[i * n / m] with blk = i (an evenly strided sample of a tile
+// list, each with its own bitmask block).
+hipError_t launch_sample_items(const TileItem *items, int64_t n, int64_t m, TileItem *out, hipStream_t s);
 // keys[i] >>= shift
 hipError_t launch_shift_keys(uint64_t *keys, int64_t n, int shift, hipStream_t s);
 // Ball (FP32 center, FP64 radius bound) of each of the nrb row blocks
@@ -327,8 +334,8 @@ hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off
                          int32_t d, double E, uint8_t *keep, hipStream_t s);
 // r2[c] = max |x - land_c|^2 over the points of cell c (double bits; r2
 // zeroed by the caller).
-hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, const uint8_t *cell,
-                              unsigned long long *r2, hipStream_t s);
+hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
+                              const uint8_t *cell, unsigned long long *r2, hipStream_t s);
 // out[pos[i]] = items[i] with blk = pos[i] for kept items; diag_blk and
 // next_blk (the blocks of (I, I) and (I, I + 1) at rb_off[e] + I, -1 if
 // screened out; next_blk preset to -1 by the caller); *pairs += the

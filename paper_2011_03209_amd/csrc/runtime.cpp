@@ -465,14 +465,14 @@ void balanced_endpoints(Arena &arena, const double *f, int64_t n, int nint, doub
 }
 
 // ----------------------------------------------------------------- autotuner
-// Precision choice: predicted time = matrix-core time + (band fraction x FP64
-// recheck time).  The band fraction of each precision is measured on a
-// sample of in-element pairs (exact FP64 distances from the device) against
-// the nominal half-width of that precision's certified band.
-struct TuneSample {
-    std::vector<double> D, na, nb;
-};
-
+// Precision choice (MAPPER_PREC_AUTO), measured: on the first run of its
+// kind, each of the five precisions packs the run's panels and runs the tile
+// kernel on an evenly strided sample of up to 8192 of the run's own tile
+// pairs (after screening), timed with HIP events; its band pairs are counted.
+// Predicted time = sampled tile time x (tile pairs / sample) + band pairs x
+// (tile pairs / sample) x the FP64 recheck's cost per pair (a gather of two
+// FP32 rows at 7 TB/s, as the recheck kernel runs).  The fastest is cached
+// per kind of run (tune_key) and used without sampling afterwards.
 using TuneKey = std::tuple<int, int, int>;
 
 // The autotuner's cache key: d, eps^2 against the cloud's median squared row
@@ -514,38 +514,81 @@ int cached_precision(mapper_context *ctx, const TuneKey &key) {
     return it == ctx->tune.end() ? -1 : it->second;
 }
 
-int choose_precision(mapper_context *ctx, int d, int dp16, double E, const TuneSample &ts, const TuneKey &key) {
-    if (ts.D.empty()) return P_BF16X3;
-    const double u = std::ldexp(1.0, -23);
-    auto gam = [&](double k) { return k * u / (1.0 - k * u); };
-    const double K16 = dp16, K32 = 32.0 * std::ceil(d / 32.0);
-    // nominal e_i / |x_i|^2 for each precision (same structure as the packing bound)
-    const double c[5] = {
-        gam(2 * K32 + 2) * 0.5,                                       // FP32
-        gam(K16 + 2) * 0.5 + std::ldexp(1.0, -9) * 0.67,              // BF16
-        gam(K16 + 2) * 0.5 + gam(2 * K16 + 2) * std::ldexp(1.0, -8) + std::ldexp(1.0, -24) * 3,  // BF16X3
-        gam(K16 + 2) * 0.5 + std::ldexp(1.0, -12) * 0.67,             // FP16
-        gam(K16 + 2) * 0.5 + gam(2 * K16 + 2) * std::ldexp(1.0, -11) + std::ldexp(1.0, -24) * 3, // FP16X3
-    };
-    // issued matrix-core seconds per pair (peak FLOP rates, 2 flops per MAC),
-    // and the fraction of peak each precision's tile kernel reaches (measured
-    // on MI355X at 1M x 256: the 16-bit kernels are bound by the chip's power
-    // limit, not by the matrix cores)
-    const double mfma[5] = {2 * K32 / 157e12, 2 * K16 / 2.5e15, 6 * K16 / 2.5e15,
-                            2 * K16 / 2.5e15, 6 * K16 / 2.5e15};
-    const double eff[5] = {0.8, 0.18, 0.41, 0.22, 0.39};
-    const double recheck = 2.0 * d * 4.0 / 6.5e12;          // per band pair: gather of two FP32 rows
-    int best = P_FP32;
-    double tbest = 1e300;
-    for (int p = 0; p < 5; ++p) {
-        size_t inband = 0;
-        for (size_t k = 0; k < ts.D.size(); ++k) {
-            const double beta = 2.0 * c[p] * (ts.na[k] + ts.nb[k]) * 1.05;
-            if (std::fabs(ts.D[k] - E) <= beta) ++inband;
+int tune_precision(mapper_context *ctx, const mapper_cloud *cloud, const TileTable &tt, int64_t n_tiles,
+                   const uint32_t *slot_point, int64_t S, double scale, double E, const TuneKey &key,
+                   mapper_run_stats &st, hipStream_t s) {
+    const int32_t d = cloud->d;
+    const int64_t m = std::min<int64_t>(n_tiles, 8192);
+    int best = P_BF16X3;
+    if (m > 0 && S > 0) {
+        Scope tmp(ctx->arena, s);
+        TileItem *smp = tmp.get<TileItem>(m);
+        HIPCHK(launch_sample_items(tt.items, n_tiles, m, smp, s));
+        TileTable ts = tt;
+        ts.items = smp;
+        ts.n_items = m;
+        float *thrA = tmp.get<float>(S), *thrB = tmp.get<float>(S);
+        int32_t *cnt = tmp.get<int32_t>(S);
+        uint32_t *bm = tmp.get<uint32_t>((uint64_t)m * TILE_WORDS);
+        const int nseg = 8;
+        const int64_t cap = 256;                        // band pairs are counted; few are stored
+        unsigned long long *bn = tmp.get<unsigned long long>(nseg);
+        BandPair *band = tmp.get<BandPair>((uint64_t)nseg * cap);
+        uint64_t most = 0;
+        for (int p = 0; p < 5; ++p) most = std::max<uint64_t>(most, (uint64_t)panel_row_stride(p, panel_dp(p, d)));
+        char *panel = tmp.get<char>((uint64_t)S * most);
+        const double per_band_ms = 8.0 * d / 7.0e12 * 1e3;
+        double bestt = 1e300;
+        for (int p = 0; p < 5; ++p) {
+            PackArgs pk{};
+            pk.X = cloud->X;
+            pk.d = d;
+            pk.dp = panel_dp(p, d);
+            pk.slot_point = slot_point;
+            pk.n_slots = S;
+            pk.prec = p;
+            pk.scale = scale;
+            pk.n_levels = 1;
+            pk.E_scaled[0] = E * scale * scale;
+            pk.panel = panel;
+            pk.thrA = thrA;
+            pk.thrB = thrB;
+            HIPCHK(launch_pack(pk, s));
+            HIPCHK(hipMemsetAsync(cnt, 0, (size_t)S * 4, s));
+            HIPCHK(hipMemsetAsync(bn, 0, (size_t)nseg * 8, s));
+            TileArgs ta{};
+            ta.tt = ts;
+            ta.panel = panel;
+            ta.dp = pk.dp;
+            ta.thrA = thrA;
+            ta.thrB = thrB;
+            ta.bitmask = bm;
+            ta.count = cnt;
+            ta.band = band;
+            ta.band_n = bn;
+            ta.band_cap = cap;
+            ta.nseg = nseg;
+            ta.n_levels = 1;
+            ta.level_slots = S;
+            ta.level_words = (uint64_t)m * TILE_WORDS;
+            Events ev(s, ctx->events);
+            ev.mark();
+            HIPCHK(launch_tiles(p, ta, s));
+            ev.mark();
+            std::vector<unsigned long long> bh;
+            d2h(bh, bn, nseg, s);
+            HIPCHK(hipStreamSynchronize(s));
+            uint64_t nb = 0;
+            for (unsigned long long v : bh) nb += v;
+            const double scale_up = (double)n_tiles / (double)m;
+            const double t = ev.ms(0, 1) * scale_up + (double)nb * scale_up * per_band_ms;
+            st.tune_pred_ms[p] = t;
+            if (t < bestt) {
+                bestt = t;
+                best = p;
+            }
         }
-        const double frac = (double)inband / (double)ts.D.size();
-        const double t = mfma[p] / eff[p] + frac * recheck;
-        if (t < tbest) { tbest = t; best = p; }
+        st.tune_sampled = 1;
     }
     std::lock_guard<std::mutex> lk(ctx->tune_mu);
     ctx->tune[key] = best;
@@ -648,47 +691,45 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
 }
 
 // ------------------------------------------------------------- cloud cells
-// The locality order of a cloud (cells.hip): up to CELL_MAX landmarks by
-// farthest-point sampling over an evenly strided sample of 4096 rows (FP64,
-// on the host; the first sampled row starts), numbered along a
-// nearest-neighbour chain, then every point's nearest landmark on the GPU.  Only clouds large enough to fill several tiles get
-// cells, and only when the landmarks fit the kernel's LDS; otherwise slots
-// stay in point order.  Built once, when the cloud is uploaded.
+// The locality order of a cloud (cells.hip), built once when it is
+// uploaded.  From an evenly strided sample of 4096 rows: each row's nearest
+// other sample row (GPU), the inliers (no more than 4x the median of those
+// squared distances away: isolated rows such as uniform background noise
+// would otherwise be picked first), up to CELL_MAX - 1 landmarks among the
+// inliers by farthest-point sampling (FP64, host), numbered along a
+// nearest-neighbour chain.  Every point then goes to its nearest landmark,
+// or to the outlier cell when it lies farther from it than 1.5x the largest
+// distance of an inlier sample row in that cell.  Each landmark cell gets a
+// ball (the landmark, the largest distance of a member); the outlier cell
+// has none and is near every cell.  Only clouds large enough to fill
+// several tiles get cells, and only when the landmarks fit the kernel's
+// LDS; otherwise slots stay in point order.
 void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     const int64_t n = c->n;
     const int32_t d = c->d;
-    const int ncell = std::min<int>(CELL_MAX, CELL_LDS_FLOATS / std::max(d, 1));
-    if (n < 8 * TILE || ncell < 8) return;
+    const int ncell_max = std::min<int>(CELL_MAX - 1, CELL_LDS_FLOATS / std::max(d, 1));
+    if (n < 8 * TILE || ncell_max < 8) return;
     const int64_t m = std::min<int64_t>(n, 4096), step = n / m;
     std::vector<float> sub((size_t)(m * d));
-    HIPCHK(hipMemcpy2DAsync(sub.data(), (size_t)d * 4, c->X, (size_t)(step * d) * 4, (size_t)d * 4, (size_t)m,
-                            hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    std::vector<double> dmin((size_t)m, 1e300);
-    std::vector<int64_t> pick;
-    int64_t cur = 0;
-    for (int k = 0; k < ncell; ++k) {
-        pick.push_back(cur);
-        const float *y = &sub[(size_t)(cur * d)];
-        int64_t far = 0;
-        for (int64_t i = 0; i < m; ++i) {
-            const float *x = &sub[(size_t)(i * d)];
-            double acc = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double t = (double)x[j] - (double)y[j];
-                acc += t * t;
-            }
-            dmin[(size_t)i] = std::min(dmin[(size_t)i], acc);
-            if (dmin[(size_t)i] > dmin[(size_t)far]) far = i;
-        }
-        if (dmin[(size_t)far] <= 0.0) break;                    // fewer distinct points than landmarks
-        cur = far;
+    std::vector<float> nn2((size_t)m);
+    {
+        Scope tmp(ctx->arena, s);
+        float *dsub = tmp.get<float>((uint64_t)m * d);
+        float *dnn = tmp.get<float>(m);
+        HIPCHK(hipMemcpy2DAsync(dsub, (size_t)d * 4, c->X, (size_t)(step * d) * 4, (size_t)d * 4, (size_t)m,
+                                hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_sample_nn2(dsub, (int32_t)m, d, dnn, s));
+        HIPCHK(hipMemcpyAsync(sub.data(), dsub, sub.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(nn2.data(), dnn, nn2.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
-    const int nc = (int)pick.size();
-    if (nc < 2) return;
-    // number the landmarks along a nearest-neighbour chain, so that the
-    // cells of one cluster (farthest-point sampling splits a large cluster
-    // among several landmarks) are consecutive in the slot order
+    std::vector<float> sorted_nn = nn2;
+    std::nth_element(sorted_nn.begin(), sorted_nn.begin() + m / 2, sorted_nn.end());
+    const float inl = 4.0f * sorted_nn[(size_t)(m / 2)];
+    std::vector<int64_t> rows;                                  // the inlier sample rows
+    for (int64_t i = 0; i < m; ++i)
+        if (nn2[(size_t)i] <= inl) rows.push_back(i);
+    if ((int64_t)rows.size() < 2 * ncell_max) return;
     auto dist2 = [&](int64_t a, int64_t b) {
         const float *x = &sub[(size_t)(a * d)], *y = &sub[(size_t)(b * d)];
         double acc = 0.0;
@@ -698,6 +739,24 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         }
         return acc;
     };
+    std::vector<double> dmin(rows.size(), 1e300);
+    std::vector<int64_t> pick;
+    size_t cur = 0;
+    for (int k = 0; k < ncell_max; ++k) {
+        pick.push_back(rows[cur]);
+        size_t far = 0;
+        for (size_t q = 0; q < rows.size(); ++q) {
+            dmin[q] = std::min(dmin[q], dist2(rows[q], rows[cur]));
+            if (dmin[q] > dmin[far]) far = q;
+        }
+        if (dmin[far] <= 0.0) break;                            // fewer distinct rows than landmarks
+        cur = far;
+    }
+    const int nc = (int)pick.size();
+    if (nc < 2) return;
+    // number the landmarks along a nearest-neighbour chain, so that the
+    // cells of one cluster (farthest-point sampling splits a large cluster
+    // among several landmarks) are consecutive in the slot order
     std::vector<int64_t> chain{pick[0]};
     std::vector<char> used((size_t)nc, 0);
     used[0] = 1;
@@ -712,28 +771,38 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         used[(size_t)best] = 1;
         chain.push_back(pick[(size_t)best]);
     }
+    // each cell's limit: 1.5x the largest distance of an inlier sample row
+    // whose nearest landmark it is
+    std::vector<float> limit2((size_t)nc, 0.f);
+    for (int64_t r : rows) {
+        int best = 0;
+        double bd = dist2(r, chain[0]);
+        for (int k = 1; k < nc; ++k) {
+            const double t = dist2(r, chain[(size_t)k]);
+            if (t < bd) { bd = t; best = k; }
+        }
+        limit2[(size_t)best] = std::max(limit2[(size_t)best], (float)(2.25 * bd));
+    }
     std::vector<float> land((size_t)nc * d);
     for (int k = 0; k < nc; ++k)
         std::memcpy(&land[(size_t)k * d], &sub[(size_t)(chain[k] * d)], (size_t)d * 4);
     uint8_t *cell = (uint8_t *)ctx->arena.alloc((uint64_t)n);
-    float *dl = (float *)ctx->arena.alloc((uint64_t)nc * d * 4);
-    if (!cell || !dl) {                                         // no room: keep point order
-        ctx->arena.release(cell);
-        ctx->arena.release(dl);
-        return;
-    }
+    float *dl = (float *)ctx->arena.alloc((uint64_t)nc * d * 4 + (uint64_t)nc * 4);
     unsigned long long *r2 = (unsigned long long *)ctx->arena.alloc((uint64_t)CELL_MAX * 8);
-    if (!r2) {                                                  // no room: keep point order
+    if (!cell || !dl || !r2) {                                  // no room: keep point order
         ctx->arena.release(cell);
         ctx->arena.release(dl);
+        ctx->arena.release(r2);
         return;
     }
+    float *dlim = dl + (size_t)nc * d;
     std::vector<unsigned long long> r2h((size_t)CELL_MAX, 0);
     try {
         HIPCHK(hipMemcpyAsync(dl, land.data(), land.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_assign_cells(c->X, n, d, dl, nc, cell, s));
+        HIPCHK(hipMemcpyAsync(dlim, limit2.data(), limit2.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_assign_cells(c->X, n, d, dl, nc, dlim, cell, s));
         HIPCHK(hipMemsetAsync(r2, 0, (size_t)CELL_MAX * 8, s));
-        HIPCHK(launch_cell_radius(c->X, n, d, dl, cell, r2, s));
+        HIPCHK(launch_cell_radius(c->X, n, d, dl, nc, cell, r2, s));
         HIPCHK(hipMemcpyAsync(r2h.data(), r2, (size_t)CELL_MAX * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     } catch (DevError &) {
@@ -747,23 +816,25 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     ctx->arena.release(r2);
     // cell balls: landmark l_c, radius r_c >= max |x - l_c| over its points
     // (relative margin 2^-40 for the FP64 sums, d <= BALL_DMAX); the gap of
-    // two cells bounds every distance between their points from below
+    // two cells bounds every distance between their points from below.  Cell
+    // nc (the outliers) has no ball: a gap of -1 keeps it near every cell.
+    const int nall = nc + 1;
     std::vector<double> rad((size_t)nc);
     for (int a = 0; a < nc; ++a) {
         double r2v;
         std::memcpy(&r2v, &r2h[(size_t)a], 8);
         rad[(size_t)a] = std::sqrt(r2v) * (1.0 + 0x1.0p-40);
     }
-    c->cell_gap.assign((size_t)nc * nc, 0.0);
+    c->cell_gap.assign((size_t)nall * nall, -1.0);
     for (int a = 0; a < nc; ++a)
         for (int b = 0; b < nc; ++b)
             if (a != b)
-                c->cell_gap[(size_t)a * nc + b] =
+                c->cell_gap[(size_t)a * nall + b] =
                     std::sqrt(dist2(chain[(size_t)a], chain[(size_t)b])) * (1.0 - 0x1.0p-40) - rad[(size_t)a] -
                     rad[(size_t)b];
-    c->ncell = nc;
+    c->ncell = nall;
     c->cell = cell;
-    c->cell_bits = 32 - __builtin_clz((unsigned)(nc - 1));
+    c->cell_bits = 32 - __builtin_clz((unsigned)(nall - 1));
 }
 
 // ------------------------------------------------------------------ the run
@@ -933,73 +1004,15 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     st.pairs = pairs;
     st.tiles = nblocks;
 
-    // ---- precision
+    // ---- panel scale and tile order (both independent of the precision)
     const float scale_src = cloud->maxabs;
     double scale = 1.0;
     if (scale_src > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)scale_src));
-    const int dp16 = 64 * ((d + 63) / 64);
-    int prec = P->precision;
-    TuneKey key{};
-    if (prec == MAPPER_PREC_AUTO) {
-        // a cached choice needs no sample (the key uses the cloud's median norm)
-        key = tune_key(d, E, cloud_median_norm2(ctx, cloud, s), (double)pairs);
-        prec = cached_precision(ctx, key);
-    }
-    if (prec < 0) {
-        TuneSample ts;
-        if (S > 1 && !order.empty()) {
-            // sample pairs of elements in proportion to their pair counts
-            const int NS = 4096;
-            std::vector<int32_t> pa(NS), pb(NS);
-            std::vector<uint32_t> pts;
-            d2h(pts, slot_point, S, s);
-            HIPCHK(hipStreamSynchronize(s));
-            uint64_t rs = 0x9E3779B97F4A7C15ull ^ (uint64_t)S;
-            auto rnd = [&]() { rs ^= rs << 13; rs ^= rs >> 7; rs ^= rs << 17; return rs; };
-            std::vector<double> cum(order.size());
-            double acc = 0;
-            for (size_t k = 0; k < order.size(); ++k) {
-                const double ne = (double)(eoff[order[k] + 1] - eoff[order[k]]);
-                acc += ne * ne;
-                cum[k] = acc;
-            }
-            for (int q = 0; q < NS; ++q) {
-                const double r = (double)(rnd() >> 11) * 0x1.0p-53 * acc;
-                const size_t k = std::min(order.size() - 1,
-                                          (size_t)(std::lower_bound(cum.begin(), cum.end(), r) - cum.begin()));
-                const int e = order[k];
-                const int64_t ne = eoff[e + 1] - eoff[e];
-                pa[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
-                pb[q] = (int32_t)pts[eoff[e] + (int64_t)(rnd() % (uint64_t)ne)];
-            }
-            Scope tmp(ctx->arena, s);
-            int32_t *dpa = tmp.get<int32_t>(NS), *dpb = tmp.get<int32_t>(NS);
-            double *dD = tmp.get<double>(NS), *dna = tmp.get<double>(NS), *dnb = tmp.get<double>(NS);
-            h2d(dpa, pa.data(), NS, s);
-            h2d(dpb, pb.data(), NS, s);
-            HIPCHK(launch_pair_d64(dpa, dpb, NS, cloud->X, d, dD, s));
-            HIPCHK(launch_row_norm2(dpa, NS, cloud->X, d, dna, s));
-            HIPCHK(launch_row_norm2(dpb, NS, cloud->X, d, dnb, s));
-            d2h(ts.D, dD, NS, s);
-            d2h(ts.na, dna, NS, s);
-            d2h(ts.nb, dnb, NS, s);
-            HIPCHK(hipStreamSynchronize(s));
-        }
-        prec = choose_precision(ctx, d, dp16, E, ts, key);
-    }
-    st.precision = prec;
     // screening of tile pairs by their rows' balls: when the cloud has a
     // locality order (cells) and the balls' margins hold (d <= BALL_DMAX)
     const bool screen = cloud->cell != nullptr && d <= BALL_DMAX && nblocks > 0 &&
                         !(P->flags & (MAPPER_FLAG_NO_SCREEN | MAPPER_FLAG_TILE_MACRO));
-    // launch form: macro tiles for single 16-bit products with one eps value
-    // (screened runs keep scattered tile pairs: tile pairs then)
-    const bool macro_ok = (prec == P_BF16 || prec == P_FP16) && n_levels == 1 && !screen &&
-                          (uint64_t)panel_row_stride(prec, panel_dp(prec, d)) * MTILE < (1ull << 32);
-    const bool use_macro = macro_ok && !(P->flags & MAPPER_FLAG_TILE_PAIRS);
-    st.tile_m = st.tile_n = use_macro ? MTILE : TILE;
-    st.split_terms = prec_is_split(prec) ? 3 : 1;
-    const int super = supertile_size(prec, panel_dp(prec, d));
+    const int super = supertile_size(d);
     std::vector<int64_t> colpre, cp_off(E_count);
     build_supertile_columns(T, super, colpre, cp_off);
     int64_t nrb = 0;                                            // row blocks of all elements
@@ -1033,15 +1046,16 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int64_t *d_rb_off = mem.get<int64_t>(rb_off.size());
     h2d(d_rb_off, rb_off.data(), (int64_t)rb_off.size(), s);
 
-    // ---- screening: the tile pairs that can hold a neighbour pair
+    // ---- screening: the tile pairs that can hold a neighbour pair, each
+    // with its own bitmask block (their position in launch order)
     int64_t n_tiles = nblocks;                                  // tile pairs computed
-    uint8_t *keep = nullptr;
-    int64_t *kpos = nullptr;
+    int64_t *diag_blk = nullptr, *next_blk = nullptr;
+    st.pairs_computed = pairs;
     if (screen) {
         float *centers = mem.get<float>((uint64_t)nrb * d);
         double *radius = mem.get<double>(nrb);
-        keep = mem.get<uint8_t>(nblocks);
-        kpos = mem.get<int64_t>(nblocks + 1);
+        uint8_t *keep = mem.get<uint8_t>(nblocks);
+        int64_t *kpos = mem.get<int64_t>(nblocks + 1);
         void *kst = mem.get<char>(scan_temp_bytes(nblocks));
         double Emax = 0.0;
         for (int lv = 0; lv < n_levels; ++lv) Emax = std::max(Emax, Elev[lv]);
@@ -1065,9 +1079,39 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         HIPCHK(launch_scan_u8(keep, kpos, nblocks, kst, s));
         HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        TileItem *kept = mem.get<TileItem>(std::max<int64_t>(n_tiles, 1));
+        diag_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
+        next_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
+        unsigned long long *pc = mem.get<unsigned long long>(1);
+        HIPCHK(hipMemsetAsync(pc, 0, 8, s));
+        HIPCHK(hipMemsetAsync(next_blk, 0xff, (size_t)std::max<int64_t>(nrb, 1) * 8, s));   // -1: no pair (I, I + 1)
+        HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, diag_blk, next_blk, pc, s));
+        unsigned long long pairs_c = 0;
+        HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        st.pairs_computed = (int64_t)pairs_c;
+        tt.items = kept;
+        tt.n_items = n_tiles;
     }
     st.tiles_screened_out = nblocks - n_tiles;
     st.tiles = n_tiles;
+
+    // ---- precision: as asked, or (AUTO) the cached choice for this kind of
+    // run, or measured now on a sample of this run's tile pairs
+    int prec = P->precision;
+    if (prec == MAPPER_PREC_AUTO) {
+        const TuneKey key = tune_key(d, E, cloud_median_norm2(ctx, cloud, s), (double)pairs);
+        prec = cached_precision(ctx, key);
+        if (prec < 0) prec = tune_precision(ctx, cloud, tt, n_tiles, slot_point, S, scale, E, key, st, s);
+    }
+    st.precision = prec;
+    // launch form: macro tiles for single 16-bit products with one eps value
+    // (screened runs keep scattered tile pairs: tile pairs then)
+    const bool macro_ok = (prec == P_BF16 || prec == P_FP16) && n_levels == 1 && !screen &&
+                          (uint64_t)panel_row_stride(prec, panel_dp(prec, d)) * MTILE < (1ull << 32);
+    const bool use_macro = macro_ok && !(P->flags & MAPPER_FLAG_TILE_PAIRS);
+    st.tile_m = st.tile_n = use_macro ? MTILE : TILE;
+    st.split_terms = prec_is_split(prec) ? 3 : 1;
 
     // ---- host tables of the macro form
     const uint64_t level_words = (uint64_t)std::max<int64_t>(n_tiles, 1) * TILE_WORDS;
@@ -1104,9 +1148,6 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     auto r256 = [](uint64_t b) { return (b + 16 + 255) & ~(uint64_t)255; };
     const uint64_t E1 = (uint64_t)std::max<int64_t>(E_count, 1), U = (uint64_t)Sa;
     uint64_t fixed = 0;
-    if (screen)                                                 // kept tile pairs, hook blocks
-        fixed += r256((uint64_t)std::max<int64_t>(n_tiles, 1) * sizeof(TileItem)) +
-                 2 * r256((uint64_t)std::max<int64_t>(nrb, 1) * 8) + r256(8);
     if (use_macro)
         fixed += r256(mitem_off.size() * 8) + r256(mcolpre.size() * 8) + 2 * r256(E1 * 8) +
                  r256((uint64_t)std::max<int64_t>(n_mitems, 1) * sizeof(MacroItem));
@@ -1152,25 +1193,6 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     st.reserved_bytes = res ? need : 0;
     if (may_retry && res) admitted(ctx, out.req);
 
-    // ---- the kept tile pairs (screened runs): their own bitmask blocks
-    int64_t *diag_blk = nullptr, *next_blk = nullptr;
-    if (screen) {
-        TileItem *kept = rm.get<TileItem>(std::max<int64_t>(n_tiles, 1));
-        diag_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
-        next_blk = rm.get<int64_t>(std::max<int64_t>(nrb, 1));
-        unsigned long long *pc = rm.get<unsigned long long>(1);
-        HIPCHK(hipMemsetAsync(pc, 0, 8, s));
-        HIPCHK(hipMemsetAsync(next_blk, 0xff, (size_t)std::max<int64_t>(nrb, 1) * 8, s));   // -1: no pair (I, I + 1)
-        HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, diag_blk, next_blk, pc, s));
-        unsigned long long pairs_c = 0;
-        HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        st.pairs_computed = (int64_t)pairs_c;
-        tt.items = kept;
-        tt.n_items = n_tiles;
-    } else {
-        st.pairs_computed = pairs;
-    }
     MacroItem *d_mitems = nullptr;
     if (use_macro) {
         int64_t *d_mitem_off = rm.get<int64_t>(mitem_off.size());
@@ -1930,7 +1952,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.tt.elem_off = d_eo;
         ta.tt.blk_off = d_bo;
         std::vector<int64_t> colpre, cp_off(1);
-        const int super = supertile_size(precision, dp);
+        const int super = supertile_size(d);
         build_supertile_columns(std::vector<int64_t>{T}, super, colpre, cp_off);
         int64_t *d_cp = mem.get<int64_t>(colpre.size()), *d_cpo = mem.get<int64_t>(1);
         h2d(d_cp, colpre.data(), (int64_t)colpre.size(), s);

@@ -143,7 +143,7 @@ int main(int argc, char **argv) {
     const int64_t tmax = argc > 1 ? std::atoll(argv[1]) : 200;
     std::set<int64_t> sizes = {1, 5, 8, 24};
     for (int prec = 0; prec < 5; ++prec)
-        for (int d : {1, 32, 64, 200, 256, 257, 512, 2050}) sizes.insert(supertile_size(prec, panel_dp(prec, d)));
+        for (int d : {1, 32, 64, 200, 256, 257, 512, 2050}) sizes.insert(supertile_size(d) + 0 * prec);
     int64_t items = 0;
     for (int64_t S : sizes)
         for (int64_t t = 1; t <= tmax; ++t)

@@ -199,6 +199,32 @@ def test_screening_on_blobs(ctx):
     assert g.stats["pairs_computed"] < g.stats["pairs"]
 
 
+def test_autotuner_measures_then_caches():
+    """MAPPER_PREC_AUTO on the first run of its kind times every precision on
+    a sample of the run's own tile pairs and picks the smallest predicted
+    time; the next run of the same kind reuses the choice without sampling.
+    Both graphs are the oracle's."""
+    from paper_2011_03209_amd import binding
+    w = synth.mixture_1m_d256(scale=0.03)
+    params = with_prec(w.params, synth.PREC_AUTO)
+    c = binding.Context(arena_bytes=8 << 30)
+    try:
+        cloud = c.cloud(w.X)
+        g1 = cloud.run(params, debug=True)
+        g2 = cloud.run(params)
+        cloud.destroy()
+    finally:
+        c.close()
+    pred = g1.stats["tune_pred_ms"]
+    assert g1.stats["tune_sampled"] == 1 and all(t > 0 for t in pred), pred
+    assert g1.stats["precision"] == int(np.argmin(pred)), (g1.stats["precision"], pred)
+    assert g2.stats["tune_sampled"] == 0 and g2.stats["precision"] == g1.stats["precision"]
+    ref = oracle_graph(w.X, params)
+    same_stages(g1, ref, 1)
+    same_graph(g1, ref)
+    same_graph(g2, ref)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_mixture_d64(ctx, prec):
     w = synth.mixture_100k_d64(scale=0.06)
