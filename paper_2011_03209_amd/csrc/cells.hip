@@ -6,13 +6,16 @@
 // of them.  Most pairs of a large element are far apart when the cloud has
 // cluster structure, so the library lays each element's members out in the
 // order of a coarse partition of the cloud (its "cells": the nearest of up
-// to 64 landmarks chosen by farthest-point sampling), and bounds every
-// 128-row tile by a ball (its mean and the largest distance of a member from
-// it).  A tile pair whose balls lie more than eps apart holds no neighbour
-// pair (triangle inequality) and is not computed; so is a tile pair none of
-// whose cells are near each other (each cell bounded by its own ball, the
-// landmark and the largest distance of a member from it).  The partition
-// only orders the work; the graph does not depend on it.
+// to 63 landmarks chosen by farthest-point sampling, plus one cell for
+// outlying points), and bounds every landmark cell by a ball (the landmark
+// and the largest distance of a member from it).  A tile pair none of whose
+// cells are near each other (balls more than eps apart) holds no neighbour
+// pair (triangle inequality) and is not computed.  Bounding each 128-row
+// tile by a ball of its own as well screened no more than 0.1% extra tile
+// pairs on the mixtures measured (members of one cell are in point order
+// within it, so the tiles of one cell overlap), and it cost two more reads
+// of every row, so it is not done.  The partition only orders the work; the
+// graph does not depend on it.
 #include "internal.h"
 
 namespace mgpu {
@@ -77,23 +80,33 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
 }
 
 // out[i] = min over j != i of |x_i - x_j|^2 among the m sample rows (FP32;
-// it only separates isolated rows from rows in dense regions).
-__global__ void k_sample_nn2(const float *__restrict__ sub, int32_t m, int32_t d, float *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+// it only separates isolated rows from rows in dense regions).  One
+// workgroup per row i, its row in LDS; each wave takes every fourth row j,
+// the lanes striding its coordinates (coalesced), a shuffle sum per j.
+__global__ void __launch_bounds__(256) k_sample_nn2(const float *__restrict__ sub, int32_t m, int32_t d,
+                                                    float *__restrict__ out) {
+    __shared__ float xi[CELL_LDS_FLOATS / 8];
+    __shared__ float part[4];
+    const int i = blockIdx.x;
     const float *x = sub + (int64_t)i * d;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) xi[k] = x[k];
+    __syncthreads();
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     float best = 3.0e38f;
-    for (int j = 0; j < m; ++j) {
+    for (int j = w; j < m; j += 4) {
         if (j == i) continue;
         const float *y = sub + (int64_t)j * d;
         float acc = 0.f;
-        for (int k = 0; k < d; ++k) {
-            const float t = x[k] - y[k];
+        for (int k = lane; k < d; k += WAVE) {
+            const float t = xi[k] - y[k];
             acc += t * t;
         }
+        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
         best = acc < best ? acc : best;
     }
-    out[i] = best;
+    if (lane == 0) part[w] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) out[i] = fminf(fminf(part[0], part[1]), fminf(part[2], part[3]));
 }
 
 // r2[c] = max over the points of cell c of |x - l_c|^2 (FP64 sums of
@@ -132,41 +145,25 @@ __device__ __forceinline__ int rb_element(const int64_t *rb_off, int32_t n_elem,
     return lo;
 }
 
-// Ball of each 128-slot row block: center c = the rows' mean, rounded to
-// FP32; radius r >= max over the rows of |x - c| (FP64 sums of exact
-// squares of FP32 differences, square root, then a relative margin of
-// 2^-40, which covers the roundings for d <= BALL_DMAX).  One workgroup
-// (four waves) per row block.
-__global__ void __launch_bounds__(256) k_tile_balls(const float *__restrict__ X, int32_t d,
-                                                    const uint32_t *__restrict__ slot_point,
+// The cells of each 128-slot row block: cmask = the cells of its rows,
+// nmask = the cells near any of them (near[c]: the cells whose balls lie
+// within eps of cell c's ball, c included).  One wave per row block.
+__global__ void __launch_bounds__(256) k_tile_cells(const uint32_t *__restrict__ slot_point,
                                                     const int64_t *__restrict__ elem_off,
-                                                    const int64_t *__restrict__ rb_off, int32_t n_elem,
+                                                    const int64_t *__restrict__ rb_off, int32_t n_elem, int64_t nrb,
                                                     const uint8_t *__restrict__ cell,
                                                     const unsigned long long *__restrict__ near,
-                                                    float *__restrict__ centers, double *__restrict__ radius,
                                                     unsigned long long *__restrict__ cmask,
                                                     unsigned long long *__restrict__ nmask) {
-    __shared__ double part[4];
-    __shared__ unsigned long long cm[4], nm[4];
-    __shared__ float c[BALL_DMAX];
-    const int64_t rb = blockIdx.x;
+    const int64_t rb = block_linear() * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (rb >= nrb) return;                                    // the whole wave leaves together
     const int e = rb_element(rb_off, n_elem, rb);
-    const int64_t I = rb - rb_off[e];
-    const int64_t s0 = elem_off[e] + I * TILE;
+    const int64_t s0 = elem_off[e] + (rb - rb_off[e]) * TILE;
     const int64_t s1 = min(elem_off[e + 1], s0 + (int64_t)TILE);
-    const int rows = (int)(s1 - s0);
-    for (int j = threadIdx.x; j < d; j += blockDim.x) {
-        double acc = 0.0;
-        for (int r = 0; r < rows; ++r) acc += (double)X[(int64_t)slot_point[s0 + r] * d + j];
-        c[j] = (float)(acc / rows);
-        centers[rb * (int64_t)d + j] = c[j];
-    }
-    __syncthreads();
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    // the cells present among the rows, and the cells near any of them
     unsigned long long mc = 0, mn = 0;
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        const int c = cell[slot_point[s0 + r]];
+    for (int64_t r = s0 + lane; r < s1; r += WAVE) {
+        const int c = cell[slot_point[r]];
         mc |= 1ull << c;
         mn |= near[c];
     }
@@ -175,69 +172,23 @@ __global__ void __launch_bounds__(256) k_tile_balls(const float *__restrict__ X,
         mn |= __shfl_xor(mn, o, WAVE);
     }
     if (lane == 0) {
-        cm[w] = mc;
-        nm[w] = mn;
-    }
-    double worst = 0.0;
-    for (int r = w; r < rows; r += 4) {
-        const float *x = X + (int64_t)slot_point[s0 + r] * d;
-        double acc = 0.0;
-        for (int j = lane; j < d; j += WAVE) {
-            const double t = (double)x[j] - (double)c[j];
-            acc += t * t;
-        }
-        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
-        worst = acc > worst ? acc : worst;
-    }
-    if (lane == 0) part[w] = worst;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double m = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
-        radius[rb] = sqrt(m) * (1.0 + 0x1.0p-40);
-        cmask[rb] = cm[0] | cm[1] | cm[2] | cm[3];
-        nmask[rb] = nm[0] | nm[1] | nm[2] | nm[3];
+        cmask[rb] = mc;
+        nmask[rb] = mn;
     }
 }
 
-// keep[i] = 0 when tile pair i provably holds no pair within eps: with the
-// balls (c_I, r_I), (c_J, r_J), every x in I and y in J satisfy
-// |x - y| >= |c_I - c_J| - r_I - r_J (triangle inequality), and the
-// canonical FP64 distance is at least (1 - (d + 1) 2^-53) |x - y|^2.  The
-// center distance is summed in FP64 from exact squares of FP32 differences
-// and shrunk by 2^-40; the test keeps a further relative margin.  One wave
-// per tile pair.
-__global__ void __launch_bounds__(256) k_screen(const TileItem *__restrict__ items, int64_t n,
-                                                const int64_t *__restrict__ rb_off, const float *__restrict__ centers,
-                                                const double *__restrict__ radius,
-                                                const unsigned long long *__restrict__ cmask,
-                                                const unsigned long long *__restrict__ nmask, int32_t d, double E,
-                                                uint8_t *__restrict__ keep) {
-    const int64_t i = block_linear() * 4 + threadIdx.x / WAVE;
-    const int lane = threadIdx.x & (WAVE - 1);
+// keep[i] = 0 when tile pair i provably holds no pair within eps: no cell
+// of row block J is near a cell of row block I, so the cells' balls put
+// every pair of the two blocks farther apart than eps.  Diagonal pairs are
+// always kept.
+__global__ void k_screen(const TileItem *__restrict__ items, int64_t n, const int64_t *__restrict__ rb_off,
+                         const unsigned long long *__restrict__ cmask, const unsigned long long *__restrict__ nmask,
+                         uint8_t *__restrict__ keep) {
+    const int64_t i = block_linear() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const TileItem it = items[i];
-    if (it.I == it.J) {
-        if (lane == 0) keep[i] = 1;
-        return;
-    }
     const int64_t a = rb_off[it.e] + it.I, b = rb_off[it.e] + it.J;
-    // no cell of tile J is near a cell of tile I: every pair is farther
-    // than eps (the cells' own balls prove it)
-    if ((nmask[a] & cmask[b]) == 0) {
-        if (lane == 0) keep[i] = 0;
-        return;
-    }
-    const float *ca = centers + a * (int64_t)d, *cb = centers + b * (int64_t)d;
-    double acc = 0.0;
-    for (int j = lane; j < d; j += WAVE) {
-        const double t = (double)ca[j] - (double)cb[j];
-        acc += t * t;
-    }
-    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
-    if (lane != 0) return;
-    const double gap = sqrt(acc) * (1.0 - 0x1.0p-40) - radius[a] - radius[b];
-    const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
-    keep[i] = (gap > 0.0 && gap * gap * shrink > E * (1.0 + 0x1.0p-40)) ? 0 : 1;
+    keep[i] = (it.I == it.J || (nmask[a] & cmask[b]) != 0) ? 1 : 0;
 }
 
 // The kept tile pairs, in their launch order, each with its own bitmask
@@ -284,24 +235,19 @@ hipError_t launch_sample_items(const TileItem *items, int64_t n, int64_t m, Tile
     return hipGetLastError();
 }
 
-hipError_t launch_tile_balls(const float *X, int32_t d, const uint32_t *slot_point, const int64_t *elem_off,
-                             const int64_t *rb_off, int32_t n_elem, int64_t nrb, const uint8_t *cell,
-                             const unsigned long long *near, float *centers, double *radius,
+hipError_t launch_tile_cells(const uint32_t *slot_point, const int64_t *elem_off, const int64_t *rb_off,
+                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const unsigned long long *near,
                              unsigned long long *cmask, unsigned long long *nmask, hipStream_t s) {
     if (nrb <= 0) return hipSuccess;
-    if (nrb > 0x7fffffff || d > BALL_DMAX) return hipErrorInvalidValue;
-    k_tile_balls<<<dim3((unsigned)nrb), dim3(256), 0, s>>>(X, d, slot_point, elem_off, rb_off, n_elem, cell, near,
-                                                            centers, radius, cmask, nmask);
+    k_tile_cells<<<grid_2d((nrb + 3) / 4), dim3(256), 0, s>>>(slot_point, elem_off, rb_off, n_elem, nrb, cell, near,
+                                                               cmask, nmask);
     return hipGetLastError();
 }
 
-hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const float *centers,
-                         const double *radius, const unsigned long long *cmask, const unsigned long long *nmask,
-                         int32_t d, double E, uint8_t *keep, hipStream_t s) {
+hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const unsigned long long *cmask,
+                         const unsigned long long *nmask, uint8_t *keep, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (d > BALL_DMAX) return hipErrorInvalidValue;
-    k_screen<<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(items, n, rb_off, centers, radius, cmask, nmask, d, E,
-                                                         keep);
+    k_screen<<<grid_2d((n + 255) / 256), dim3(256), 0, s>>>(items, n, rb_off, cmask, nmask, keep);
     return hipGetLastError();
 }
 
@@ -324,7 +270,8 @@ hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float
 
 hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    k_sample_nn2<<<dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s>>>(sub, m, d, out);
+    if (d > CELL_LDS_FLOATS / 8) return hipErrorInvalidValue;
+    k_sample_nn2<<<dim3((unsigned)m), dim3(256), 0, s>>>(sub, m, d, out);
     return hipGetLastError();
 }
 

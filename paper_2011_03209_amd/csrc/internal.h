@@ -318,20 +318,18 @@ hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out,
 hipError_t launch_sample_items(const TileItem *items, int64_t n, int64_t m, TileItem *out, hipStream_t s);
 // keys[i] >>= shift
 hipError_t launch_shift_keys(uint64_t *keys, int64_t n, int shift, hipStream_t s);
-// Ball (FP32 center, FP64 radius bound) of each of the nrb row blocks
-// (d <= BALL_DMAX: the margins of the bound assume it).
+// The margins of the cell balls' bounds assume d <= BALL_DMAX.
 constexpr int BALL_DMAX = 2048;
-// Also per row block: cmask = its rows' cells, nmask = the cells near any of
-// them (near: the table of cells that eps may join, one 64-bit mask per cell).
-hipError_t launch_tile_balls(const float *X, int32_t d, const uint32_t *slot_point, const int64_t *elem_off,
-                             const int64_t *rb_off, int32_t n_elem, int64_t nrb, const uint8_t *cell,
-                             const unsigned long long *near, float *centers, double *radius,
+// Per row block (nrb of them, numbered by rb_off): cmask = its rows' cells,
+// nmask = the cells near any of them (near: the table of cells that eps may
+// join, one 64-bit mask per cell).
+hipError_t launch_tile_cells(const uint32_t *slot_point, const int64_t *elem_off, const int64_t *rb_off,
+                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const unsigned long long *near,
                              unsigned long long *cmask, unsigned long long *nmask, hipStream_t s);
-// keep[i] = 0 if the balls of tile pair i lie more than sqrt(E) apart, or
-// no cell of one side is near a cell of the other.
-hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const float *centers,
-                         const double *radius, const unsigned long long *cmask, const unsigned long long *nmask,
-                         int32_t d, double E, uint8_t *keep, hipStream_t s);
+// keep[i] = 0 if no cell of tile pair i's column block is near a cell of its
+// row block (diagonal pairs are kept).
+hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const unsigned long long *cmask,
+                         const unsigned long long *nmask, uint8_t *keep, hipStream_t s);
 // r2[c] = max |x - land_c|^2 over the points of cell c (double bits; r2
 // zeroed by the caller).
 hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,

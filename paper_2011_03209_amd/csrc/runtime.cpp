@@ -1008,8 +1008,8 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     const float scale_src = cloud->maxabs;
     double scale = 1.0;
     if (scale_src > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)scale_src));
-    // screening of tile pairs by their rows' balls: when the cloud has a
-    // locality order (cells) and the balls' margins hold (d <= BALL_DMAX)
+    // screening of tile pairs by their rows' cells: when the cloud has a
+    // locality order (cells) and the cell balls' margins hold (d <= BALL_DMAX)
     const bool screen = cloud->cell != nullptr && d <= BALL_DMAX && nblocks > 0 &&
                         !(P->flags & (MAPPER_FLAG_NO_SCREEN | MAPPER_FLAG_TILE_MACRO));
     const int super = supertile_size(d);
@@ -1052,15 +1052,15 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int64_t *diag_blk = nullptr, *next_blk = nullptr;
     st.pairs_computed = pairs;
     if (screen) {
-        float *centers = mem.get<float>((uint64_t)nrb * d);
-        double *radius = mem.get<double>(nrb);
         uint8_t *keep = mem.get<uint8_t>(nblocks);
         int64_t *kpos = mem.get<int64_t>(nblocks + 1);
         void *kst = mem.get<char>(scan_temp_bytes(nblocks));
         double Emax = 0.0;
         for (int lv = 0; lv < n_levels; ++lv) Emax = std::max(Emax, Elev[lv]);
         // cells eps may join: all but the pairs whose balls' gap g satisfies
-        // g^2 (1 - (d + 8) 2^-52) > E (1 + 2^-40), the bound k_screen uses
+        // g^2 (1 - (d + 8) 2^-52) > E (1 + 2^-40): the canonical FP64
+        // distance of two points is at least (1 - (d + 1) 2^-53) times
+        // their exact squared distance, which the gap bounds from below
         const int nc = cloud->ncell;
         std::vector<unsigned long long> nearh((size_t)CELL_MAX, 0);
         const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
@@ -1073,9 +1073,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         unsigned long long *near = mem.get<unsigned long long>(CELL_MAX);
         unsigned long long *cmask = mem.get<unsigned long long>(nrb), *nmask = mem.get<unsigned long long>(nrb);
         h2d(near, nearh.data(), CELL_MAX, s);
-        HIPCHK(launch_tile_balls(cloud->X, d, slot_point, elem_off, d_rb_off, (int32_t)E_count, nrb, cloud->cell,
-                                 near, centers, radius, cmask, nmask, s));
-        HIPCHK(launch_screen(d_items, nblocks, d_rb_off, centers, radius, cmask, nmask, d, Emax, keep, s));
+        HIPCHK(launch_tile_cells(slot_point, elem_off, d_rb_off, (int32_t)E_count, nrb, cloud->cell, near, cmask,
+                                 nmask, s));
+        HIPCHK(launch_screen(d_items, nblocks, d_rb_off, cmask, nmask, keep, s));
         HIPCHK(launch_scan_u8(keep, kpos, nblocks, kst, s));
         HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -161,8 +161,9 @@ def test_macro_tiles(ctx, prec, d):
 
 @pytest.mark.parametrize("prec", [synth.PREC_FP32, synth.PREC_BF16X3, synth.PREC_FP16])
 def test_screening_exact_at_eps(ctx, prec):
-    """Tile pairs are skipped only when their balls prove them empty.  Groups
-    of 300 identical points (balls of radius 0) on the first axis at 0, 2,
+    """Tile pairs are skipped only when their cells' balls prove them empty.
+    Groups of 300 identical points (four cells, balls of radius 0) on the
+    first axis at 0, 2,
     4 + 2^-20 and 100 with eps = 2: the first two are exactly eps apart
     (D = eps^2, neighbours, one cluster), the third lies just beyond eps of
     the second (its own cluster), the fourth is far (its tile pairs are
