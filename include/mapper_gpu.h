@@ -131,10 +131,11 @@ typedef struct {
  * ignored otherwise. */
 #define MAPPER_FLAG_TILE_PAIRS 2u
 #define MAPPER_FLAG_TILE_MACRO 4u
-/* Compute every tile pair of every element.  By default a tile pair whose
- * rows' bounding balls lie more than eps apart is proven to hold no
- * neighbour pair and skipped (clouds of at least 1024 points and d <= 2048,
- * whose members are laid out in a locality order); the graph is the same. */
+/* Compute every tile pair of every element.  By default a tile pair none of
+ * whose rows' landmark cells lies within eps of a cell of its columns (each
+ * cell bounded by a ball) is proven to hold no neighbour pair and skipped
+ * (clouds of at least 1024 points and d <= 2048, whose members are laid out
+ * by cell); the graph is the same. */
 #define MAPPER_FLAG_NO_SCREEN 8u
 
 typedef struct mapper_context mapper_context;
