@@ -146,9 +146,10 @@ __device__ __forceinline__ float round_dn_f(double v) {
 }
 
 // Sixteen lanes per slot (four slots per wave): lane `sub` of a slot handles
-// coordinates j = sub, sub + 16, ..., so its loads and the split rows' stores
-// are contiguous runs per slot, and each cross-lane step of the FP64 sums
-// serves four slots at once.
+// coordinates 4 sub .. 4 sub + 3, then 64 further on, and so on, so a slot's
+// loads and its panel stores are contiguous 256-byte runs (one 16-byte load
+// and one 8- or 16-byte store per lane), and each cross-lane step of the
+// FP64 sums serves four slots at once.
 constexpr int PK_LANES = 16;
 
 __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
@@ -161,32 +162,52 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
     const float *x = a.X + (int64_t)a.slot_point[sl] * a.d;
     const bool split = a.prec == P_BF16X3 || a.prec == P_FP16X3;
     const bool bf = a.prec == P_BF16 || a.prec == P_BF16X3;
+    const bool vec = (a.d & 3) == 0;                       // rows start 16-byte aligned
+    char *row = (char *)a.panel + s * panel_row_stride(a.prec, a.dp);
     double nx = 0, hh = 0, ll = 0, xt = 0, rr = 0;
-    for (int j = sub; j < a.dp; j += PK_LANES) {
-        const float xs = j < a.d ? (float)((double)x[j] * a.scale) : 0.0f;   // exact power-of-two scaling
-        const double xd = (double)xs;
-        nx += xd * xd;
+    for (int j0 = 4 * sub; j0 < a.dp; j0 += 4 * PK_LANES) {   // dp is a multiple of 32
+        float v[4];
+        if (vec && j0 + 4 <= a.d) {
+            const float4 q = *(const float4 *)(x + j0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = j0 + q < a.d ? x[j0 + q] : 0.0f;
+        }
+        float xs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xs[q] = (float)((double)v[q] * a.scale);        // exact power-of-two scaling
+            nx += (double)xs[q] * (double)xs[q];
+        }
         if (a.prec == P_FP32) {
-            if (live) ((float *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp)))[j] = xs;
+            if (live) *(float4 *)(row + (int64_t)j0 * 4) = make_float4(xs[0], xs[1], xs[2], xs[3]);
             continue;
         }
-        uint16_t hb, lb = 0;
-        const float h = bf ? bf16_round(xs, &hb) : fp16_round(xs, &hb);
-        // split rows interleave 16 hi and 16 lo values per group of 16 coordinates
-        uint16_t *row16 = (uint16_t *)((char *)a.panel + s * panel_row_stride(a.prec, a.dp));
-        const int64_t at = split ? (int64_t)(j >> 4) * 32 + (j & 15) : j;
-        if (live) row16[at] = hb;
-        double lo = 0.0;
-        if (split) {
-            const float rem = xs - h;            // exact in FP32
-            lo = (double)(bf ? bf16_round(rem, &lb) : fp16_round(rem, &lb));
-            if (live) row16[at + 16] = lb;
+        uint16_t hb[4], lb[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float h = bf ? bf16_round(xs[q], &hb[q]) : fp16_round(xs[q], &hb[q]);
+            double lo = 0.0;
+            if (split) {
+                const float rem = xs[q] - h;                 // exact in FP32
+                lo = (double)(bf ? bf16_round(rem, &lb[q]) : fp16_round(rem, &lb[q]));
+            }
+            const double hd = (double)h, r = (double)xs[q] - hd - lo;   // exact in FP64
+            hh += hd * hd;
+            ll += lo * lo;
+            xt += (hd + lo) * (hd + lo);
+            rr += r * r;
         }
-        const double hd = (double)h, r = xd - hd - lo;   // exact in FP64
-        hh += hd * hd;
-        ll += lo * lo;
-        xt += (hd + lo) * (hd + lo);
-        rr += r * r;
+        // split rows interleave 16 hi and 16 lo values per group of 16 coordinates
+        const int64_t at = split ? (int64_t)(j0 >> 4) * 32 + (j0 & 15) : j0;
+        if (live) {
+            uint16_t *row16 = (uint16_t *)row;
+            *(uint2 *)(row16 + at) = make_uint2(hb[0] | ((uint32_t)hb[1] << 16), hb[2] | ((uint32_t)hb[3] << 16));
+            if (split)
+                *(uint2 *)(row16 + at + 16) =
+                    make_uint2(lb[0] | ((uint32_t)lb[1] << 16), lb[2] | ((uint32_t)lb[3] << 16));
+        }
     }
 #pragma unroll
     for (int o = PK_LANES / 2; o > 0; o >>= 1) {            // within each slot's 16 lanes

@@ -581,13 +581,21 @@ __global__ void k_run_starts(const uint64_t *k, int64_t m, uint8_t *flag) {
     if (i < m) flag[i] = (i == 0 || k[i - 1] != k[i]);
 }
 
+// Run r of the sorted edge keys starts at i (rank[i] = r, the exclusive scan
+// of the run-start flags, m + 1 entries) and ends where run r + 1 starts:
+// the first j > i with rank[j] = r + 2 is one past that start (or m when r
+// is the last run).  A binary search, so a heavy edge costs no long walk.
 __global__ void k_edge_compact(const uint64_t *k, int64_t m, const int64_t *rank, int64_t nn,
                                int32_t *edges, int32_t *weights) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m || (i > 0 && k[i - 1] == k[i])) return;
-    int64_t e = i + 1;
-    while (e < m && k[e] == k[i]) ++e;
     const int64_t r = rank[i];
+    int64_t lo = i + 1, hi = m + 1;             // first j in [i + 1, m] with rank[j] >= r + 2, else m + 1
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (rank[mid] >= r + 2) hi = mid; else lo = mid + 1;
+    }
+    const int64_t e = lo - 1;
     edges[2 * r] = (int32_t)(k[i] / (uint64_t)nn);
     edges[2 * r + 1] = (int32_t)(k[i] % (uint64_t)nn);
     weights[r] = (int32_t)(e - i);

@@ -110,7 +110,10 @@ __device__ __forceinline__ unsigned long long dkey(double x) {
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// One atomic pair per workgroup (the waves' results meet in LDS first): the
+// two words are shared by the whole launch.
 __global__ void __launch_bounds__(256) k_range(const double *f, int64_t n, unsigned long long *keys2) {
+    __shared__ unsigned long long wmn[4], wmx[4];
     unsigned long long mn = ~0ull, mx = 0ull;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -124,7 +127,17 @@ __global__ void __launch_bounds__(256) k_range(const double *f, int64_t n, unsig
         mn = a < mn ? a : mn;
         mx = b > mx ? b : mx;
     }
+    const int w = threadIdx.x / WAVE;
     if ((threadIdx.x & (WAVE - 1)) == 0) {
+        wmn[w] = mn;
+        wmx[w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x / WAVE); ++v) {
+            mn = wmn[v] < mn ? wmn[v] : mn;
+            mx = wmx[v] > mx ? wmx[v] : mx;
+        }
         atomicMin(&keys2[0], mn);
         atomicMax(&keys2[1], mx);
     }
@@ -199,7 +212,7 @@ hipError_t launch_lens(const float *X, int64_t n, int32_t d, int kind, int32_t c
 
 hipError_t launch_range(const double *f, int64_t n, unsigned long long *keys2, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     k_range<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(f, n, keys2);
     return hipGetLastError();

@@ -1077,9 +1077,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
                                  nmask, s));
         HIPCHK(launch_screen(d_items, nblocks, d_rb_off, cmask, nmask, keep, s));
         HIPCHK(launch_scan_u8(keep, kpos, nblocks, kst, s));
-        HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        TileItem *kept = mem.get<TileItem>(std::max<int64_t>(n_tiles, 1));
+        TileItem *kept = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));   // room for all: one read below
         diag_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
         next_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
         unsigned long long *pc = mem.get<unsigned long long>(1);
@@ -1087,6 +1085,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         HIPCHK(hipMemsetAsync(next_blk, 0xff, (size_t)std::max<int64_t>(nrb, 1) * 8, s));   // -1: no pair (I, I + 1)
         HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, diag_blk, next_blk, pc, s));
         unsigned long long pairs_c = 0;
+        HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         st.pairs_computed = (int64_t)pairs_c;
