@@ -59,14 +59,14 @@ def time_path(cloud, params, steps: int, warmup: int, flags: int = 0):
     return g, times, stats
 
 
-def recorded_traffic(precision: str):
+def recorded_traffic(workload: str, precision: str):
     """HBM bytes per launch of the tile kernel from the committed rocprofv3
     counter record (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
     calibration), or None when the record is missing or was taken from
     another version of the kernel source (tile.hip, and internal.h, which
     holds the tile order and the panel layout)."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", f"mapper_mix1m_d256_{precision}.txt")
+    rec = os.path.join(ROOT, "profiles", f"mapper_{workload}_{precision}.txt")
     csrc = os.path.join(ROOT, "paper_2011_03209_amd", "csrc")
     srcs = [os.path.join(csrc, "tile.hip"), os.path.join(csrc, "internal.h")]
     if not (os.path.exists(rec) and all(os.path.exists(s) for s in srcs)):
@@ -277,6 +277,21 @@ def main():
         out["fp32_path"] = {"s_per_graph": float(np.median(t32)), "ms_tiles": float(np.median([s["ms_tiles"] for s in s32])),
                             "band_pairs": int(s32[-1]["band_pairs"]), "graph_identical": bool(same)}
         print(f"[bench] fp32: {np.median(t32):.4f} s/graph, identical={same}", file=sys.stderr, flush=True)
+    if not args.no_fp32 and prec != 5:
+        # the precision the library's own autotuner picks for this run (its
+        # first run samples the five precisions; the timed runs reuse it)
+        import copy
+        pa = copy.copy(w.params)
+        pa.precision = 5
+        ga, ta, sa = time_path(cloud, pa, max(1, min(args.steps, 3)), 1)
+        same = (np.array_equal(g.node_offsets, ga.node_offsets) and np.array_equal(g.node_members, ga.node_members)
+                and np.array_equal(g.edges, ga.edges) and np.array_equal(g.edge_weights, ga.edge_weights)
+                and np.array_equal(g.node_element, ga.node_element))
+        out["auto_path"] = {"s_per_graph": float(np.median(ta)), "precision": PREC_NAME.get(sa[-1]["precision"]),
+                            "ms_tiles": float(np.median([s["ms_tiles"] for s in sa])),
+                            "band_pairs": int(sa[-1]["band_pairs"]), "graph_identical": bool(same)}
+        print(f"[bench] auto ({out['auto_path']['precision']}): {np.median(ta):.4f} s/graph, identical={same}",
+              file=sys.stderr, flush=True)
     cloud.destroy()
     st = stats[-1]
     used = PREC_NAME.get(st["precision"], "fp32")
@@ -307,8 +322,8 @@ def main():
                    "overlap": [a.overlap for a in w.params.axes], "eps": w.params.eps,
                    "min_pts": w.params.min_pts, "precision": used},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[used] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[used], "traffic": recorded_traffic(used),
-                     "traffic_source": (f"profiles/mapper_mix1m_d256_{used}.txt: rocprofv3 --pmc FETCH_SIZE, "
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[used], "traffic": recorded_traffic(w.name, used),
+                     "traffic_source": (f"profiles/mapper_{w.name}_{used}.txt: rocprofv3 --pmc FETCH_SIZE, "
                                         "WRITE_SIZE of this kernel source (matched by its SHA-256), scaled by "
                                         "a 1 GiB copy; recorded, not measured in this run"),
                      "kernel": f"k_tiles<{used}>", "ms_per_launch": ms_tiles,

@@ -82,16 +82,16 @@ __global__ void k_member_count(const double *f0, const double *f1, int64_t n,
 }
 
 __global__ void k_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals) {
+                              int two_d, const uint16_t *okey, int key_bits, uint64_t *keys, uint32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t p = pos[i];
     const int kl0 = range4[4 * i], kh0 = range4[4 * i + 1];
     const int kl1 = two_d ? range4[4 * i + 2] : 0, kh1 = two_d ? range4[4 * i + 3] : 0;
-    const uint64_t c = cell ? (uint64_t)cell[i] : 0;
+    const uint64_t c = okey ? (uint64_t)okey[i] : 0;
     for (int k0 = kl0; k0 <= kh0; ++k0)
         for (int k1 = kl1; k1 <= kh1; ++k1) {
-            keys[p] = ((uint64_t)((int64_t)k0 * (two_d ? n1 : 1) + k1) << cell_bits) | c;
+            keys[p] = ((uint64_t)((int64_t)k0 * (two_d ? n1 : 1) + k1) << key_bits) | c;
             vals[p] = (uint32_t)i;
             ++p;
         }
@@ -261,10 +261,10 @@ hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
 }
 
 hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals,
+                              int two_d, const uint16_t *okey, int key_bits, uint64_t *keys, uint32_t *vals,
                               hipStream_t s) {
     k_member_emit<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(range4, pos, n, n1, two_d,
-                                                                         cell, cell_bits, keys, vals);
+                                                                         okey, key_bits, keys, vals);
     return hipGetLastError();
 }
 

@@ -127,6 +127,43 @@ __global__ void k_cell_radius(const float *__restrict__ X, int64_t n, int32_t d,
     atomicMax(&r2[c], (unsigned long long)__double_as_longlong(acc));
 }
 
+// gap[i] <= min over the landmark cells c of |x_i - l_c| - r_c for a point
+// of the outlier cell (FP64 sums of exact squares of FP32 differences,
+// square root shrunk by 2^-40, rounded down to FP32): every point of every
+// landmark cell lies at least gap[i] from x_i (triangle inequality).  -1 for
+// the other points.  One wave per point.
+__global__ void __launch_bounds__(256) k_outlier_gap(const float *__restrict__ X, int64_t n, int32_t d,
+                                                     const float *__restrict__ land, int32_t ncell,
+                                                     const double *__restrict__ rad,
+                                                     const uint8_t *__restrict__ cell, float *__restrict__ gap) {
+    const int64_t i = block_linear() * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= n) return;                                      // the whole wave leaves together
+    if (cell[i] != ncell) {
+        if (lane == 0) gap[i] = -1.0f;
+        return;
+    }
+    const float *x = X + i * (int64_t)d;
+    double best = 1e300;
+    for (int c = 0; c < ncell; ++c) {
+        const float *l = land + (int64_t)c * d;
+        double acc = 0.0;
+        for (int j = lane; j < d; j += WAVE) {
+            const double t = (double)x[j] - (double)l[j];
+            acc += t * t;
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+        const double g = sqrt(acc) * (1.0 - 0x1.0p-40) - rad[c];
+        best = g < best ? g : best;
+    }
+    if (lane == 0) {
+        float f = (float)best;                               // round down
+        if ((double)f > best) f = __uint_as_float(f > 0.0f ? __float_as_uint(f) - 1u
+                                                 : f == 0.0f ? 0x80000001u : __float_as_uint(f) + 1u);
+        gap[i] = f;
+    }
+}
+
 // keys[s] >>= shift (the element id of each slot after the sort by
 // (element, cell)).
 __global__ void k_shift_keys(uint64_t *keys, int64_t n, int shift) {
@@ -147,11 +184,16 @@ __device__ __forceinline__ int rb_element(const int64_t *rb_off, int32_t n_elem,
 
 // The cells of each 128-slot row block: cmask = the cells of its rows,
 // nmask = the cells near any of them (near[c]: the cells whose balls lie
-// within eps of cell c's ball, c included).  One wave per row block.
+// within eps of cell c's ball, c included).  A point of the outlier cell
+// whose gap to every landmark cell exceeds eps (the same bound as between
+// two cells) counts as cell outlier + 1, which is near outliers only.  One
+// wave per row block.
 __global__ void __launch_bounds__(256) k_tile_cells(const uint32_t *__restrict__ slot_point,
                                                     const int64_t *__restrict__ elem_off,
                                                     const int64_t *__restrict__ rb_off, int32_t n_elem, int64_t nrb,
                                                     const uint8_t *__restrict__ cell,
+                                                    const float *__restrict__ ogap, int32_t outlier,
+                                                    double shrink, double Eb,
                                                     const unsigned long long *__restrict__ near,
                                                     unsigned long long *__restrict__ cmask,
                                                     unsigned long long *__restrict__ nmask) {
@@ -163,7 +205,12 @@ __global__ void __launch_bounds__(256) k_tile_cells(const uint32_t *__restrict__
     const int64_t s1 = min(elem_off[e + 1], s0 + (int64_t)TILE);
     unsigned long long mc = 0, mn = 0;
     for (int64_t r = s0 + lane; r < s1; r += WAVE) {
-        const int c = cell[slot_point[r]];
+        const uint32_t p = slot_point[r];
+        int c = cell[p];
+        if (c == outlier && ogap) {                            // farther than eps from every landmark cell
+            const double g = (double)ogap[p];
+            if (g > 0.0 && g * g * shrink > Eb) c = outlier + 1;
+        }
         mc |= 1ull << c;
         mn |= near[c];
     }
@@ -236,11 +283,21 @@ hipError_t launch_sample_items(const TileItem *items, int64_t n, int64_t m, Tile
 }
 
 hipError_t launch_tile_cells(const uint32_t *slot_point, const int64_t *elem_off, const int64_t *rb_off,
-                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const unsigned long long *near,
-                             unsigned long long *cmask, unsigned long long *nmask, hipStream_t s) {
+                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const float *ogap, int32_t outlier,
+                             double shrink, double Eb, const unsigned long long *near, unsigned long long *cmask,
+                             unsigned long long *nmask, hipStream_t s) {
     if (nrb <= 0) return hipSuccess;
-    k_tile_cells<<<grid_2d((nrb + 3) / 4), dim3(256), 0, s>>>(slot_point, elem_off, rb_off, n_elem, nrb, cell, near,
-                                                               cmask, nmask);
+    if (outlier < 0 || outlier + 1 >= CELL_MAX) return hipErrorInvalidValue;
+    k_tile_cells<<<grid_2d((nrb + 3) / 4), dim3(256), 0, s>>>(slot_point, elem_off, rb_off, n_elem, nrb, cell, ogap,
+                                                               outlier, shrink, Eb, near, cmask, nmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_outlier_gap(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
+                              const double *rad, const uint8_t *cell, float *gap, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (ncell < 1 || ncell >= CELL_MAX) return hipErrorInvalidValue;
+    k_outlier_gap<<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(X, n, d, land, ncell, rad, cell, gap);
     return hipGetLastError();
 }
 
@@ -263,7 +320,7 @@ hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t 
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
                                const float *limit2, uint8_t *cell, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (ncell < 1 || ncell >= CELL_MAX || (int64_t)ncell * d > CELL_LDS_FLOATS) return hipErrorInvalidValue;
+    if (ncell < 1 || ncell + 1 >= CELL_MAX || (int64_t)ncell * d > CELL_LDS_FLOATS) return hipErrorInvalidValue;
     k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, land, ncell, limit2, cell);
     return hipGetLastError();
 }

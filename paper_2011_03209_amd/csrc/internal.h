@@ -256,9 +256,9 @@ hipError_t launch_member_count(const double *f0, const double *f1, int64_t n,
                                const double *lo1, const double *hc1, int32_t n1,
                                int32_t *range4, int32_t *count, unsigned long long *pair_sum,
                                hipStream_t s);
-// keys = element id << cell_bits | cell[point] (cell may be null: 0)
+// keys = element id << key_bits | okey[point] (okey may be null: 0)
 hipError_t launch_member_emit(const int32_t *range4, const int64_t *pos, int64_t n, int32_t n1,
-                              int two_d, const uint8_t *cell, int cell_bits, uint64_t *keys, uint32_t *vals,
+                              int two_d, const uint16_t *okey, int key_bits, uint64_t *keys, uint32_t *vals,
                               hipStream_t s);
 // Packed panel rows.  A row holds dp coordinates: FP32 values (4 bytes), one
 // 16-bit value each (BF16, FP16), or for the hi/lo splits groups of 16 hi
@@ -303,12 +303,14 @@ struct PackArgs {
 };
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 
-// cells.hip: landmark cells of a cloud (at most CELL_MAX landmarks, staged
-// whole in LDS: ncell * d <= CELL_LDS_FLOATS)
+// cells.hip: landmark cells of a cloud (at most CELL_MAX - 2 landmarks,
+// staged whole in LDS: ncell * d <= CELL_LDS_FLOATS).  Cell ids fit a 64-bit
+// mask: the landmarks 0 .. ncell - 1, the outlier cell ncell, and at run
+// time ncell + 1 for outliers farther than eps from every landmark cell.
 constexpr int CELL_MAX = 64;
 constexpr int CELL_LDS_FLOATS = 16384;
 // cell[i] = nearest landmark, or ncell (the outlier cell) past limit2[c]
-// (squared distance); ncell < CELL_MAX.
+// (squared distance); ncell + 1 < CELL_MAX.
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
                                const float *limit2, uint8_t *cell, hipStream_t s);
 // out[i] = squared distance from sample row i to its nearest other row.
@@ -323,9 +325,17 @@ constexpr int BALL_DMAX = 2048;
 // Per row block (nrb of them, numbered by rb_off): cmask = its rows' cells,
 // nmask = the cells near any of them (near: the table of cells that eps may
 // join, one 64-bit mask per cell).
+// A point of cell `outlier` whose ogap (null: none) passes the eps test
+// g^2 shrink > Eb counts as cell outlier + 1.
 hipError_t launch_tile_cells(const uint32_t *slot_point, const int64_t *elem_off, const int64_t *rb_off,
-                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const unsigned long long *near,
-                             unsigned long long *cmask, unsigned long long *nmask, hipStream_t s);
+                             int32_t n_elem, int64_t nrb, const uint8_t *cell, const float *ogap, int32_t outlier,
+                             double shrink, double Eb, const unsigned long long *near, unsigned long long *cmask,
+                             unsigned long long *nmask, hipStream_t s);
+// gap[i] = a lower bound of the distance from point i of the outlier cell
+// (id ncell) to every point of the landmark cells (landmarks land, radius
+// bounds rad), rounded down to FP32; -1 for the points of landmark cells.
+hipError_t launch_outlier_gap(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
+                              const double *rad, const uint8_t *cell, float *gap, hipStream_t s);
 // keep[i] = 0 if no cell of tile pair i's column block is near a cell of its
 // row block (diagonal pairs are kept).
 hipError_t launch_screen(const TileItem *items, int64_t n, const int64_t *rb_off, const unsigned long long *cmask,

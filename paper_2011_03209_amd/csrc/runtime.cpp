@@ -288,7 +288,9 @@ struct mapper_cloud {
     int32_t d = 0;
     float maxabs = 0.f;
     uint8_t *cell = nullptr;           // landmark cell of each point (locality order), or null
-    int32_t cell_bits = 0;             // bits of a cell id in the binning key
+    float *ogap = nullptr;             // per point of the outlier cell: distance bound to every landmark cell
+    uint16_t *okey = nullptr;          // per point: cell << 8 | rank of its outlier gap (the slot order key)
+    int32_t cell_bits = 0;             // bits of okey in the binning key
     int32_t ncell = 0;
     std::vector<double> cell_gap;      // ncell x ncell: lower bound of the distance between two cells' points
                                        // before eps (landmark distance - both radii), FP64
@@ -707,7 +709,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
 void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     const int64_t n = c->n;
     const int32_t d = c->d;
-    const int ncell_max = std::min<int>(CELL_MAX - 1, CELL_LDS_FLOATS / std::max(d, 1));
+    const int ncell_max = std::min<int>(CELL_MAX - 2, CELL_LDS_FLOATS / std::max(d, 1));
     if (n < 8 * TILE || ncell_max < 8) return;
     const int64_t m = std::min<int64_t>(n, 4096), step = n / m;
     std::vector<float> sub((size_t)(m * d));
@@ -812,12 +814,11 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         ctx->arena.release(r2);
         throw;
     }
-    ctx->arena.release(dl);
-    ctx->arena.release(r2);
     // cell balls: landmark l_c, radius r_c >= max |x - l_c| over its points
     // (relative margin 2^-40 for the FP64 sums, d <= BALL_DMAX); the gap of
     // two cells bounds every distance between their points from below.  Cell
-    // nc (the outliers) has no ball: a gap of -1 keeps it near every cell.
+    // nc (the outliers) has no ball: a gap of -1 keeps it near every cell;
+    // each of its points gets its own gap to the landmark cells instead.
     const int nall = nc + 1;
     std::vector<double> rad((size_t)nc);
     for (int a = 0; a < nc; ++a) {
@@ -825,6 +826,24 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         std::memcpy(&r2v, &r2h[(size_t)a], 8);
         rad[(size_t)a] = std::sqrt(r2v) * (1.0 + 0x1.0p-40);
     }
+    float *ogap = (float *)ctx->arena.alloc((uint64_t)n * 4);
+    if (ogap) {                                                 // no room: every outlier stays near every cell
+        try {
+            double *drad = (double *)r2;                            // the radius scratch, reused
+            HIPCHK(hipMemcpyAsync(drad, rad.data(), (size_t)nc * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(launch_outlier_gap(c->X, n, d, dl, nc, drad, cell, ogap, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } catch (DevError &) {
+            (void)hipStreamSynchronize(s);
+            ctx->arena.release(ogap);
+            ctx->arena.release(cell);
+            ctx->arena.release(dl);
+            ctx->arena.release(r2);
+            throw;
+        }
+    }
+    ctx->arena.release(dl);
+    ctx->arena.release(r2);
     c->cell_gap.assign((size_t)nall * nall, -1.0);
     for (int a = 0; a < nc; ++a)
         for (int b = 0; b < nc; ++b)
@@ -832,9 +851,53 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
                 c->cell_gap[(size_t)a * nall + b] =
                     std::sqrt(dist2(chain[(size_t)a], chain[(size_t)b])) * (1.0 - 0x1.0p-40) - rad[(size_t)a] -
                     rad[(size_t)b];
+    // the slot order key: cell, then (outliers) the gap in 256 quantiles
+    // ascending, so that for any eps the outliers within eps of a landmark
+    // cell come first in their element and the far ones fill row blocks of
+    // their own
+    uint16_t *okey = (uint16_t *)ctx->arena.alloc((uint64_t)n * 2);
+    if (okey) {
+        std::vector<uint8_t> ch;
+        std::vector<float> gh;
+        std::vector<uint16_t> kh((size_t)n);
+        try {
+            d2h(ch, cell, n, s);
+            if (ogap) d2h(gh, ogap, n, s);
+            HIPCHK(hipStreamSynchronize(s));
+            std::vector<float> og;
+            if (ogap)
+                for (int64_t i = 0; i < n; ++i)
+                    if (ch[(size_t)i] == nc) og.push_back(gh[(size_t)i]);
+            std::sort(og.begin(), og.end());
+            std::vector<float> q;                                   // upper ends of quantiles 0 .. 254
+            for (int k = 1; k < 256 && !og.empty(); ++k) q.push_back(og[(size_t)((og.size() - 1) * k / 256)]);
+            for (int64_t i = 0; i < n; ++i) {
+                const int cc = ch[(size_t)i];
+                int gq = 0;
+                if (cc == nc && !q.empty())
+                    gq = (int)(std::lower_bound(q.begin(), q.end(), gh[(size_t)i]) - q.begin());
+                kh[(size_t)i] = (uint16_t)(cc << 8 | gq);
+            }
+            HIPCHK(hipMemcpyAsync(okey, kh.data(), (size_t)n * 2, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } catch (DevError &) {
+            (void)hipStreamSynchronize(s);
+            ctx->arena.release(okey);
+            ctx->arena.release(ogap);
+            ctx->arena.release(cell);
+            throw;
+        }
+    }
+    if (!okey) {                                                // no room: keep point order
+        ctx->arena.release(ogap);
+        ctx->arena.release(cell);
+        return;
+    }
     c->ncell = nall;
     c->cell = cell;
-    c->cell_bits = 32 - __builtin_clz((unsigned)(nall - 1));
+    c->ogap = ogap;
+    c->okey = okey;
+    c->cell_bits = 8 + (32 - __builtin_clz((unsigned)(nall - 1)));
 }
 
 // ------------------------------------------------------------------ the run
@@ -964,10 +1027,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     uint64_t *skey = mem.get<uint64_t>(Sa), *skey2 = mem.get<uint64_t>(Sa);
     uint32_t *sval = mem.get<uint32_t>(Sa), *sval2 = mem.get<uint32_t>(Sa);
     void *sortmp = mem.get<char>(sort_temp_bytes(Sa));
-    // slots sorted by (element, cell): each element's members in the cloud's
-    // locality order, point order within a cell (the sort is stable)
-    const int cbits = cloud->cell ? cloud->cell_bits : 0;
-    HIPCHK(launch_member_emit(range4, mpos, n, nint[1], na == 2, cloud->cell, cbits, skey, sval, s));
+    // slots sorted by (element, cell, outlier gap rank): each element's
+    // members in the cloud's locality order, point order within a cell (the
+    // sort is stable)
+    const int cbits = cloud->okey ? cloud->cell_bits : 0;
+    HIPCHK(launch_member_emit(range4, mpos, n, nint[1], na == 2, cloud->okey, cbits, skey, sval, s));
     bool alt = false;
     HIPCHK(radix_sort_pairs(skey, sval, skey2, sval2, S, bits_for((uint64_t)E_count) + cbits, sortmp, &alt, s));
     uint64_t *slot_elem = alt ? skey2 : skey;
@@ -1064,17 +1128,22 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         const int nc = cloud->ncell;
         std::vector<unsigned long long> nearh((size_t)CELL_MAX, 0);
         const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
+        const double Eb = Emax * (1.0 + 0x1.0p-40);
         for (int a = 0; a < nc; ++a)
             for (int b = 0; b < nc; ++b) {
                 const double g = cloud->cell_gap[(size_t)a * nc + b];
-                if (!(a != b && g > 0.0 && g * g * shrink > Emax * (1.0 + 0x1.0p-40)))
-                    nearh[(size_t)a] |= 1ull << b;
+                if (!(a != b && g > 0.0 && g * g * shrink > Eb)) nearh[(size_t)a] |= 1ull << b;
             }
+        // outliers farther than eps from every landmark cell (id nc, next to
+        // the outlier cell nc - 1): near the outliers only
+        const int out_id = nc - 1, far_id = nc;
+        nearh[(size_t)out_id] |= 1ull << far_id;
+        nearh[(size_t)far_id] = (1ull << out_id) | (1ull << far_id);
         unsigned long long *near = mem.get<unsigned long long>(CELL_MAX);
         unsigned long long *cmask = mem.get<unsigned long long>(nrb), *nmask = mem.get<unsigned long long>(nrb);
         h2d(near, nearh.data(), CELL_MAX, s);
-        HIPCHK(launch_tile_cells(slot_point, elem_off, d_rb_off, (int32_t)E_count, nrb, cloud->cell, near, cmask,
-                                 nmask, s));
+        HIPCHK(launch_tile_cells(slot_point, elem_off, d_rb_off, (int32_t)E_count, nrb, cloud->cell, cloud->ogap,
+                                 out_id, shrink, Eb, near, cmask, nmask, s));
         HIPCHK(launch_screen(d_items, nblocks, d_rb_off, cmask, nmask, keep, s));
         HIPCHK(launch_scan_u8(keep, kpos, nblocks, kst, s));
         TileItem *kept = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));   // room for all: one read below
@@ -1765,6 +1834,8 @@ mapper_status mapper_cloud_destroy(mapper_cloud *c) {
     if (!c) return fail(MAPPER_EINVAL, "null cloud");
     if (c->inflight.load() > 0) return fail(MAPPER_EBUSY, "cloud has requests in flight");
     c->ctx->arena.release(c->cell);
+    c->ctx->arena.release(c->ogap);
+    c->ctx->arena.release(c->okey);
     c->ctx->arena.release(c->X);
     delete c;
     return MAPPER_OK;

@@ -200,6 +200,37 @@ def test_screening_on_blobs(ctx):
     assert g.stats["pairs_computed"] < g.stats["pairs"]
 
 
+def test_screening_far_outliers(ctx):
+    """Blobs with a 30% uniform background and a bridge of points between
+    two blobs: the background lies outside every landmark cell (the outlier
+    cell), and each such point farther than eps from every landmark cell's
+    ball is screened against the cells (it can only neighbour other
+    outliers); bridge points within eps of a blob are not.  The graph is the
+    oracle's and the unscreened run's; most tile pairs are screened out,
+    which the background rows would prevent if outliers stayed near every
+    cell."""
+    from paper_2011_03209_amd import binding
+    rng = np.random.default_rng(47)
+    Xb, _ = synth.blobs(rng, 14000, 32, 4, 40.0)
+    lo, hi = Xb.min(axis=0), Xb.max(axis=0)
+    bg = (lo + rng.uniform(0.0, 1.0, size=(6000, 32)) * (hi - lo)).astype(np.float32)
+    t = np.linspace(0.0, 1.0, 60)[:, None]
+    c0 = np.zeros(32); c1 = np.zeros(32)
+    c0[0] = 40.0; c1[1] = 40.0
+    bridge = (c0 + t * (c1 - c0) + rng.normal(0.0, 0.05, size=(60, 32))).astype(np.float32)
+    X = np.ascontiguousarray(np.concatenate([Xb, bg, bridge])[rng.permutation(20060)])
+    params = synth.Params([synth.Axis(synth.LENS_L2, 1, 0.0)], eps=9.0, min_pts=6, precision=synth.PREC_BF16X3)
+    g, ref = run_and_compare(ctx, X, params)
+    assert g.stats["tiles_screened_out"] > g.stats["tiles"], (g.stats["tiles_screened_out"], g.stats["tiles"])
+    cloud = ctx.cloud(X)
+    try:
+        gn = cloud.run(params, flags=binding.FLAG_NO_SCREEN)
+    finally:
+        cloud.destroy()
+    assert gn.stats["tiles_screened_out"] == 0
+    same_graph(gn, ref)
+
+
 def test_autotuner_measures_then_caches():
     """MAPPER_PREC_AUTO on the first run of its kind times every precision on
     a sample of the run's own tile pairs and picks the smallest predicted
