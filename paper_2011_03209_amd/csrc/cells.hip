@@ -6,7 +6,7 @@
 // of them.  Most pairs of a large element are far apart when the cloud has
 // cluster structure, so the library lays each element's members out in the
 // order of a coarse partition of the cloud (its "cells": the nearest of up
-// to 63 landmarks chosen by farthest-point sampling, plus one cell for
+// to 62 landmarks chosen by farthest-point sampling, plus one cell for
 // outlying points), and bounds every landmark cell by a ball (the landmark
 // and the largest distance of a member from it).  A tile pair none of whose
 // cells are near each other (balls more than eps apart) holds no neighbour
@@ -14,8 +14,10 @@
 // tile by a ball of its own as well screened no more than 0.1% extra tile
 // pairs on the mixtures measured (members of one cell are in point order
 // within it, so the tiles of one cell overlap), and it cost two more reads
-// of every row, so it is not done.  The partition only orders the work; the
-// graph does not depend on it.
+// of every row, so it is not done.  A point of the outlier cell gets its own
+// bound on the distance to every landmark cell, and one farther than eps
+// from all of them can only neighbour other outliers.  The partition only
+// orders the work; the graph does not depend on it.
 #include "internal.h"
 
 namespace mgpu {

@@ -697,15 +697,16 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
 // uploaded.  From an evenly strided sample of 4096 rows: each row's nearest
 // other sample row (GPU), the inliers (no more than 4x the median of those
 // squared distances away: isolated rows such as uniform background noise
-// would otherwise be picked first), up to CELL_MAX - 1 landmarks among the
+// would otherwise be picked first), up to CELL_MAX - 2 landmarks among the
 // inliers by farthest-point sampling (FP64, host), numbered along a
 // nearest-neighbour chain.  Every point then goes to its nearest landmark,
 // or to the outlier cell when it lies farther from it than 1.5x the largest
 // distance of an inlier sample row in that cell.  Each landmark cell gets a
 // ball (the landmark, the largest distance of a member); the outlier cell
-// has none and is near every cell.  Only clouds large enough to fill
-// several tiles get cells, and only when the landmarks fit the kernel's
-// LDS; otherwise slots stay in point order.
+// has none, and each of its points gets a lower bound of its distance to
+// every landmark cell instead (the slot order sorts them by it).  Only
+// clouds large enough to fill several tiles get cells, and only when the
+// landmarks fit the kernel's LDS; otherwise slots stay in point order.
 void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     const int64_t n = c->n;
     const int32_t d = c->d;
