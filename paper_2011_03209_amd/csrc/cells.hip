@@ -30,20 +30,15 @@ constexpr int CC = 32;        // columns per LDS slab
 // cell[i] = the landmark nearest to point i (smallest |l|^2 - 2 x.l, FP32;
 // the order is a heuristic, so rounding does not matter), or the outlier
 // cell ncell when the point lies farther from it than limit2 (squared).
-// Landmarks are staged whole in LDS (ncell * d <= CELL_LDS_FLOATS).
+// The landmarks come transposed (coordinate j of landmark c at
+// landT[j * CELL_MAX + c], zero past ncell), so every thread reads the same
+// 64 values per coordinate: wave-uniform loads that the FMAs take as scalar
+// operands.  One point per thread, its row staged through LDS in slabs.
 __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X, int64_t n, int32_t d,
-                                                     const float *__restrict__ land, int32_t ncell,
+                                                     const float *__restrict__ landT,
+                                                     const float *__restrict__ lnorm, int32_t ncell,
                                                      const float *__restrict__ limit2, uint8_t *__restrict__ cell) {
-    __shared__ float L[CELL_LDS_FLOATS];
     __shared__ float tile[CB][CC + 1];
-    __shared__ float lnorm[CELL_MAX];
-    for (int i = threadIdx.x; i < ncell * d; i += CB) L[i] = land[i];
-    __syncthreads();
-    if (threadIdx.x < ncell) {
-        float s = 0.f;
-        for (int j = 0; j < d; ++j) s += L[threadIdx.x * d + j] * L[threadIdx.x * d + j];
-        lnorm[threadIdx.x] = s;
-    }
     const int64_t row0 = (int64_t)blockIdx.x * CB;
     float acc[CELL_MAX], nx = 0.f;
 #pragma unroll
@@ -60,10 +55,10 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
         __syncthreads();
         for (int j = 0; j < cw; ++j) {
             const float x = tile[threadIdx.x][j];
+            const float *lt = landT + (int64_t)(c0 + j) * CELL_MAX;
             nx += x * x;
 #pragma unroll
-            for (int c = 0; c < CELL_MAX; ++c)
-                if (c < ncell) acc[c] += x * L[c * d + c0 + j];
+            for (int c = 0; c < CELL_MAX; ++c) acc[c] += x * lt[c];
         }
     }
     const int64_t my = row0 + threadIdx.x;
@@ -114,19 +109,23 @@ __global__ void __launch_bounds__(256) k_sample_nn2(const float *__restrict__ su
 // r2[c] = max over the points of cell c of |x - l_c|^2 (FP64 sums of
 // squares of FP32 differences), as the bits of a non-negative double, which
 // order like the values.
-__global__ void k_cell_radius(const float *__restrict__ X, int64_t n, int32_t d, const float *__restrict__ land,
-                              int32_t ncell, const uint8_t *__restrict__ cell, unsigned long long *__restrict__ r2) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void __launch_bounds__(256) k_cell_radius(const float *__restrict__ X, int64_t n, int32_t d,
+                                                     const float *__restrict__ land, int32_t ncell,
+                                                     const uint8_t *__restrict__ cell,
+                                                     unsigned long long *__restrict__ r2) {
+    const int64_t i = block_linear() * 4 + threadIdx.x / WAVE;    // one wave per point, lanes along its row
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= n) return;                                      // the whole wave leaves together
     const int c = cell[i];
-    if (c >= ncell) return;                          // the outlier cell has no ball
+    if (c >= ncell) return;                                  // the outlier cell has no ball
     const float *x = X + i * (int64_t)d, *l = land + (int64_t)c * d;
     double acc = 0.0;
-    for (int j = 0; j < d; ++j) {
+    for (int j = lane; j < d; j += WAVE) {
         const double t = (double)x[j] - (double)l[j];
         acc += t * t;
     }
-    atomicMax(&r2[c], (unsigned long long)__double_as_longlong(acc));
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+    if (lane == 0) atomicMax(&r2[c], (unsigned long long)__double_as_longlong(acc));
 }
 
 // gap[i] <= min over the landmark cells c of |x_i - l_c| - r_c for a point
@@ -319,11 +318,12 @@ hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t 
     return hipGetLastError();
 }
 
-hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
-                               const float *limit2, uint8_t *cell, hipStream_t s) {
+hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *landT, const float *lnorm,
+                               int32_t ncell, const float *limit2, uint8_t *cell, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (ncell < 1 || ncell + 1 >= CELL_MAX || (int64_t)ncell * d > CELL_LDS_FLOATS) return hipErrorInvalidValue;
-    k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, land, ncell, limit2, cell);
+    if (ncell < 1 || ncell + 1 >= CELL_MAX) return hipErrorInvalidValue;
+    k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, landT, lnorm, ncell, limit2,
+                                                                          cell);
     return hipGetLastError();
 }
 
@@ -337,7 +337,7 @@ hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out,
 hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
                               const uint8_t *cell, unsigned long long *r2, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_cell_radius<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, d, land, ncell, cell, r2);
+    k_cell_radius<<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(X, n, d, land, ncell, cell, r2);
     return hipGetLastError();
 }
 
