@@ -108,24 +108,36 @@ __global__ void __launch_bounds__(256) k_sample_nn2(const float *__restrict__ su
 
 // r2[c] = max over the points of cell c of |x - l_c|^2 (FP64 sums of
 // squares of FP32 differences), as the bits of a non-negative double, which
-// order like the values.
+// order like the values.  A wave takes one point at a time, its lanes along
+// the row; the workgroup's maxima meet in LDS, so each workgroup of
+// CR_POINTS points issues at most one global atomic per cell.
+constexpr int CR_POINTS = 256;
+
 __global__ void __launch_bounds__(256) k_cell_radius(const float *__restrict__ X, int64_t n, int32_t d,
                                                      const float *__restrict__ land, int32_t ncell,
                                                      const uint8_t *__restrict__ cell,
                                                      unsigned long long *__restrict__ r2) {
-    const int64_t i = block_linear() * 4 + threadIdx.x / WAVE;    // one wave per point, lanes along its row
-    const int lane = threadIdx.x & (WAVE - 1);
-    if (i >= n) return;                                      // the whole wave leaves together
-    const int c = cell[i];
-    if (c >= ncell) return;                                  // the outlier cell has no ball
-    const float *x = X + i * (int64_t)d, *l = land + (int64_t)c * d;
-    double acc = 0.0;
-    for (int j = lane; j < d; j += WAVE) {
-        const double t = (double)x[j] - (double)l[j];
-        acc += t * t;
+    __shared__ unsigned long long bmax[CELL_MAX];
+    if (threadIdx.x < CELL_MAX) bmax[threadIdx.x] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int64_t p0 = block_linear() * CR_POINTS;
+    for (int q = w; q < CR_POINTS; q += (int)(blockDim.x / WAVE)) {
+        const int64_t i = p0 + q;
+        if (i >= n) break;                                   // uniform across the wave
+        const int c = cell[i];
+        if (c >= ncell) continue;                            // the outlier cell has no ball
+        const float *x = X + i * (int64_t)d, *l = land + (int64_t)c * d;
+        double acc = 0.0;
+        for (int j = lane; j < d; j += WAVE) {
+            const double t = (double)x[j] - (double)l[j];
+            acc += t * t;
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+        if (lane == 0) atomicMax(&bmax[c], (unsigned long long)__double_as_longlong(acc));
     }
-    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
-    if (lane == 0) atomicMax(&r2[c], (unsigned long long)__double_as_longlong(acc));
+    __syncthreads();
+    if (threadIdx.x < ncell && bmax[threadIdx.x]) atomicMax(&r2[threadIdx.x], bmax[threadIdx.x]);
 }
 
 // gap[i] <= min over the landmark cells c of |x_i - l_c| - r_c for a point
@@ -337,7 +349,8 @@ hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out,
 hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
                               const uint8_t *cell, unsigned long long *r2, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_cell_radius<<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(X, n, d, land, ncell, cell, r2);
+    if (ncell < 1 || ncell >= CELL_MAX) return hipErrorInvalidValue;
+    k_cell_radius<<<grid_2d((n + CR_POINTS - 1) / CR_POINTS), dim3(256), 0, s>>>(X, n, d, land, ncell, cell, r2);
     return hipGetLastError();
 }
 

@@ -317,6 +317,16 @@ def _cases():
     # very wide rows: many stages, ragged last one
     Xw = rng.normal(size=(200, 2050)).astype(np.float32)
     out.append(("d2050", Xw, synth.Params([synth.Axis(synth.LENS_LINF, 2, 0.3)], 64.0, 3)))
+    # one 128-row block with 40 non-core rows, each within eps of cores of
+    # two clusters: lines of cores at x = 0 and x = 10 (y = 0 .. 120), border
+    # points at (5, 3k + 0.5) with 7 neighbours (minPts 8), listed first so
+    # they share row block 0; each joins the lower cluster id (R3)
+    ya = np.arange(121, dtype=np.float32)
+    Xa = np.stack([np.zeros(121, np.float32), ya], axis=1)
+    Xb2 = np.stack([np.full(121, 10.0, np.float32), ya], axis=1)
+    Xbd = np.stack([np.full(40, 5.0, np.float32), 3.0 * np.arange(40, dtype=np.float32) + 0.5], axis=1)
+    out.append(("border_two_clusters", np.ascontiguousarray(np.concatenate([Xbd, Xa, Xb2])),
+                synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=1)], 5.05, 8)))
     # 2-D with one axis of one interval
     out.append(("2d_1x9", Xv, synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0),
                                              synth.Axis(synth.LENS_COLUMN, 9, 0.5, column=1)], 3.0, 3)))
