@@ -310,9 +310,10 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 constexpr int CELL_MAX = 64;
 constexpr int CELL_LDS_FLOATS = 16384;
 // cell[i] = nearest landmark, or ncell (the outlier cell) past limit2[c]
-// (squared distance); ncell + 1 < CELL_MAX.
-hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *land, int32_t ncell,
-                               const float *limit2, uint8_t *cell, hipStream_t s);
+// (squared distance); ncell + 1 < CELL_MAX.  landT: the landmarks
+// transposed, d x CELL_MAX (zero past ncell); lnorm[c] = |l_c|^2 (FP32).
+hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *landT, const float *lnorm,
+                               int32_t ncell, const float *limit2, uint8_t *cell, hipStream_t s);
 // out[i] = squared distance from sample row i to its nearest other row.
 hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out, hipStream_t s);
 // out[i] = items[i * n / m] with blk = i (an evenly strided sample of a tile

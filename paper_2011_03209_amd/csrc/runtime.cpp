@@ -786,11 +786,25 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         }
         limit2[(size_t)best] = std::max(limit2[(size_t)best], (float)(2.25 * bd));
     }
-    std::vector<float> land((size_t)nc * d);
-    for (int k = 0; k < nc; ++k)
-        std::memcpy(&land[(size_t)k * d], &sub[(size_t)(chain[k] * d)], (size_t)d * 4);
+    // landmarks row by row (nc x d), the cells' limits (nc), then the
+    // landmarks transposed with CELL_MAX columns (d x CELL_MAX, zero past
+    // nc) and their squared norms (CELL_MAX), for the assignment kernel
+    const size_t lt_off = ((size_t)nc * d + nc + 63) / 64 * 64;      // 256-byte aligned
+    std::vector<float> land(lt_off + (size_t)d * CELL_MAX + CELL_MAX, 0.0f);
+    float *lt = land.data() + lt_off, *ln = lt + (size_t)d * CELL_MAX;
+    for (int k = 0; k < nc; ++k) {
+        const float *src = &sub[(size_t)(chain[k] * d)];
+        std::memcpy(&land[(size_t)k * d], src, (size_t)d * 4);
+        float nrm = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            lt[(size_t)j * CELL_MAX + k] = src[j];
+            nrm += src[j] * src[j];
+        }
+        ln[k] = nrm;
+    }
+    std::memcpy(land.data() + (size_t)nc * d, limit2.data(), (size_t)nc * 4);
     uint8_t *cell = (uint8_t *)ctx->arena.alloc((uint64_t)n);
-    float *dl = (float *)ctx->arena.alloc((uint64_t)nc * d * 4 + (uint64_t)nc * 4);
+    float *dl = (float *)ctx->arena.alloc((uint64_t)land.size() * 4);
     unsigned long long *r2 = (unsigned long long *)ctx->arena.alloc((uint64_t)CELL_MAX * 8);
     if (!cell || !dl || !r2) {                                  // no room: keep point order
         ctx->arena.release(cell);
@@ -798,12 +812,11 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
         ctx->arena.release(r2);
         return;
     }
-    float *dlim = dl + (size_t)nc * d;
+    float *dlim = dl + (size_t)nc * d, *dlt = dl + lt_off, *dln = dlt + (size_t)d * CELL_MAX;
     std::vector<unsigned long long> r2h((size_t)CELL_MAX, 0);
     try {
         HIPCHK(hipMemcpyAsync(dl, land.data(), land.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(dlim, limit2.data(), limit2.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_assign_cells(c->X, n, d, dl, nc, dlim, cell, s));
+        HIPCHK(launch_assign_cells(c->X, n, d, dlt, dln, nc, dlim, cell, s));
         HIPCHK(hipMemsetAsync(r2, 0, (size_t)CELL_MAX * 8, s));
         HIPCHK(launch_cell_radius(c->X, n, d, dl, nc, cell, r2, s));
         HIPCHK(hipMemcpyAsync(r2h.data(), r2, (size_t)CELL_MAX * 8, hipMemcpyDeviceToHost, s));
