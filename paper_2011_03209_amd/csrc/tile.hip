@@ -217,6 +217,16 @@ __device__ __forceinline__ void grid_mfma(const GridOps &o, Acc<PREC> &acc) {
     }
 }
 
+// acc + this lane's bit of a wave mask (the mask as the carry-in of an add):
+// one instruction, and the mask is consumed at once instead of being kept
+// until the block's end.
+__device__ __forceinline__ int add_lane_bit(int acc, uint64_t mask) {
+    int r;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, 0, %2, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(mask));
+    return r;
+}
+
 // LV: eps values (levels) the workgroup can serve; the decisions of one
 // level at a time go through words, bwords and colcnt.
 template <int LV> struct EpiShared {
@@ -227,10 +237,19 @@ template <int LV> struct EpiShared {
     uint8_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes (<= 32)
 };
 
+// Bits j >= k of a 32-bit word, and bit k alone (none when k is outside
+// 0 .. 31).
+__device__ __forceinline__ uint32_t bits_from(int k) { return k <= 0 ? ~0u : (k >= 32 ? 0u : ~0u << k); }
+__device__ __forceinline__ uint32_t bit_at(int k) { return (k >= 0 && k < 32) ? 1u << k : 0u; }
+
 // Decisions of one 32 x 32 accumulator block (its 16 Gram values per lane in
 // gv): the row words of its bitmask and of its band pairs go to LDS, and the
 // lane's column count is added to colc.  FULL: the block lies inside the
 // element and off the diagonal, so no bounds or triangle masks are needed.
+// Otherwise (a diagonal or ragged tile pair) the same compares are masked
+// with wave-uniform words: the rows and columns inside the element, on the
+// diagonal only columns at or past the row, and the pair of a point with
+// itself always in.  DEBUG also stores every Gram value.
 template <bool FULL, bool DEBUG, int LV>
 __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared<LV> &es, int lv,
                                           const f32x16 &gv, int bm, int wm, int wn, int &colc) {
@@ -247,38 +266,56 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         TA[q] = *(const f32x4 *)&es.thrA[lv][r0 + 8 * q];
         TB[q] = *(const f32x4 *)&es.thrB[lv][r0 + 8 * q];
     }
+    // masked blocks: rows of tile I inside the element, and the columns
+    // wn * 32 .. + 31 of tile J inside it (lane bits)
+    const int rbase = wm * 64 + bm * 32, cbase = wn * 32;
+    int rows = TILE;
+    uint32_t colok = ~0u;
+    if constexpr (!FULL && !DEBUG) {
+        const int64_t rv = tl.ne - (int64_t)tl.I * TILE, cv = tl.ne - (int64_t)tl.J * TILE - cbase;
+        rows = (int)(rv < TILE ? rv : TILE);
+        colok = cv >= 32 ? ~0u : (cv <= 0 ? 0u : (1u << cv) - 1u);
+    }
     int word = 0, bword = 0;                               // lane li (< 32): row li of the block
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const float g = gv[v];
-        bool in, band;
+        uint64_t ib, bb, cm;                               // in, band, column-count lanes
         if constexpr (FULL) {
-            in = g >= TA[v >> 2][v & 3] + Aj;
-            band = !(g < TB[v >> 2][v & 3] + Bj);           // band once the "in" pairs are removed
-            colc += in ? 1 : 0;
+            ib = __ballot(g >= TA[v >> 2][v & 3] + Aj);
+            bb = __ballot(!(g < TB[v >> 2][v & 3] + Bj)) & ~ib;   // band once the "in" pairs are removed
+            cm = ib;
+        } else if constexpr (!DEBUG) {
+            const int rlo = rbase + 8 * (v >> 2) + (v & 3), rhi = rlo + 4;   // rows of lanes 0-31, 32-63
+            const uint32_t vlo = rlo < rows ? colok & (diag ? bits_from(rlo - cbase) : ~0u) : 0u;
+            const uint32_t vhi = rhi < rows ? colok & (diag ? bits_from(rhi - cbase) : ~0u) : 0u;
+            const uint64_t valid = ((uint64_t)vhi << 32) | vlo;
+            const uint64_t self = diag ? (((uint64_t)bit_at(rhi - cbase) << 32) | bit_at(rlo - cbase)) : 0ull;
+            ib = (__ballot(g >= TA[v >> 2][v & 3] + Aj) | self) & valid;
+            bb = __ballot(!(g < TB[v >> 2][v & 3] + Bj)) & valid & ~ib;
+            cm = ib & ~self;
         } else {
             const int rl = r0 + 8 * (v >> 2) + (v & 3);
             const int64_t gr = (int64_t)tl.I * TILE + rl;
             const bool valid = gr < tl.ne && gc < tl.ne && (!diag || rl <= cl);
             const bool self = diag && rl == cl;
-            in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
-            band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
-            colc += (in && !self) ? 1 : 0;
-            if constexpr (DEBUG) {
-                if (gr < tl.ne && gc < tl.ne) {
-                    a.debug_g[gr * a.debug_ld + gc] = g;
-                    a.debug_g[gc * a.debug_ld + gr] = g;
-                }
+            const bool in = valid && (self || g >= TA[v >> 2][v & 3] + Aj);
+            const bool band = valid && !in && !(g < TB[v >> 2][v & 3] + Bj);
+            if (gr < tl.ne && gc < tl.ne) {
+                a.debug_g[gr * a.debug_ld + gc] = g;
+                a.debug_g[gc * a.debug_ld + gr] = g;
             }
+            ib = __ballot(in);
+            bb = __ballot(band);
+            cm = __ballot(in && !self);
         }
-        const uint64_t ib = __ballot(in);
-        // the low half of the ballot is row 8(v/4) + v%4, the high half the row 4 below
+        colc = add_lane_bit(colc, cm);
+        // the low half of a ballot is row 8(v/4) + v%4, the high half the row 4 below
         word = lane_write((int)(uint32_t)ib, 8 * (v >> 2) + (v & 3), word);
         word = lane_write((int)(uint32_t)(ib >> 32), 8 * (v >> 2) + 4 + (v & 3), word);
         // band pairs are rare, but the two lane writes cost less than the
         // branch around them (measured: the branch taken at every value
         // added 3.3 ms to the FP16 tile pass at 1M x 256)
-        const uint64_t bb = __ballot(band) & ~ib;
         bword = lane_write((int)(uint32_t)bb, 8 * (v >> 2) + (v & 3), bword);
         bword = lane_write((int)(uint32_t)(bb >> 32), 8 * (v >> 2) + 4 + (v & 3), bword);
     }
@@ -287,6 +324,9 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         es.words[at] = (uint32_t)word;
         es.bwords[at] = (uint32_t)bword;
     }
+    // one block at a time: interleaving the blocks' compares would keep many
+    // 64-bit ballot masks live and spill scalar registers
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // The band pairs of tile row t (its band words bw) at level lv -> FP64
@@ -341,13 +381,23 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
     for (int lv = 0; lv < nlev; ++lv) {
         if (lv > 0) lds_barrier();                          // the previous level's words are stored
         int colc = 0;
-        if (!DEBUG && full) {
+        if constexpr (!DEBUG) {
+            if (full) {
 #pragma unroll
-            for (int bm = 0; bm < 2; ++bm) epi_block<true, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
-        } else {                                            // diagonal or ragged tiles (few): one copy
+                for (int bm = 0; bm < 2; ++bm) epi_block<true, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
+            } else if constexpr (LV == 1) {                 // diagonal or ragged tiles: masked
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+                    epi_block<false, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
+            } else {                                        // (one copy in the multi-level kernel)
+#pragma unroll 1
+                for (int bm = 0; bm < 2; ++bm)
+                    epi_block<false, false, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
+            }
+        } else {
 #pragma unroll 1
             for (int bm = 0; bm < 2; ++bm)
-                epi_block<false, DEBUG, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
+                epi_block<false, true, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
         }
         const int lane = lane_id_here();
         es.colcnt[wm * 2 + (lane >> 5)][wn * 32 + (lane & 31)] = (uint8_t)colc;
@@ -519,16 +569,6 @@ __device__ __forceinline__ void macro_mfma(const char *stage, MacroAcc &acc, int
                         __builtin_bit_cast(f16x8, va[rb]), __builtin_bit_cast(f16x8, vb[cb]), c, 0, 0, 0);
             }
     }
-}
-
-// acc + this lane's bit of a wave mask (the mask as the carry-in of an add):
-// one instruction, and the mask is consumed at once instead of being kept
-// until the block's end.
-__device__ __forceinline__ int add_lane_bit(int acc, uint64_t mask) {
-    int r;
-    uint64_t carry;
-    asm("v_addc_co_u32_e64 %0, %1, 0, %2, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(mask));
-    return r;
 }
 
 // Decisions of accumulator block (rb, cb) of wave (wm, wn) in tile pair
