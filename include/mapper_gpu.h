@@ -152,7 +152,8 @@ typedef struct {
     uint64_t arena_peak_bytes;
     int32_t precision;       /* precision actually used */
     int32_t tile_m, tile_n, split_terms;
-    int32_t tile_launches;   /* > 1 if the band list had to grow */
+    int32_t tile_launches;   /* > 1 if the band list had to grow (the band records
+                                are collected again; macro tiles are redone) */
     double band_halfwidth;   /* largest FP32 half-width of the eps^2 band */
     uint64_t reserved_bytes; /* workspace reserved in one block after binning */
     uint64_t reserve_overflow_bytes;  /* taken beyond the reservation (a regrown band list) */

@@ -362,6 +362,10 @@ struct TileArgs {
     // band pairs: nseg segments of band_cap entries; band_n[g] counts the pairs
     // of segment g (past band_cap they are counted but not stored)
     BandPair *band; unsigned long long *band_n; int64_t band_cap; int32_t nseg;
+    // tile pair form: per level and tile pair, one band-mask word per lane of
+    // each of its eight waves (TILE_WORDS words, the bitmask's block layout
+    // in size); k_band_collect turns them into band records
+    uint32_t *bandmask;
     // eps values served by the pass: thresholds, counts and bitmask of level t
     // at t * level_slots (thrA, thrB, count) and t * level_words (bitmask)
     int32_t n_levels; int64_t level_slots; uint64_t level_words;
@@ -371,6 +375,13 @@ struct TileArgs {
     int64_t n_mitems;
 };
 hipError_t launch_tiles(int prec, const TileArgs &a, hipStream_t s);
+// Band records of every tile pair of tt (its items) from the band masks the
+// tile pair form left: n_levels levels level_words apart; segment = tile pair
+// index mod nseg; band_n counts every pair, records past band_cap are not
+// stored (band_n zeroed by the caller).
+hipError_t launch_band_collect(const TileTable &tt, const uint32_t *bandmask, int32_t n_levels, uint64_t level_words,
+                               BandPair *band, unsigned long long *band_n, int64_t band_cap, int32_t nseg,
+                               hipStream_t s);
 // The same bitmask, counts and band records as launch_tiles, computed by one
 // workgroup per macro item (a.mitems); single 16-bit products (BF16, FP16),
 // one eps value, no debug output.

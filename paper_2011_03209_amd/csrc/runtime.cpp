@@ -532,6 +532,7 @@ int tune_precision(mapper_context *ctx, const mapper_cloud *cloud, const TileTab
         float *thrA = tmp.get<float>(S), *thrB = tmp.get<float>(S);
         int32_t *cnt = tmp.get<int32_t>(S);
         uint32_t *bm = tmp.get<uint32_t>((uint64_t)m * TILE_WORDS);
+        uint32_t *bmk = tmp.get<uint32_t>((uint64_t)m * TILE_WORDS);    // band masks
         const int nseg = 8;
         const int64_t cap = 256;                        // band pairs are counted; few are stored
         unsigned long long *bn = tmp.get<unsigned long long>(nseg);
@@ -573,10 +574,12 @@ int tune_precision(mapper_context *ctx, const mapper_cloud *cloud, const TileTab
             ta.n_levels = 1;
             ta.level_slots = S;
             ta.level_words = (uint64_t)m * TILE_WORDS;
+            ta.bandmask = bmk;
             Events ev(s, ctx->events);
             ev.mark();
             HIPCHK(launch_tiles(p, ta, s));
             ev.mark();
+            HIPCHK(launch_band_collect(ts, bmk, 1, ta.level_words, band, bn, cap, nseg, s));
             std::vector<unsigned long long> bh;
             d2h(bh, bn, nseg, s);
             HIPCHK(hipStreamSynchronize(s));
@@ -1235,6 +1238,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
                  r256((uint64_t)std::max<int64_t>(n_mitems, 1) * sizeof(MacroItem));
     fixed += r256(U * stride) + 2 * r256((uint64_t)n_levels * U * 4) + r256((uint64_t)n_levels * U * 4) +
              r256((uint64_t)n_levels * level_words * 4) + r256((uint64_t)nseg * 8);
+    if (!use_macro) fixed += r256((uint64_t)n_levels * level_words * 4);     // band masks
     const uint64_t EPb = std::max<uint64_t>(pair_bound, 1);
     const uint64_t level = r256(U * 4) + r256(U) + r256((U + 1) * 8) + 2 * r256(U * 4) +
                            r256(scan_temp_bytes((int64_t)U + 1)) + r256((uint64_t)std::max<int64_t>(nrb, 1)) +
@@ -1320,12 +1324,33 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     uint32_t *bitmask_all = rm.get<uint32_t>((uint64_t)n_levels * level_words);
     st.bitmask_bytes = n_tiles * TILE_WORDS * 4;
     unsigned long long *band_n = rm.get<unsigned long long>(nseg);
+    uint32_t *bandmask_all = use_macro ? nullptr : rm.get<uint32_t>((uint64_t)n_levels * level_words);
     BandPair *band = rm.get<BandPair>((uint64_t)nseg * band_cap);
     ev.mark();                                                      // 3
     std::vector<unsigned long long> segn(nseg);
+    double ms_collect = 0.0;
+    // the tile pass, then (tile pair form) the band records from its band
+    // masks; when a band-list segment overflows the list grows and the
+    // records are collected again (the macro form redoes its tiles)
     for (int launch = 0;; ++launch) {
-        HIPCHK(hipMemsetAsync(count_all, 0, (size_t)n_levels * Sa * 4, s));
         HIPCHK(hipMemsetAsync(band_n, 0, (size_t)nseg * 8, s));
+        if (!use_macro && launch > 0) {
+            Events ct(s, ctx->events);
+            ct.mark();
+            HIPCHK(launch_band_collect(tt, bandmask_all, n_levels, level_words, band, band_n, band_cap, nseg, s));
+            ct.mark();
+            HIPCHK(hipMemcpyAsync(segn.data(), band_n, (size_t)nseg * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            st.tile_launches = launch + 1;
+            ms_collect = ct.ms(0, 1);
+            const int64_t most = (int64_t)*std::max_element(segn.begin(), segn.end());
+            if (most <= band_cap) break;
+            band_cap = most + most / 8 + 256;
+            rm.release(band);                               // the stream is synchronized
+            band = rm.get<BandPair>((uint64_t)nseg * band_cap);
+            continue;
+        }
+        HIPCHK(hipMemsetAsync(count_all, 0, (size_t)n_levels * Sa * 4, s));
         TileArgs ta{};
         ta.tt = tt;
         ta.panel = panel;
@@ -1343,18 +1368,23 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         ta.level_words = level_words;
         ta.mitems = d_mitems;
         ta.n_mitems = n_mitems;
+        ta.bandmask = bandmask_all;
         Events kt(s, ctx->events);
         kt.mark();
         if (use_macro) HIPCHK(launch_tiles_macro(prec, ta, s));
         else HIPCHK(launch_tiles(prec, ta, s));
         kt.mark();
+        if (!use_macro)
+            HIPCHK(launch_band_collect(tt, bandmask_all, n_levels, level_words, band, band_n, band_cap, nseg, s));
+        kt.mark();
         HIPCHK(hipMemcpyAsync(segn.data(), band_n, (size_t)nseg * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         st.tile_launches = launch + 1;
         st.ms_tiles = kt.ms(0, 1);
+        ms_collect = kt.ms(1, 2);
         const int64_t most = (int64_t)*std::max_element(segn.begin(), segn.end());
         if (most <= band_cap) break;
-        band_cap = most + most / 8 + 256;                   // grow and redo the tiles
+        band_cap = most + most / 8 + 256;                   // grow, and collect (macro: tile) again
         rm.release(band);                                   // the stream is synchronized
         band = rm.get<BandPair>((uint64_t)nseg * band_cap);
     }
@@ -1559,7 +1589,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     }
     g->stats.ms_lens = ev.ms(0, 1);                                 // the stream has passed every event
     g->stats.ms_bin = ev.ms(1, 2);
-    g->stats.ms_recheck = ev.ms(4, 5);
+    g->stats.ms_recheck = ev.ms(4, 5) + ms_collect;                // band records and their FP64 re-decision
     g->stats.ms_cc = lev.ms(0, 1);
     g->stats.ms_edges = lev.ms(1, 2);
     g->stats.ms_total = ev.ms(0, 5) + lev.ms(0, 2);
@@ -2054,6 +2084,7 @@ extern "C" mapper_status mapper_debug_tile_d2(mapper_context *ctx, const mapper_
         ta.thrA = pk.thrA;
         ta.thrB = pk.thrB;
         ta.bitmask = mem.get<uint32_t>((uint64_t)P * TILE_WORDS);
+        ta.bandmask = mem.get<uint32_t>((uint64_t)P * TILE_WORDS);
         ta.count = mem.get<int32_t>(nrows);
         ta.band_cap = 0;
         ta.band = nullptr;

@@ -227,13 +227,20 @@ __device__ __forceinline__ int add_lane_bit(int acc, uint64_t mask) {
     return r;
 }
 
+// 2 acc + this lane's bit of a wave mask: the bit shifted in at the bottom.
+__device__ __forceinline__ uint32_t shift_in_lane_bit(uint32_t acc, uint64_t mask) {
+    uint32_t r;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(mask));
+    return r;
+}
+
 // LV: eps values (levels) the workgroup can serve; the decisions of one
-// level at a time go through words, bwords and colcnt.
+// level at a time go through words and colcnt.
 template <int LV> struct EpiShared {
     __attribute__((aligned(16))) float thrA[LV][2 * TILE];
     __attribute__((aligned(16))) float thrB[LV][2 * TILE];
     __attribute__((aligned(16))) uint32_t words[TILE * 4];    // bitmask block: 4 words per row
-    __attribute__((aligned(16))) uint32_t bwords[TILE * 4];   // band pairs, same layout
     uint8_t colcnt[4][TILE];   // column counts, one partial per 32-row band of lanes (<= 32)
 };
 
@@ -252,7 +259,7 @@ __device__ __forceinline__ uint32_t bit_at(int k) { return (k >= 0 && k < 32) ? 
 // itself always in.  DEBUG also stores every Gram value.
 template <bool FULL, bool DEBUG, int LV>
 __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, EpiShared<LV> &es, int lv,
-                                          const f32x16 &gv, int bm, int wm, int wn, int &colc) {
+                                          const f32x16 &gv, int bm, int wm, int wn, int &colc, uint32_t &bmask) {
     const int lane = lane_id_here();
     const int li = lane & 31, lg = lane >> 5;
     const bool diag = tl.I == tl.J;
@@ -276,7 +283,7 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         rows = (int)(rv < TILE ? rv : TILE);
         colok = cv >= 32 ? ~0u : (cv <= 0 ? 0u : (1u << cv) - 1u);
     }
-    int word = 0, bword = 0;                               // lane li (< 32): row li of the block
+    int word = 0;                                          // lane li (< 32): row li of the block
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const float g = gv[v];
@@ -313,17 +320,10 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
         // the low half of a ballot is row 8(v/4) + v%4, the high half the row 4 below
         word = lane_write((int)(uint32_t)ib, 8 * (v >> 2) + (v & 3), word);
         word = lane_write((int)(uint32_t)(ib >> 32), 8 * (v >> 2) + 4 + (v & 3), word);
-        // band pairs are rare, but the two lane writes cost less than the
-        // branch around them (measured: the branch taken at every value
-        // added 3.3 ms to the FP16 tile pass at 1M x 256)
-        bword = lane_write((int)(uint32_t)bb, 8 * (v >> 2) + (v & 3), bword);
-        bword = lane_write((int)(uint32_t)(bb >> 32), 8 * (v >> 2) + 4 + (v & 3), bword);
+        // band pairs: the lane's own bit, shifted into its band mask
+        bmask = shift_in_lane_bit(bmask, bb);
     }
-    if (lane < 32) {
-        const int at = (wm * 64 + bm * 32 + li) * 4 + wn;
-        es.words[at] = (uint32_t)word;
-        es.bwords[at] = (uint32_t)bword;
-    }
+    if (lane < 32) es.words[(wm * 64 + bm * 32 + li) * 4 + wn] = (uint32_t)word;
     // one block at a time: interleaving the blocks' compares would keep many
     // 64-bit ballot masks live and spill scalar registers
     __builtin_amdgcn_sched_barrier(0);
@@ -331,7 +331,8 @@ __device__ __forceinline__ void epi_block(const TileArgs &a, const TilePos &tl, 
 
 // The band pairs of tile row t (its band words bw) at level lv -> FP64
 // recheck list, in segment blockIdx.x % nseg (no single counter is shared by
-// the whole launch).
+// the whole launch).  The macro form appends from its workgroups; the tile
+// pair form leaves band masks that k_band_collect turns into records.
 __device__ __forceinline__ void band_append(const TileArgs &a, const TilePos &tl, int t, u32x4 bw, int lv) {
     const int n = __popc(bw.x) + __popc(bw.y) + __popc(bw.z) + __popc(bw.w);
     const int seg = (int)(blockIdx.x % (unsigned)a.nseg);
@@ -381,25 +382,31 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
     for (int lv = 0; lv < nlev; ++lv) {
         if (lv > 0) lds_barrier();                          // the previous level's words are stored
         int colc = 0;
+        uint32_t bmask = 0;                                 // block 0 ends in bits 31 .. 16, block 1 in 15 .. 0
         if constexpr (!DEBUG) {
             if (full) {
 #pragma unroll
-                for (int bm = 0; bm < 2; ++bm) epi_block<true, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
+                for (int bm = 0; bm < 2; ++bm)
+                    epi_block<true, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc, bmask);
             } else if constexpr (LV == 1) {                 // diagonal or ragged tiles: masked
 #pragma unroll
                 for (int bm = 0; bm < 2; ++bm)
-                    epi_block<false, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc);
+                    epi_block<false, false, LV>(a, tl, es, lv, acc.c[bm], bm, wm, wn, colc, bmask);
             } else {                                        // (one copy in the multi-level kernel)
 #pragma unroll 1
                 for (int bm = 0; bm < 2; ++bm)
-                    epi_block<false, false, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
+                    epi_block<false, false, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc, bmask);
             }
         } else {
 #pragma unroll 1
             for (int bm = 0; bm < 2; ++bm)
-                epi_block<false, true, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc);
+                epi_block<false, true, LV>(a, tl, es, lv, acc_block(acc, bm), bm, wm, wn, colc, bmask);
         }
         const int lane = lane_id_here();
+        // the band masks of the tile pair: one word per lane of each wave,
+        // turned into band records by k_band_collect
+        a.bandmask[(uint64_t)lv * a.level_words + (uint64_t)tl.blk * TILE_WORDS + (threadIdx.x & ~(WAVE - 1)) + lane] =
+            bmask;
         es.colcnt[wm * 2 + (lane >> 5)][wn * 32 + (lane & 31)] = (uint8_t)colc;
         lds_barrier();
         const int t = (threadIdx.x & ~(WAVE - 1)) + lane;
@@ -412,8 +419,6 @@ __device__ __forceinline__ void tile_epilogue(const TileArgs &a, const TilePos &
                 const u32x4 wv = *(const u32x4 *)(es.words + 4 * t);
                 const int c = __popc(wv.x) + __popc(wv.y) + __popc(wv.z) + __popc(wv.w);
                 if (r < tl.ne && c) atomicAdd(&cnt[r], c);
-                const u32x4 bw = *(const u32x4 *)(es.bwords + 4 * t);
-                if (bw.x | bw.y | bw.z | bw.w) band_append(a, tl, t, bw, lv);
             } else {
                 const int cc = t - TILE;
                 const int64_t gc = (int64_t)tl.J * TILE + cc;
@@ -933,6 +938,69 @@ __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
     out[i] = mode == 1 ? -kth : kth;
 }
 
+// Band records from the band masks of the tile pair form: one wave per
+// (level, tile pair).  Word w * 64 + l of the pair's mask block belongs to
+// lane l of wave w of its workgroup (wave (wm, wn) = (w / 4, w % 4)): column
+// wn * 32 + l % 32; bit 31 - v for value v of accumulator block 0, bit
+// 15 - v for block 1, on the rows of the accumulator layout.  A tile pair
+// with any band bit reserves its records with one atomic on its segment
+// (tile pair index mod nseg) and every lane writes its own; past band_cap
+// they are only counted.
+__global__ void __launch_bounds__(256) k_band_collect(const TileItem *__restrict__ items, int64_t n_items,
+                                                      const uint32_t *__restrict__ bandmask, int32_t n_levels,
+                                                      uint64_t level_words, BandPair *__restrict__ band,
+                                                      unsigned long long *__restrict__ band_n, int64_t band_cap,
+                                                      int32_t nseg) {
+    const int64_t wv = block_linear() * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (wv >= n_items * n_levels) return;                    // the whole wave leaves together
+    const int lv = (int)(wv / n_items);
+    const int64_t t = wv - (int64_t)lv * n_items;
+    const TileItem it = items[t];
+    const uint32_t *mb = bandmask + (uint64_t)lv * level_words + (uint64_t)it.blk * TILE_WORDS + lane;
+    uint32_t m[8];
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        m[w] = mb[w * WAVE];
+        n += __popc(m[w]);
+    }
+    if (__ballot(n != 0) == 0) return;                      // uniform: most tile pairs have no band pair
+    int incl = n;                                            // inclusive prefix sum over the lanes
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(incl, (unsigned)o, WAVE);
+        if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, WAVE - 1, WAVE);
+    const int seg = (int)(t % nseg);
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(&band_n[seg], (unsigned long long)total);
+    const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    int64_t idx = (int64_t)(((uint64_t)bhi << 32) | blo) + (incl - n);
+    const int li = lane & 31, lg = lane >> 5;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        const int wm = w >> 2, wn = w & 3, cl = wn * 32 + li;
+        uint32_t mm = m[w];
+        while (mm) {
+            const int k = __ffs(mm) - 1;
+            mm &= mm - 1;
+            const int bm = k >= 16 ? 0 : 1, v = 15 - (k & 15);
+            const int rl = wm * 64 + bm * 32 + 4 * lg + 8 * (v >> 2) + (v & 3);
+            if (idx < band_cap) {
+                BandPair bp;
+                bp.si = (int32_t)(it.slot0 + (int64_t)it.I * TILE + rl);
+                bp.sj = (int32_t)(it.slot0 + (int64_t)it.J * TILE + cl);
+                bp.bit = (((uint64_t)it.blk * TILE_WORDS + (uint64_t)(rl * 4 + wn)) * 32u + (uint64_t)li) |
+                         ((uint64_t)lv << BAND_LEVEL_SHIFT);
+                band[(int64_t)seg * band_cap + idx] = bp;
+            }
+            ++idx;
+        }
+    }
+}
+
 __global__ void k_build_items(TileTable tt, TileItem *items) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= tt.n_items) return;
@@ -1026,6 +1094,17 @@ hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
                             const int32_t *ccnt, int32_t cmax, int32_t mode, double *out, hipStream_t s) {
     k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_collect(const TileTable &tt, const uint32_t *bandmask, int32_t n_levels, uint64_t level_words,
+                               BandPair *band, unsigned long long *band_n, int64_t band_cap, int32_t nseg,
+                               hipStream_t s) {
+    if (tt.n_items <= 0) return hipSuccess;
+    if (n_levels < 1 || n_levels > MAX_LEVELS || nseg < 1) return hipErrorInvalidValue;
+    const int64_t waves = tt.n_items * n_levels;
+    k_band_collect<<<grid_2d((waves + 3) / 4), dim3(256), 0, s>>>(tt.items, tt.n_items, bandmask, n_levels,
+                                                                   level_words, band, band_n, band_cap, nseg);
     return hipGetLastError();
 }
 
