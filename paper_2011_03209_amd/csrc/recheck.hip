@@ -18,7 +18,8 @@ namespace {
 // (ties, in practice) need the canonical chain itself, which lane 0 then
 // evaluates.  Workgroups RECHECK_WG_PER_SEG * g .. + RECHECK_WG_PER_SEG - 1
 // serve band segment g.
-constexpr int RECHECK_WG_PER_SEG = 8;
+constexpr int RECHECK_WG_PER_SEG = 16;
+constexpr int RG = 4;                  // pairs re-decided together (their row loads in flight at once)
 
 __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const unsigned long long *band_n,
                                                  int64_t band_cap, const float *X,
@@ -42,24 +43,26 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
             px = (int)slot_point[bp.si];
             py = (int)slot_point[bp.sj];
         }
-        for (int g = 0; g < m; g += 4) {
-            const int np = m - g < 4 ? m - g : 4;
-            const float *x[4], *y[4];
+        for (int g = 0; g < m; g += RG) {
+            const int np = m - g < RG ? m - g : RG;
+            const float *x[RG], *y[RG];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RG; ++i) {
                 const int k = g + (i < np ? i : 0);          // slots past np repeat the first pair
                 x[i] = X + (int64_t)__builtin_amdgcn_readlane(px, k) * d;
                 y[i] = X + (int64_t)__builtin_amdgcn_readlane(py, k) * d;
             }
-            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            double s[RG];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) s[i] = 0.0;
             for (int j0 = 0; j0 < d; j0 += 4 * WAVE) {
-                float xv[4][4], yv[4][4];
+                float xv[RG][4], yv[RG][4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int j = j0 + q * WAVE + lane;
                     const int jj = j < d ? j : d - 1;       // in bounds; the term is dropped below
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < RG; ++i) {
                         xv[i][q] = x[i][jj];
                         yv[i][q] = y[i][jj];
                     }
@@ -68,7 +71,7 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
                 for (int q = 0; q < 4; ++q) {
                     const bool live = j0 + q * WAVE + lane < d;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < RG; ++i) {
                         const double t = live ? (double)xv[i][q] - (double)yv[i][q] : 0.0;
                         s[i] = __builtin_fma(t, t, s[i]);
                     }
@@ -77,9 +80,9 @@ __global__ void __launch_bounds__(256) k_recheck(const BandPair *band, const uns
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], o, WAVE);
+                for (int i = 0; i < RG; ++i) s[i] += __shfl_xor(s[i], o, WAVE);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < RG; ++i) {
                 if (i < np) {
                     const int level = (int)__builtin_amdgcn_readlane((int)(uint32_t)(bp.bit >> BAND_LEVEL_SHIFT), g + i);
                     const double E = lv.E[level];
