@@ -274,9 +274,17 @@ __global__ void k_compact_items(const TileItem *__restrict__ items, int64_t n, c
             out[p] = it;
         }
     }
-    // every lane of the wave reaches here
+    // every thread of the workgroup reaches here: the workgroup's sum, one
+    // atomic on one of PAIR_SLOTS counters (the caller adds them up), so
+    // the launch does not queue on a single address
     for (int o = WAVE / 2; o > 0; o >>= 1) np += __shfl_xor(np, o, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && np) atomicAdd(pairs, np);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & (WAVE - 1)) == 0) part[threadIdx.x / WAVE] = np;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(&pairs[block_linear() % PAIR_SLOTS], t);
+    }
 }
 
 __global__ void k_sample_items(const TileItem *__restrict__ items, int64_t n, int64_t m, TileItem *__restrict__ out) {

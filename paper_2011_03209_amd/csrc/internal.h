@@ -347,8 +347,10 @@ hipError_t launch_cell_radius(const float *X, int64_t n, int32_t d, const float 
                               const uint8_t *cell, unsigned long long *r2, hipStream_t s);
 // out[pos[i]] = items[i] with blk = pos[i] for kept items; diag_blk and
 // next_blk (the blocks of (I, I) and (I, I + 1) at rb_off[e] + I, -1 if
-// screened out; next_blk preset to -1 by the caller); *pairs += the
-// in-element pairs of the kept tile pairs.
+// screened out; next_blk preset to -1 by the caller); the in-element pairs
+// of the kept tile pairs are added to pairs[0 .. PAIR_SLOTS - 1] (zeroed by
+// the caller, who sums them).
+constexpr int PAIR_SLOTS = 64;
 hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t *keep, const int64_t *pos,
                                 const int64_t *rb_off, TileItem *out, int64_t *diag_blk, int64_t *next_blk,
                                 unsigned long long *pairs, hipStream_t s);

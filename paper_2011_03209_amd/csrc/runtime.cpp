@@ -1166,15 +1166,16 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         TileItem *kept = mem.get<TileItem>(std::max<int64_t>(nblocks, 1));   // room for all: one read below
         diag_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
         next_blk = mem.get<int64_t>(std::max<int64_t>(nrb, 1));
-        unsigned long long *pc = mem.get<unsigned long long>(1);
-        HIPCHK(hipMemsetAsync(pc, 0, 8, s));
+        unsigned long long *pc = mem.get<unsigned long long>(PAIR_SLOTS);
+        HIPCHK(hipMemsetAsync(pc, 0, PAIR_SLOTS * 8, s));
         HIPCHK(hipMemsetAsync(next_blk, 0xff, (size_t)std::max<int64_t>(nrb, 1) * 8, s));   // -1: no pair (I, I + 1)
         HIPCHK(launch_compact_items(d_items, nblocks, keep, kpos, d_rb_off, kept, diag_blk, next_blk, pc, s));
-        unsigned long long pairs_c = 0;
+        unsigned long long pairs_c[PAIR_SLOTS];
         HIPCHK(hipMemcpyAsync(&n_tiles, kpos + nblocks, 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&pairs_c, pc, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(pairs_c, pc, PAIR_SLOTS * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        st.pairs_computed = (int64_t)pairs_c;
+        st.pairs_computed = 0;
+        for (int q = 0; q < PAIR_SLOTS; ++q) st.pairs_computed += (int64_t)pairs_c[q];
         tt.items = kept;
         tt.n_items = n_tiles;
     }
