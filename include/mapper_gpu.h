@@ -103,7 +103,7 @@ typedef struct {
 /* Cover of one lens axis (Background section).  UNIFORM: n closed intervals
  * of equal length tiling [min f, max f], neighbours sharing the fraction p of
  * their length.  BALANCED: intervals holding equal numbers of points (the
- * "balanced" cover the paper mentions): the uniform cover laid on the rank
+ * balanced cover the paper mentions): the uniform cover laid on the rank
  * axis [0, N-1] of the sorted lens values v_0 <= ... <= v_{N-1}, each rank
  * interval [a, b] becoming the closed value interval [v[floor a], v[ceil b]];
  * with distinct values every interval holds between floor(L) + 1 and

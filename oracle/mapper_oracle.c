@@ -8,9 +8,10 @@
  * What it computes (Zhou et al., "Mapper Interactive", Background section):
  *   - a filter (lens) f : X -> R (1-D mapper) or R^2 (2-D mapper);
  *   - a cover V = {V_k} of f(X) by n intervals of equal length whose
- *     neighbours overlap by a fraction p ("number of cover elements n and
- *     their percentage of overlaps p"); for 2-D the cover elements are the
- *     products of the two axes' intervals (rectangles);
+ *     neighbours overlap by a fraction p (the paper's two cover parameters:
+ *     the number of elements and their overlap, given as a percentage); for
+ *     2-D the cover elements are the products of the two axes' intervals
+ *     (rectangles);
  *   - for every cover element, DBSCAN (Ester et al.) of its pullback
  *     f^{-1}(V_k) with the Euclidean metric and parameters eps, minPts;
  *   - the mapper graph = 1-D nerve of the resulting clusters: one node per
@@ -30,7 +31,7 @@
  *            hi_k = lo_k + L (k < n-1), hi_{n-1} = M; closed intervals.
  *   balanced the same formula on the rank axis [0, N-1] of the sorted lens
  *            values v_0 <= ... <= v_{N-1}, rounded outward to ranks:
- *            lo_k = v[floor(rlo_k)], hi_k = v[ceil(rhi_k)] (the "balanced"
+ *            lo_k = v[floor(rlo_k)], hi_k = v[ceil(rhi_k)] (the balanced
  *            cover whose intervals hold equal numbers of points).
  *   distance D(a,b): t_j = (double)x_aj - (double)x_bj, D = fma(t_j,t_j,D)
  *            in j order starting from 0; neighbours iff D <= fl(eps*eps)
@@ -196,7 +197,7 @@ static int orc_cmp_double(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-/* Background section: the "balanced" cover, whose intervals hold equal
+/* Background section: the balanced cover, whose intervals hold equal
  * numbers of points.  The uniform cover is laid on the rank axis [0, N-1] of
  * the sorted lens values, and each rank interval [rlo, rhi] becomes the
  * value interval [v[floor(rlo)], v[ceil(rhi)]] (outward, so it is never
