@@ -55,9 +55,11 @@ def _replay(ctx, clouds, reqs, t_origin):
     return np.array(lat), np.array(lag)
 
 
-# Stream slots: measured on MI355X at 70% of saturation, two slots gave p99
-# 130-134 ms against 164-172 ms for three or four (more concurrent large
-# requests finish later) and saturation 131-134 graphs/s against 106 for one.
+# Stream slots: measured on MI355X (one run each, 256 requests, at 70% of
+# each setting's own saturation): 1 slot 289 graphs/s, p99 25 ms; 2 slots
+# 437 graphs/s, p99 24 ms; 3 slots 536 graphs/s, p99 76 ms; 4 slots 573
+# graphs/s, p99 36 ms.  More slots raise throughput, but large requests that
+# share the chip with more others finish later, so two keep the lowest p99.
 SLOTS = 2
 
 
