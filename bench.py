@@ -238,6 +238,15 @@ def main():
                           "ms_recheck": gs4[0].stats["ms_recheck"],
                           "ms_cc_each": [gg.stats["ms_cc"] for gg in gs4],
                           "nodes": [gg.n_nodes for gg in gs4]}), file=sys.stderr, flush=True)
+        mp4 = [5, 10, 20, 40]
+        cloud.run_sweep(w.params, [w.params.eps], mp4)
+        t1 = time.perf_counter()
+        gm = cloud.run_sweep(w.params, [w.params.eps], mp4)[0]
+        t2 = time.perf_counter()
+        print(json.dumps({"sweep": f"minPts sweep {mp4} at eps {w.params.eps} {args.precision}", "s_for_all": t2 - t1,
+                          "ms_tiles": gm[0].stats["ms_tiles"], "ms_cc_each": [gg.stats["ms_cc"] for gg in gm],
+                          "ms_edges_each": [gg.stats["ms_edges"] for gg in gm],
+                          "nodes": [gg.n_nodes for gg in gm]}), file=sys.stderr, flush=True)
         sub = ctx.cloud(np.ascontiguousarray(w.X[:100_000]))
         sub.knn_d2(5, 5)
         t0 = time.perf_counter()

@@ -211,6 +211,22 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
                                    const mapper_params *params, const double *eps_list,
                                    int32_t n_eps, mapper_graph **out);
 
+/* --- graphs for several (eps, minPts) pairs from one pass, synchronous -------
+ * The same interactive recomputation with minPts free as well: out[t * n_minpts
+ * + u] receives exactly the graph mapper_run returns with params->eps =
+ * eps_list[t] and params->min_pts = minpts_list[u].  A pair's neighbour
+ * count and adjacency do not depend on minPts (DBSCAN's core rule compares
+ * the count with it afterwards, Background section), so beyond the single
+ * eps sweep only the clusters, border points, nodes and edges are computed
+ * per minPts value.  eps_list as for mapper_run_eps_sweep; minpts_list: host,
+ * n_minpts values >= 1 (1 <= n_minpts <= MAPPER_MAX_MINPTS_VALUES), any
+ * order; out holds n_eps * n_minpts graphs owned by the caller; on error
+ * every out[.] is NULL. */
+#define MAPPER_MAX_MINPTS_VALUES 16
+mapper_status mapper_run_sweep(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
+                               const double *eps_list, int32_t n_eps, const int32_t *minpts_list,
+                               int32_t n_minpts, mapper_graph **out);
+
 /* --- k-th nearest-neighbour distances, synchronous -----------------------
  * The eps-selection module of the CIFAR-10 use case (Use Cases section)
  * plots the distribution of every point's distance to its k-th nearest

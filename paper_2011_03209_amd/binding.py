@@ -24,6 +24,7 @@ FLAG_TILE_PAIRS = 2         # force one workgroup per 128 x 128 tile pair
 FLAG_TILE_MACRO = 4         # force macro tiles (single 16-bit products)
 FLAG_NO_SCREEN = 8          # compute every tile pair (no ball screening)
 MAX_EPS_VALUES = 4          # MAPPER_MAX_EPS_VALUES
+MAX_MINPTS_VALUES = 16      # MAPPER_MAX_MINPTS_VALUES
 
 PREC_NAMES = {0: "fp32", 1: "bf16", 2: "bf16x3", 3: "fp16", 4: "fp16x3", 5: "auto"}
 
@@ -89,6 +90,8 @@ EXPORTS = {
                       ctypes.c_int),
     "mapper_run_eps_sweep": ([_vp, _vp, _P(_Params), _P(ctypes.c_double), ctypes.c_int32, _P(_vp)],
                              ctypes.c_int),
+    "mapper_run_sweep": ([_vp, _vp, _P(_Params), _P(ctypes.c_double), ctypes.c_int32, _P(ctypes.c_int32),
+                          ctypes.c_int32, _P(_vp)], ctypes.c_int),
     "mapper_submit": ([_vp, _vp, _P(_Params), _P(ctypes.c_uint64)], ctypes.c_int),
     "mapper_wait": ([_vp, ctypes.c_uint64, ctypes.c_int64, _P(_vp)], ctypes.c_int),
     "mapper_graph_num_nodes": ([_vp], ctypes.c_int64),
@@ -344,6 +347,20 @@ class Cloud:
         out = (_vp * len(eps_list))()
         _check(self.ctx.L.mapper_run_eps_sweep(self.ctx.h, self.h, ctypes.byref(p), eps, len(eps_list), out))
         return [_take_graph(_vp(out[t])) for t in range(len(eps_list))]
+
+    def run_sweep(self, params, eps_list, minpts_list, debug: bool = False) -> List[List[Graph]]:
+        """The graphs for every (eps, minPts) pair (at most MAX_EPS_VALUES eps
+        and MAX_MINPTS_VALUES minPts values) from one pass: result[t][u]
+        equals run(params with eps = eps_list[t], min_pts = minpts_list[u])."""
+        _check_axes(params, self.n, self.d)
+        keep: list = []
+        p = make_params(params, FLAG_DEBUG_STAGES if debug else 0, keep)
+        ne, nm = len(eps_list), len(minpts_list)
+        eps = (ctypes.c_double * ne)(*[float(e) for e in eps_list])
+        mps = (ctypes.c_int32 * nm)(*[int(m) for m in minpts_list])
+        out = (_vp * (ne * nm))()
+        _check(self.ctx.L.mapper_run_sweep(self.ctx.h, self.h, ctypes.byref(p), eps, ne, mps, nm, out))
+        return [[_take_graph(_vp(out[t * nm + u])) for u in range(nm)] for t in range(ne)]
 
     def knn_d2(self, k: int, precision: int = 5):
         """k-th smallest canonical squared distance from every point to the

@@ -946,7 +946,7 @@ struct RunOut {
 // tiles are shared; every level has its own bitmask, counts and graph.
 Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
                    hipStream_t s, bool may_retry, RunOut &out, const double *eps_list = nullptr,
-                   int n_levels = 1) {
+                   int n_levels = 1, const int32_t *minpts_list = nullptr, int n_minpts = 1) {
     Scope mem(ctx->arena, s);
     Events ev(s, ctx->events);
     const int64_t n = cloud->n;
@@ -1404,9 +1404,12 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     }
     ev.mark();                                                      // 5
 
-    // ---- one graph per level
-    for (int lv = 0; lv < n_levels; ++lv) {
-    Scope lm(sub, s, &ctx->arena);                                  // this level's work arrays
+    // ---- one graph per level and minPts value (counts and bitmask do not
+    // depend on minPts: only the clusters, border points and edges are redone)
+    for (int lv = 0; lv < n_levels; ++lv)
+    for (int mu = 0; mu < n_minpts; ++mu) {
+    const int32_t min_pts = minpts_list ? minpts_list[mu] : P->min_pts;
+    Scope lm(sub, s, &ctx->arena);                                  // this graph's work arrays
     Events lev(s, ctx->events);
     lev.mark();                                                     // 0
     int32_t *count = count_all + (int64_t)lv * Sa;
@@ -1421,11 +1424,11 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     int32_t *node = lm.get<int32_t>(Sa);
     int32_t *node_elem = lm.get<int32_t>(Sa);
     HIPCHK(launch_cc_init(parent, S, s));
-    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, diag_blk, next_blk, bitmask, count, P->min_pts,
+    HIPCHK(launch_cc_hook(tt, d_rb_off, nrb, (int32_t)E_count, diag_blk, next_blk, bitmask, count, min_pts,
                           parent, s));
     HIPCHK(launch_cc_compress(parent, S, s));
-    HIPCHK(launch_cc_tiles(tt, bitmask, count, P->min_pts, parent, s));
-    HIPCHK(launch_cc_flatten(count, P->min_pts, parent, isroot, S, s));
+    HIPCHK(launch_cc_tiles(tt, bitmask, count, min_pts, parent, s));
+    HIPCHK(launch_cc_flatten(count, min_pts, parent, isroot, S, s));
     void *stmp2 = lm.get<char>(scan_temp_bytes(Sa + 1));
     HIPCHK(launch_scan_u8(isroot, rank, S, stmp2, s));
     // canonical node order: the roots sorted by (element, smallest core point id)
@@ -1436,17 +1439,17 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     uint32_t *rv1 = lm.get<uint32_t>(Sa), *rv2 = lm.get<uint32_t>(Sa);
     void *rsort = lm.get<char>(sort_temp_bytes(Sa));
     int32_t *node_of_rank = lm.get<int32_t>(Sa);
-    HIPCHK(launch_root_keys(count, P->min_pts, parent, slot_point, isroot, rank, slot_elem, minpt, rk1, rv1, S, s));
+    HIPCHK(launch_root_keys(count, min_pts, parent, slot_point, isroot, rank, slot_elem, minpt, rk1, rv1, S, s));
     HIPCHK(hipStreamSynchronize(s));                                // N
     bool ralt = false;
     HIPCHK(radix_sort_pairs(rk1, rv1, rk2, rv2, N, 32 + bits_for((uint64_t)E_count), rsort, &ralt, s));
-    HIPCHK(launch_node_ids(count, P->min_pts, parent, rank, ralt ? rk2 : rk1, ralt ? rv2 : rv1, N, node_of_rank,
+    HIPCHK(launch_node_ids(count, min_pts, parent, rank, ralt ? rk2 : rk1, ralt ? rv2 : rv1, N, node_of_rank,
                            node, node_elem, S, s));
     {
         uint8_t *ncflag = lm.get<uint8_t>(std::max<int64_t>(nrb, 1));
         HIPCHK(hipMemsetAsync(ncflag, 0, (size_t)std::max<int64_t>(nrb, 1), s));
-        HIPCHK(launch_noncore_flags(count, P->min_pts, slot_elem, elem_off, d_rb_off, ncflag, S, s));
-        HIPCHK(launch_border(tt, bitmask, count, P->min_pts, ncflag, d_rb_off, node, s));
+        HIPCHK(launch_noncore_flags(count, min_pts, slot_elem, elem_off, d_rb_off, ncflag, S, s));
+        HIPCHK(launch_border(tt, bitmask, count, min_pts, ncflag, d_rb_off, node, s));
     }
     lev.mark();                                                     // 1
 
@@ -1582,7 +1585,7 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
         const int32_t *cnt = (const int32_t *)g->stages["slot_count"].first.data();
         for (int64_t i = 0; i < S; ++i) {
             if (nodev[i] == 0x7fffffff) nodev[i] = -1;
-            corev[i] = cnt[i] >= P->min_pts;
+            corev[i] = cnt[i] >= min_pts;
         }
         g->stages["slot_node"] = {std::vector<char>((char *)nodev.data(), (char *)nodev.data() + S * 4 + 1), S};
         g->stages["slot_core"] = {std::vector<char>((char *)corev.data(), (char *)corev.data() + S + 1), S};
@@ -1613,7 +1616,8 @@ struct Retry {
 // or P->eps when it is null).  req: the serving request (null otherwise).
 mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *P,
                           hipStream_t s, bool may_retry, mapper_graph **out, Retry *retry,
-                          const double *eps_list = nullptr, int n_levels = 1, const void *req = nullptr) {
+                          const double *eps_list = nullptr, int n_levels = 1, const void *req = nullptr,
+                          const int32_t *minpts_list = nullptr, int n_minpts = 1) {
     *retry = Retry{};
     RunOut ro;
     ro.req = req;
@@ -1627,8 +1631,8 @@ mapper_status run_guarded(mapper_context *ctx, const mapper_cloud *cloud, const 
     };
     try {
         HIPCHK(hipSetDevice(ctx->device));
-        run_pipeline(ctx, cloud, P, s, may_retry, ro, eps_list, n_levels);
-        for (int lv = 0; lv < n_levels; ++lv) out[lv] = ro.gs[lv];
+        run_pipeline(ctx, cloud, P, s, may_retry, ro, eps_list, n_levels, minpts_list, n_minpts);
+        for (int q = 0; q < n_levels * n_minpts; ++q) out[q] = ro.gs[(size_t)q];
         ro.gs.clear();
         return MAPPER_OK;
     } catch (AdmitWait &) {
@@ -1911,6 +1915,26 @@ mapper_status mapper_run_eps_sweep(mapper_context *ctx, const mapper_cloud *clou
     if (v != MAPPER_OK) return v;
     Retry retry;
     return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry, eps_list, n_eps);
+}
+
+mapper_status mapper_run_sweep(mapper_context *ctx, const mapper_cloud *cloud, const mapper_params *params,
+                               const double *eps_list, int32_t n_eps, const int32_t *minpts_list,
+                               int32_t n_minpts, mapper_graph **out) {
+    if (!ctx || !out || !eps_list || !minpts_list) return fail(MAPPER_EINVAL, "null argument");
+    if (n_eps < 1 || n_eps > MAPPER_MAX_EPS_VALUES) return fail(MAPPER_EINVAL, "n_eps must be in [1, MAPPER_MAX_EPS_VALUES]");
+    if (n_minpts < 1 || n_minpts > MAPPER_MAX_MINPTS_VALUES)
+        return fail(MAPPER_EINVAL, "n_minpts must be in [1, MAPPER_MAX_MINPTS_VALUES]");
+    for (int t = 0; t < n_eps * n_minpts; ++t) out[t] = nullptr;
+    for (int t = 0; t < n_eps; ++t)
+        if (!(eps_list[t] >= 0.0) || !std::isfinite(eps_list[t]))
+            return fail(MAPPER_EINVAL, "eps values must be finite and >= 0");
+    for (int u = 0; u < n_minpts; ++u)
+        if (minpts_list[u] < 1) return fail(MAPPER_EINVAL, "minPts values must be >= 1");
+    mapper_status v = validate(cloud, params);
+    if (v != MAPPER_OK) return v;
+    Retry retry;
+    return run_guarded(ctx, cloud, params, ctx->stream, false, out, &retry, eps_list, n_eps, nullptr, minpts_list,
+                       n_minpts);
 }
 
 mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32_t precision,

@@ -49,5 +49,6 @@ def test_errors_without_a_device():
     # null arguments are rejected, not dereferenced
     assert L.mapper_run(None, None, None, ctypes.byref(h)) == binding.MAPPER_EINVAL
     assert L.mapper_run_eps_sweep(None, None, None, None, 2, ctypes.byref(h)) == binding.MAPPER_EINVAL
+    assert L.mapper_run_sweep(None, None, None, None, 2, None, 2, ctypes.byref(h)) == binding.MAPPER_EINVAL
     assert L.mapper_knn_d2(None, None, 3, 2, None, None) == binding.MAPPER_EINVAL
     assert L.mapper_graph_num_nodes(None) == 0

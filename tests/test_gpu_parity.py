@@ -553,6 +553,50 @@ def test_eps_sweep_errors(ctx):
         cloud.destroy()
 
 
+@pytest.mark.parametrize("case", ["d256_bf16x3", "grid2d_fp16x3"])
+def test_eps_minpts_sweep(ctx, case):
+    """One pass for every (eps, minPts) pair gives for each the oracle's
+    graph and stages: minPts 1 (every point a core), the workload's own, and
+    values that leave few or no cores; eps repeated and out of order."""
+    import copy
+    if case == "d256_bf16x3":
+        w = synth.mixture_1m_d256(scale=0.004, precision=synth.PREC_BF16X3)
+        eps, mps = [24.0, 22.6, 24.0], [10, 1, 40, 3]
+    else:
+        w = synth.mixture_500k_d128_2d(scale=0.01, precision=synth.PREC_FP16X3)
+        eps, mps = [17.0, 19.0], [8, 2, 25]
+    print(f"[case] eps x minPts sweep {case} {eps} {mps}", flush=True)
+    cloud = ctx.cloud(w.X)
+    try:
+        gs = cloud.run_sweep(w.params, eps, mps, debug=True)
+    finally:
+        cloud.destroy()
+    assert len(gs) == len(eps) and all(len(row) == len(mps) for row in gs)
+    for e, row in zip(eps, gs):
+        for m, g in zip(mps, row):
+            p = copy.copy(w.params)
+            p.eps, p.min_pts = e, m
+            ref = oracle_graph(w.X, p)
+            same_stages(g, ref, len(p.axes))
+            same_graph(g, ref)
+
+
+def test_eps_minpts_sweep_errors(ctx):
+    from paper_2011_03209_amd import binding
+    w = synth.mixture_100k_d64(scale=0.01)
+    cloud = ctx.cloud(w.X)
+    try:
+        for bad in ([], [5] * (binding.MAX_MINPTS_VALUES + 1), [5, 0], [-1]):
+            with pytest.raises(binding.MapperError):
+                cloud.run_sweep(w.params, [w.params.eps], bad)
+        with pytest.raises(binding.MapperError):
+            cloud.run_sweep(w.params, [], [5])
+        g = cloud.run_sweep(w.params, [w.params.eps], [w.params.min_pts])[0][0]   # one pair: the plain run
+        same_graph(g, cloud.run(w.params))
+    finally:
+        cloud.destroy()
+
+
 def test_determinism_and_permutation(ctx):
     w = synth.mixture_1m_d256(scale=0.008, precision=synth.PREC_BF16X3)
     cloud = ctx.cloud(w.X)
