@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--tile-form", default="auto", choices=["auto", "pairs", "macro"],
                     help="launch form of the distance tiles (auto: the library's choice)")
     ap.add_argument("--no-screen", action="store_true",
-                    help="compute every tile pair (no ball screening of tile pairs)")
+                    help="compute every tile pair (no screening of tile pairs by landmark cells)")
     ap.add_argument("--sweep", action="store_true", help="time every tile precision (stderr)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known "

@@ -22,7 +22,7 @@ MAPPER_EBUSY, MAPPER_ETIMEDOUT, MAPPER_ENOTIMPL = -4, -5, -6
 FLAG_DEBUG_STAGES = 1
 FLAG_TILE_PAIRS = 2         # force one workgroup per 128 x 128 tile pair
 FLAG_TILE_MACRO = 4         # force macro tiles (single 16-bit products)
-FLAG_NO_SCREEN = 8          # compute every tile pair (no ball screening)
+FLAG_NO_SCREEN = 8          # compute every tile pair (no screening by cells)
 MAX_EPS_VALUES = 4          # MAPPER_MAX_EPS_VALUES
 MAX_MINPTS_VALUES = 16      # MAPPER_MAX_MINPTS_VALUES
 
