@@ -396,7 +396,7 @@ constexpr int KNN_KMAX = 16;         // largest k
 
 struct KnnArgs {
     TileArgs t;                        // panel, dp (the Gram tiles)
-    int64_t n;                         // points (= slots, identity map)
+    int64_t n;                         // slots (the points, in the order of the packed panels)
     int32_t T, C;                      // row blocks; column-block chunks per row block
     const float *hU, *hL;              // per point, scaled (packing thresholds at eps = 0)
     float *part;                       // pass 1: per (chunk, row, quarter) the 16 smallest U
@@ -405,13 +405,20 @@ struct KnnArgs {
     int32_t cmax;
     int32_t mode;                      // 0: k-th smallest D; 1: largest D (values negated)
     int32_t k;                         // the k of the k-th smallest (1 in mode 1)
+    const int32_t *jlist, *jcount;     // null: every column block; else row block I's list at I * T, its length
 };
 
 hipError_t launch_knn_pass(int prec, int pass, const KnnArgs &a, hipStream_t s);
 hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, int32_t k, float *thr,
                             hipStream_t s);
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out, hipStream_t s);
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out,
+                            hipStream_t s);
+// Column-block lists of the screened k-NN passes (k_knn_lists): cmask per row
+// block, gap the cells' nall x nall ball gaps (device), thr null for pass 1.
+hipError_t launch_knn_lists(int32_t T, int64_t n, const unsigned long long *cmask, const double *gap, int32_t nall,
+                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
+                            hipStream_t s);
 // f[i] = sqrt(f[i]) (correctly rounded FP64).
 hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).

@@ -290,6 +290,7 @@ struct mapper_cloud {
     uint8_t *cell = nullptr;           // landmark cell of each point (locality order), or null
     float *ogap = nullptr;             // per point of the outlier cell: distance bound to every landmark cell
     uint16_t *okey = nullptr;          // per point: cell << 8 | rank of its outlier gap (the slot order key)
+    uint32_t *korder = nullptr;        // the points in okey order (stable): slots of the screened k-NN
     int32_t cell_bits = 0;             // bits of okey in the binning key
     int32_t ncell = 0;
     std::vector<double> cell_gap;      // ncell x ncell: lower bound of the distance between two cells' points
@@ -617,10 +618,20 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     st.split_terms = prec_is_split(prec) ? 3 : 1;
     st.pairs = n * (n - 1);
     st.tiles = 2 * (int64_t)T * T;
-    std::vector<uint32_t> iota((size_t)n);
-    for (int64_t i = 0; i < n; ++i) iota[i] = (uint32_t)i;
-    uint32_t *ident = mem.get<uint32_t>(n);
-    h2d(ident, iota.data(), n, s);
+    // screening by the cloud's cells (k-th smallest only): slots in cell
+    // order, per row block the column blocks its rows may need (k_knn_lists)
+    const bool screen = mode == 0 && cloud->korder && cloud->cell && d <= BALL_DMAX && cloud->ncell >= 2 &&
+                        (int64_t)T * T <= (1ll << 28);
+    const uint32_t *slots = nullptr;
+    if (screen) {
+        slots = cloud->korder;
+    } else {
+        std::vector<uint32_t> iota((size_t)n);
+        for (int64_t i = 0; i < n; ++i) iota[i] = (uint32_t)i;
+        uint32_t *ident = mem.get<uint32_t>(n);
+        h2d(ident, iota.data(), n, s);
+        slots = ident;
+    }
     double scale = 1.0;
     if (cloud->maxabs > 0) scale = std::ldexp(1.0, 10 - std::ilogb((double)cloud->maxabs));
     const int dp = panel_dp(prec, d);
@@ -628,7 +639,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     pk.X = cloud->X;
     pk.d = d;
     pk.dp = dp;
-    pk.slot_point = ident;
+    pk.slot_point = slots;
     pk.n_slots = n;
     pk.prec = prec;
     pk.scale = scale;
@@ -653,11 +664,53 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     ka.part = mem.get<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
     float *thr = mem.get<float>(n);
     ka.thr = thr;
+    unsigned long long *cmask = nullptr;
+    double *dgap = nullptr;
+    int32_t *jlist = nullptr, *jcount = nullptr;
+    const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
+    const int nall = cloud->ncell;
+    auto list_sum = [&]() {
+        std::vector<int32_t> jc;
+        d2h(jc, jcount, T, s);
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t t = 0;
+        for (int32_t v : jc) t += v;
+        return t;
+    };
+    int64_t tiles1 = (int64_t)T * T;
+    if (screen) {
+        // the cells of every row block (k_tile_cells on one element of all
+        // slots; the near table is not used here)
+        cmask = mem.get<unsigned long long>(T);
+        unsigned long long *nmask = mem.get<unsigned long long>(T);
+        unsigned long long *near0 = mem.get<unsigned long long>(CELL_MAX);
+        int64_t *eo = mem.get<int64_t>(2), *rbo = mem.get<int64_t>(1);
+        const int64_t eoh[2] = {0, n}, rboh[1] = {0};
+        h2d(eo, eoh, 2, s);
+        h2d(rbo, rboh, 1, s);
+        HIPCHK(hipMemsetAsync(near0, 0, CELL_MAX * 8, s));
+        HIPCHK(launch_tile_cells(slots, eo, rbo, 1, T, cloud->cell, nullptr, nall - 1, shrink, 0.0, near0, cmask,
+                                 nmask, s));
+        dgap = mem.get<double>((uint64_t)nall * nall);
+        h2d(dgap, cloud->cell_gap.data(), (int64_t)nall * nall, s);
+        jlist = mem.get<int32_t>((uint64_t)T * T);
+        jcount = mem.get<int32_t>(T);
+        HIPCHK(launch_knn_lists(T, n, cmask, dgap, nall, nullptr, 0.0, shrink, jlist, jcount, s));
+        ka.jlist = jlist;
+        ka.jcount = jcount;
+        tiles1 = list_sum();
+    }
     Events ev(s, ctx->events);
     ev.mark();
     HIPCHK(launch_knn_pass(prec, 1, ka, s));
     HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
+    int64_t tiles2 = (int64_t)T * T;
+    if (screen) {
+        HIPCHK(launch_knn_lists(T, n, cmask, dgap, nall, thr, 1.0 / (scale * scale), shrink, jlist, jcount, s));
+    }
     ev.mark();
+    if (screen) tiles2 = list_sum();
+    st.tiles = tiles1 + tiles2;
     int32_t cmax = 64;
     int32_t *ccnt = mem.get<int32_t>(n);
     int64_t ncand = 0;
@@ -671,7 +724,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
         HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
         HIPCHK(launch_knn_pass(prec, 2, ka, s));
         e2.mark();
-        HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, mode, dout, s));
+        HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, mode, screen ? slots : nullptr, dout, s));
         e2.mark();
         std::vector<int32_t> cc;
         d2h(cc, ccnt, n, s);
@@ -873,6 +926,7 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     // cell come first in their element and the far ones fill row blocks of
     // their own
     uint16_t *okey = (uint16_t *)ctx->arena.alloc((uint64_t)n * 2);
+    uint32_t *korder = nullptr;
     if (okey) {
         std::vector<uint8_t> ch;
         std::vector<float> gh;
@@ -896,9 +950,20 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
                 kh[(size_t)i] = (uint16_t)(cc << 8 | gq);
             }
             HIPCHK(hipMemcpyAsync(okey, kh.data(), (size_t)n * 2, hipMemcpyHostToDevice, s));
+            // the points in key order (a counting sort, stable), for the k-NN
+            korder = (uint32_t *)ctx->arena.alloc((uint64_t)n * 4);
+            if (korder) {
+                std::vector<int64_t> start((size_t)65537, 0);
+                for (int64_t i = 0; i < n; ++i) ++start[(size_t)kh[(size_t)i] + 1];
+                for (size_t q = 1; q < start.size(); ++q) start[q] += start[q - 1];
+                std::vector<uint32_t> ord((size_t)n);
+                for (int64_t i = 0; i < n; ++i) ord[(size_t)start[kh[(size_t)i]]++] = (uint32_t)i;
+                HIPCHK(hipMemcpyAsync(korder, ord.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+            }
             HIPCHK(hipStreamSynchronize(s));
         } catch (DevError &) {
             (void)hipStreamSynchronize(s);
+            ctx->arena.release(korder);
             ctx->arena.release(okey);
             ctx->arena.release(ogap);
             ctx->arena.release(cell);
@@ -914,6 +979,7 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     c->cell = cell;
     c->ogap = ogap;
     c->okey = okey;
+    c->korder = korder;
     c->cell_bits = 8 + (32 - __builtin_clz((unsigned)(nall - 1)));
 }
 
@@ -1885,6 +1951,7 @@ mapper_status mapper_cloud_destroy(mapper_cloud *c) {
     c->ctx->arena.release(c->cell);
     c->ctx->arena.release(c->ogap);
     c->ctx->arena.release(c->okey);
+    c->ctx->arena.release(c->korder);
     c->ctx->arena.release(c->X);
     delete c;
     return MAPPER_OK;
@@ -2305,7 +2372,7 @@ extern "C" mapper_status mapper_knn_d2_noalloc(mapper_context *ctx, const float 
             HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
             HIPCHK(hipMemsetAsync(flags + 2, 0, 4, s));
             HIPCHK(launch_knn_pass(prec, 2, ka, s));
-            HIPCHK(launch_knn_final(points, d, n, k, cand, ccnt, cmax, 0, out_d2, s));
+            HIPCHK(launch_knn_final(points, d, n, k, cand, ccnt, cmax, 0, nullptr, out_d2, s));
             HIPCHK(launch_max_i32(ccnt, n, (int32_t *)(flags + 2), s));
             int32_t most = 0;
             HIPCHK(hipMemcpyAsync(&most, flags + 2, 4, hipMemcpyDeviceToHost, s));

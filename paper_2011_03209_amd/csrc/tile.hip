@@ -792,7 +792,11 @@ k_knn(KnnArgs a) {
     const int64_t bl = block_linear();
     if (bl >= (int64_t)a.T * a.C) return;                  // a padding block of the 2-D grid
     const int I = (int)(bl / a.C), ch = (int)(bl % a.C);
-    const int J0 = (int)((int64_t)ch * a.T / a.C), J1 = (int)((int64_t)(ch + 1) * a.T / a.C);
+    // the column blocks of row block I: all of them, or its list (screened
+    // by the cloud's cells); chunk ch of C takes an even share
+    const int nJ = a.jlist ? a.jcount[I] : a.T;
+    const int J0 = (int)((int64_t)ch * nJ / a.C), J1 = (int)((int64_t)(ch + 1) * nJ / a.C);
+    const int32_t *jl = a.jlist ? a.jlist + (int64_t)I * a.T : nullptr;
     const int r = threadIdx.x & (TILE - 1), qtr = threadIdx.x >> 7;
     const int64_t grow = (int64_t)I * TILE + r;
     const bool rvalid = grow < a.n;
@@ -811,7 +815,8 @@ k_knn(KnnArgs a) {
         hI[threadIdx.x] = hsrc[gi < a.n ? gi : a.n - 1];
     }
 #pragma unroll 1
-    for (int J = J0; J < J1; ++J) {
+    for (int jp = J0; jp < J1; ++jp) {
+        const int J = jl ? jl[jp] : jp;
         TilePos tl;
         tl.e = 0;
         tl.I = I;
@@ -908,18 +913,22 @@ __global__ void k_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 }
 
 // The exact answer: canonical FP64 D (x_j - y_j in FP64, fma in index
-// order) over row i's candidates, k-th smallest.
+// order) over row i's candidates, k-th smallest.  Rows and candidates are
+// slots; perm (null: the identity) gives each slot's point, and the result
+// goes to the point's entry.
 __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out) {
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int cnt = ccnt[i] < cmax ? ccnt[i] : cmax;
     double best[KNN_KMAX];
 #pragma unroll
     for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inf();
-    const float *x = X + i * d;
+    const int64_t pi = perm ? (int64_t)perm[i] : i;
+    const float *x = X + pi * d;
     for (int s = 0; s < cnt; ++s) {
-        const float *y = X + (int64_t)cand[i * cmax + s] * d;
+        const int64_t c = cand[i * cmax + s];
+        const float *y = X + (perm ? (int64_t)perm[c] : c) * d;
         double D = 0.0;
         for (int j = 0; j < d; ++j) {
             const double t = (double)x[j] - (double)y[j];
@@ -935,7 +944,64 @@ __global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
     double kth = best[0];
 #pragma unroll
     for (int q = 1; q < KNN_KMAX; ++q) kth = q == k - 1 ? best[q] : kth;
-    out[i] = mode == 1 ? -kth : kth;
+    out[pi] = mode == 1 ? -kth : kth;
+}
+
+// Column-block lists of the k-NN passes over slots in cell order: jlist[I *
+// T + p] (p < jcount[I]) = the column blocks J whose cells (cmask) meet
+// those row block I may need.  Pass 1 (thr null): the cells of I itself, so
+// that every row's k-th smallest upper bound comes from its own cells (an
+// upper bound of its k-th nearest distance all the same).  Pass 2: every
+// cell whose ball may lie within sqrt(tau) of a cell of I, tau the largest
+// of its rows' pass-1 bounds (scaled by inv_scale2 to the cloud's units,
+// with a margin): a block farther than that holds no point any row of I
+// needs (the triangle inequality on the cells' balls, and the canonical
+// FP64 distance at least (1 - (d + 8) 2^-52) times the exact one), so the
+// k-th smallest over the candidates is unchanged.  A row without a finite
+// bound keeps every block.  One wave per row block.
+__global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, const unsigned long long *__restrict__ cmask,
+                                                   const double *__restrict__ gap, int32_t nall,
+                                                   const float *__restrict__ thr, double inv_scale2, double shrink,
+                                                   int32_t *__restrict__ jlist, int32_t *__restrict__ jcount) {
+    const int64_t I = block_linear() * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (I >= T) return;                                      // the whole wave leaves together
+    const unsigned long long cI = cmask[I];
+    unsigned long long nm = cI;
+    if (thr) {
+        float t = 0.0f;
+        for (int r = lane; r < TILE; r += WAVE) {
+            const int64_t row = I * TILE + r;
+            if (row < n) t = fmaxf(t, thr[row]);
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) t = fmaxf(t, __shfl_xor(t, o, WAVE));
+        if (!(t < __builtin_inff())) {
+            nm = ~0ull;
+        } else {
+            const double tau = (double)t * inv_scale2 * (1.0 + 0x1.0p-20);
+            bool near = false;
+            if (lane < nall) {
+                unsigned long long m = cI;
+                while (m) {
+                    const int ca = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const double g = gap[(int64_t)ca * nall + lane];
+                    if (!(ca != lane && g > 0.0 && g * g * shrink > tau)) near = true;
+                }
+            }
+            nm = __ballot(near);
+        }
+    }
+    int cnt = 0;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
+    for (int J0 = 0; J0 < T; J0 += WAVE) {
+        const int J = J0 + lane;
+        const bool keep = J < T && (nm & cmask[J]) != 0;
+        const uint64_t b = __ballot(keep);
+        if (keep) jlist[I * T + cnt + __popcll(b & below)] = J;
+        cnt += __popcll(b);
+    }
+    if (lane == 0) jcount[I] = cnt;
 }
 
 // Band records from the band masks of the tile pair form: one wave per
@@ -1092,8 +1158,20 @@ hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 }
 
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, int32_t mode, double *out, hipStream_t s) {
-    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, out);
+                            const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out,
+                            hipStream_t s) {
+    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, perm,
+                                                                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_lists(int32_t T, int64_t n, const unsigned long long *cmask, const double *gap, int32_t nall,
+                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
+                            hipStream_t s) {
+    if (T <= 0) return hipSuccess;
+    if (nall < 1 || nall > CELL_MAX) return hipErrorInvalidValue;
+    k_knn_lists<<<grid_2d(((int64_t)T + 3) / 4), dim3(256), 0, s>>>(T, n, cmask, gap, nall, thr, inv_scale2, shrink,
+                                                                      jlist, jcount);
     return hipGetLastError();
 }
 

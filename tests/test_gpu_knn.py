@@ -48,8 +48,20 @@ def test_shapes(ctx, n, d, k, prec):
 
 
 def test_mixture_d256(ctx):
+    """A clustered cloud: the passes take only the column blocks the cells
+    leave (far fewer than the whole grid), and the values are the oracle's."""
     X = synth.mixture_1m_d256(scale=0.012).X                       # 12000 x 256
-    run(ctx, X, 5, synth.PREC_BF16X3)
+    st = run(ctx, X, 5, synth.PREC_BF16X3)
+    T = (X.shape[0] + 127) // 128
+    assert st["tiles"] < T * T, (st["tiles"], 2 * T * T)
+
+
+@pytest.mark.parametrize("k", [1, 5, 16])
+def test_background_outliers(ctx, k):
+    """Clusters with a uniform background (the outlier cell, near every cell):
+    the screened passes still find every row's k-th nearest exactly."""
+    X = synth.mixture_500k_d128_2d(scale=0.02).X                   # 10500 x 128, 5% background
+    run(ctx, X, k, synth.PREC_FP16)
 
 
 def test_duplicates_grow_candidate_lists(ctx):
@@ -111,3 +123,5 @@ def test_knn_100k_d256_sampled(ctx):
     assert np.array_equal(got[rows], O.knn_d2_rows(X, 5, rows))
     assert np.all(np.isfinite(got)) and np.all(got > 0)
     assert st["band_pairs"] >= 5 * X.shape[0]
+    T = (X.shape[0] + 127) // 128
+    assert st["tiles"] < 0.2 * 2 * T * T, (st["tiles"], 2 * T * T)     # screened by the cells
