@@ -415,10 +415,11 @@ hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
                             const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out,
                             hipStream_t s);
 // Column-block lists of the screened k-NN passes (k_knn_lists): cmask per row
-// block, gap the cells' nall x nall ball gaps (device), thr null for pass 1.
-hipError_t launch_knn_lists(int32_t T, int64_t n, const unsigned long long *cmask, const double *gap, int32_t nall,
-                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
-                            hipStream_t s);
+// block, gap and far the lower and upper bounds of the distance between two
+// cells' points (nall x nall, device), thr null for pass 1; mode as k_knn.
+hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask, const double *gap,
+                            const double *far, int32_t nall, const float *thr, double inv_scale2, double shrink,
+                            int32_t *jlist, int32_t *jcount, hipStream_t s);
 // f[i] = sqrt(f[i]) (correctly rounded FP64).
 hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <deque>
 #include <exception>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -294,6 +295,7 @@ struct mapper_cloud {
     int32_t cell_bits = 0;             // bits of okey in the binning key
     int32_t ncell = 0;
     std::vector<double> cell_gap;      // ncell x ncell: lower bound of the distance between two cells' points
+    std::vector<double> cell_far;      // ncell x ncell: upper bound of it (+inf where the outlier cell takes part)
                                        // before eps (landmark distance - both radii), FP64
     std::atomic<int> inflight{0};
     mutable double med_norm2 = -1.0;   // median squared row norm (autotuner key; under tune_mu)
@@ -618,9 +620,9 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     st.split_terms = prec_is_split(prec) ? 3 : 1;
     st.pairs = n * (n - 1);
     st.tiles = 2 * (int64_t)T * T;
-    // screening by the cloud's cells (k-th smallest only): slots in cell
-    // order, per row block the column blocks its rows may need (k_knn_lists)
-    const bool screen = mode == 0 && cloud->korder && cloud->cell && d <= BALL_DMAX && cloud->ncell >= 2 &&
+    // screening by the cloud's cells: slots in cell order, per row block the
+    // column blocks its rows may need (k_knn_lists)
+    const bool screen = cloud->korder && cloud->cell && d <= BALL_DMAX && cloud->ncell >= 2 &&
                         (int64_t)T * T <= (1ll << 28);
     const uint32_t *slots = nullptr;
     if (screen) {
@@ -691,11 +693,13 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
         HIPCHK(hipMemsetAsync(near0, 0, CELL_MAX * 8, s));
         HIPCHK(launch_tile_cells(slots, eo, rbo, 1, T, cloud->cell, nullptr, nall - 1, shrink, 0.0, near0, cmask,
                                  nmask, s));
-        dgap = mem.get<double>((uint64_t)nall * nall);
+        dgap = mem.get<double>(2 * (uint64_t)nall * nall);      // the gap table, then the far table
         h2d(dgap, cloud->cell_gap.data(), (int64_t)nall * nall, s);
+        h2d(dgap + (size_t)nall * nall, cloud->cell_far.data(), (int64_t)nall * nall, s);
         jlist = mem.get<int32_t>((uint64_t)T * T);
         jcount = mem.get<int32_t>(T);
-        HIPCHK(launch_knn_lists(T, n, cmask, dgap, nall, nullptr, 0.0, shrink, jlist, jcount, s));
+        HIPCHK(launch_knn_lists(T, n, mode, cmask, dgap, dgap + (size_t)nall * nall, nall, nullptr, 0.0, shrink, jlist,
+                                jcount, s));
         ka.jlist = jlist;
         ka.jcount = jcount;
         tiles1 = list_sum();
@@ -706,25 +710,25 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
     int64_t tiles2 = (int64_t)T * T;
     if (screen) {
-        HIPCHK(launch_knn_lists(T, n, cmask, dgap, nall, thr, 1.0 / (scale * scale), shrink, jlist, jcount, s));
+        HIPCHK(launch_knn_lists(T, n, mode, cmask, dgap, dgap + (size_t)nall * nall, nall, thr, 1.0 / (scale * scale),
+                                shrink, jlist, jcount, s));
     }
     ev.mark();
     if (screen) tiles2 = list_sum();
     st.tiles = tiles1 + tiles2;
-    int32_t cmax = 64;
+    // candidate lists: up to 256 MiB at first (1024 entries at most); a row
+    // with more candidates than that redoes pass 2 with lists as long as it
+    int32_t cmax = (int32_t)std::max<int64_t>(64, std::min<int64_t>(1024, (int64_t)(256 << 20) / (4 * n)));
     int32_t *ccnt = mem.get<int32_t>(n);
     int64_t ncand = 0;
     for (;;) {
-        Scope cm(ctx->arena, s);
-        ka.cand = cm.get<int32_t>((uint64_t)n * cmax);
+        ka.cand = mem.get<int32_t>((uint64_t)n * cmax);
         ka.ccnt = ccnt;
         ka.cmax = cmax;
         Events e2(s, ctx->events);
         e2.mark();
         HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
         HIPCHK(launch_knn_pass(prec, 2, ka, s));
-        e2.mark();
-        HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, mode, screen ? slots : nullptr, dout, s));
         e2.mark();
         std::vector<int32_t> cc;
         d2h(cc, ccnt, n, s);
@@ -736,11 +740,19 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
             ncand += cc[i];
         }
         st.ms_tiles = ev.ms(0, 1) + e2.ms(0, 1);
-        st.ms_recheck = e2.ms(1, 2);
         if (most <= cmax) break;
         if (most > (int64_t)0x7fffffff / std::max<int64_t>(n, 1)) throw NoMem{(uint64_t)most * (uint64_t)n * 4};
-        cmax = (int32_t)most;                           // grow the candidate lists and redo pass 2
+        mem.release(ka.cand);                           // the stream is idle: the lists go back at once
+        cmax = (int32_t)most;
         ++st.tile_launches;
+    }
+    {
+        Events e3(s, ctx->events);
+        e3.mark();
+        HIPCHK(launch_knn_final(cloud->X, d, n, k, ka.cand, ccnt, cmax, mode, screen ? slots : nullptr, dout, s));
+        e3.mark();
+        HIPCHK(hipStreamSynchronize(s));
+        st.ms_recheck = e3.ms(0, 1);
     }
     st.tile_launches += 1;
     st.band_pairs = ncand;
@@ -915,12 +927,13 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     ctx->arena.release(dl);
     ctx->arena.release(r2);
     c->cell_gap.assign((size_t)nall * nall, -1.0);
+    c->cell_far.assign((size_t)nall * nall, std::numeric_limits<double>::infinity());
     for (int a = 0; a < nc; ++a)
-        for (int b = 0; b < nc; ++b)
-            if (a != b)
-                c->cell_gap[(size_t)a * nall + b] =
-                    std::sqrt(dist2(chain[(size_t)a], chain[(size_t)b])) * (1.0 - 0x1.0p-40) - rad[(size_t)a] -
-                    rad[(size_t)b];
+        for (int b = 0; b < nc; ++b) {
+            const double dc = std::sqrt(dist2(chain[(size_t)a], chain[(size_t)b]));
+            if (a != b) c->cell_gap[(size_t)a * nall + b] = dc * (1.0 - 0x1.0p-40) - rad[(size_t)a] - rad[(size_t)b];
+            c->cell_far[(size_t)a * nall + b] = dc * (1.0 + 0x1.0p-40) + rad[(size_t)a] + rad[(size_t)b];
+        }
     // the slot order key: cell, then (outliers) the gap in 256 quantiles
     // ascending, so that for any eps the outliers within eps of a landmark
     // cell come first in their element and the far ones fill row blocks of
@@ -2299,6 +2312,13 @@ extern "C" mapper_status mapper_knn_d2_noalloc(mapper_context *ctx, const float 
     int32_t cmax = 64;
     while (C > 1 && knn_scratch_bytes(n, d, prec, T, C, cmax) > NOALLOC_SCRATCH_BYTES) --C;
     const uint64_t need = knn_scratch_bytes(n, d, prec, T, C, cmax);
+    if (need <= NOALLOC_SCRATCH_BYTES) {
+        // longer lists where the array has room (up to 1024 entries): a row
+        // with more candidates than the lists hold redoes pass 2
+        const uint64_t rest = NOALLOC_SCRATCH_BYTES - knn_scratch_bytes(n, d, prec, T, C, 0);
+        const uint64_t fit = rest > 256 ? (rest - 256) / ((uint64_t)n * 4) : 0;
+        cmax = (int32_t)std::max<uint64_t>(64, std::min<uint64_t>(1024, fit));
+    }
     if (need > NOALLOC_SCRATCH_BYTES) {
         char msg[160];
         std::snprintf(msg, sizeof msg, "n x d too large for the no-alloc scratch: needs %llu bytes, the array holds %llu",
@@ -2372,12 +2392,15 @@ extern "C" mapper_status mapper_knn_d2_noalloc(mapper_context *ctx, const float 
             HIPCHK(hipMemsetAsync(ccnt, 0, (size_t)n * 4, s));
             HIPCHK(hipMemsetAsync(flags + 2, 0, 4, s));
             HIPCHK(launch_knn_pass(prec, 2, ka, s));
-            HIPCHK(launch_knn_final(points, d, n, k, cand, ccnt, cmax, 0, nullptr, out_d2, s));
             HIPCHK(launch_max_i32(ccnt, n, (int32_t *)(flags + 2), s));
             int32_t most = 0;
             HIPCHK(hipMemcpyAsync(&most, flags + 2, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (most <= cmax) break;
+            if (most <= cmax) {
+                HIPCHK(launch_knn_final(points, d, n, k, cand, ccnt, cmax, 0, nullptr, out_d2, s));
+                HIPCHK(hipStreamSynchronize(s));
+                break;
+            }
             // longer candidate lists: the rest of the array, or an error
             if ((uint64_t)most * (uint64_t)n * 4 > NOALLOC_SCRATCH_BYTES - cand_off)
                 return fail(MAPPER_EINVAL, "candidate lists exceed the no-alloc scratch (many equal distances)");

@@ -912,84 +912,227 @@ __global__ void k_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
     thr[i] = kth;
 }
 
-// The exact answer: canonical FP64 D (x_j - y_j in FP64, fma in index
-// order) over row i's candidates, k-th smallest.  Rows and candidates are
+// The exact answer: the k-th smallest canonical FP64 D (x_j - y_j in FP64,
+// fma in index order) over row i's candidates.  Rows and candidates are
 // slots; perm (null: the identity) gives each slot's point, and the result
-// goes to the point's entry.
-__global__ void k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
-                            const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int cnt = ccnt[i] < cmax ? ccnt[i] : cmax;
-    double best[KNN_KMAX];
+// goes to the point's entry.  One wave per row.  Each candidate's D is first
+// summed in any order (lanes over the coordinates, a tree across the wave,
+// the candidate's row read whole at once): that sum a lies within e = cf a / 2
+// of the canonical chain (the bound of k_recheck, whose cf has a factor 2
+// of margin).  With A the k-th smallest a, U = A (1 + cf) and L = A (1 - cf):
+// a candidate with a (1 - cf) > U is not among the k smallest (k candidates
+// lie at or below U), and one with a (1 + cf) < L is surely among the first
+// k - 1 (fewer than k lie below A (1 - cf / 2)), so the answer is the
+// (k - below)-th smallest canonical D of the rest, which alone take the
+// canonical chain: one per row unless values nearly tie.  Signed values
+// (-a, -D) in mode 1, with the same rules on |v|.
+constexpr int KF_RG = 4;                 // candidates summed together (their row loads in flight at once)
+
+template <int KM>
+__device__ __forceinline__ void topk_insert_d(double (&b)[KM], double u) {
 #pragma unroll
-    for (int q = 0; q < KNN_KMAX; ++q) best[q] = __builtin_inf();
-    const int64_t pi = perm ? (int64_t)perm[i] : i;
-    const float *x = X + pi * d;
-    for (int s = 0; s < cnt; ++s) {
-        const int64_t c = cand[i * cmax + s];
-        const float *y = X + (perm ? (int64_t)perm[c] : c) * d;
-        double D = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const double t = (double)x[j] - (double)y[j];
-            D = __builtin_fma(t, t, D);
+    for (int q = KM - 1; q > 0; --q) b[q] = fmin(b[q], fmax(b[q - 1], u));
+    b[0] = fmin(b[0], u);
+}
+
+template <int KM>
+__device__ __forceinline__ double pick_d(const double (&b)[KM], int k) {
+    double v = b[0];                                         // b ascending: b[k - 1] = max(b[0 .. k - 1])
+#pragma unroll
+    for (int q = 1; q < KM; ++q) v = fmax(v, q < k ? b[q] : b[0]);
+    return v;
+}
+
+// the wave's sums of (x_j - y_j)^2 for KF_RG rows y (every lane gets them)
+__device__ __forceinline__ void knn_wave_sums(const float *x, const float *const (&y)[KF_RG], int32_t d, int lane,
+                                              double (&s)[KF_RG]) {
+#pragma unroll
+    for (int i = 0; i < KF_RG; ++i) s[i] = 0.0;
+    for (int j0 = 0; j0 < d; j0 += 4 * WAVE) {
+        float xv[4], yv[KF_RG][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + q * WAVE + lane;
+            const int jj = j < d ? j : d - 1;                // in bounds; the term is dropped below
+            xv[q] = x[jj];
+#pragma unroll
+            for (int i = 0; i < KF_RG; ++i) yv[i][q] = y[i][jj];
         }
-        if (mode == 1) D = -D;
-        if (D < best[KNN_KMAX - 1]) {
 #pragma unroll
-            for (int q = KNN_KMAX - 1; q > 0; --q) best[q] = fmin(best[q], fmax(best[q - 1], D));
-            best[0] = fmin(best[0], D);
+        for (int q = 0; q < 4; ++q) {
+            const bool live = j0 + q * WAVE + lane < d;
+#pragma unroll
+            for (int i = 0; i < KF_RG; ++i) {
+                const double t = live ? (double)xv[q] - (double)yv[i][q] : 0.0;
+                s[i] = __builtin_fma(t, t, s[i]);
+            }
         }
     }
-    double kth = best[0];
 #pragma unroll
-    for (int q = 1; q < KNN_KMAX; ++q) kth = q == k - 1 ? best[q] : kth;
-    out[pi] = mode == 1 ? -kth : kth;
+    for (int o = WAVE / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < KF_RG; ++i) s[i] += __shfl_xor(s[i], o, WAVE);
+}
+
+template <int KM>
+__global__ void __launch_bounds__(256) k_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
+                                                   const int32_t *ccnt, int32_t cmax, int32_t mode,
+                                                   const uint32_t *perm, double *out) {
+    const int64_t i = block_linear() * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= n) return;                                      // the whole wave leaves together
+    const int cnt = ccnt[i] < cmax ? ccnt[i] : cmax;
+    const int64_t pi = perm ? (int64_t)perm[i] : i;
+    const float *x = X + pi * d;
+    const int32_t *ci = cand + i * (int64_t)cmax;
+    const double u = 0x1.0p-53;
+    const double gd = (d + 4) * u / (1.0 - (d + 4) * u);
+    const double cf = 4.0 * gd / (1.0 - gd);
+    const double sg = mode == 1 ? -1.0 : 1.0;
+    auto rows = [&](int c0, const float *(&y)[KF_RG]) {
+#pragma unroll
+        for (int q = 0; q < KF_RG; ++q) {
+            const int c = c0 + q < cnt ? c0 + q : cnt - 1;   // past the end: the last candidate again
+            const int64_t sc = ci[c];
+            y[q] = X + (perm ? (int64_t)perm[sc] : sc) * d;
+        }
+    };
+    // the k smallest signed sums; lane c keeps candidate c's
+    double bv[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) bv[q] = __builtin_inf();
+    double mine = 0.0;
+    for (int c0 = 0; c0 < cnt; c0 += KF_RG) {
+        const float *y[KF_RG];
+        rows(c0, y);
+        double sm[KF_RG];
+        knn_wave_sums(x, y, d, lane, sm);
+#pragma unroll
+        for (int q = 0; q < KF_RG; ++q) {
+            if (c0 + q < cnt) {
+                topk_insert_d<KM>(bv, sg * sm[q]);
+                if (lane == c0 + q) mine = sg * sm[q];
+            }
+        }
+    }
+    const double A = pick_d<KM>(bv, k);
+    const double U = A + cf * fabs(A), L = A - cf * fabs(A);
+    int below = 0;
+    double best[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) best[q] = __builtin_inf();
+    for (int c0 = 0; c0 < cnt; c0 += KF_RG) {
+        double v[KF_RG];
+        if (c0 < WAVE) {                                     // kept from the first sweep
+#pragma unroll
+            for (int q = 0; q < KF_RG; ++q) v[q] = __shfl(mine, c0 + q, WAVE);
+        } else {                                             // summed again
+            const float *y[KF_RG];
+            rows(c0, y);
+            double sm[KF_RG];
+            knn_wave_sums(x, y, d, lane, sm);
+#pragma unroll
+            for (int q = 0; q < KF_RG; ++q) v[q] = sg * sm[q];
+        }
+#pragma unroll
+        for (int q = 0; q < KF_RG; ++q) {
+            if (c0 + q >= cnt) break;
+            const double e = cf * fabs(v[q]);
+            if (v[q] + e < L) {
+                ++below;
+            } else if (v[q] - e <= U) {                      // the canonical chain decides
+                const int64_t sc = ci[c0 + q];
+                const float *y = X + (perm ? (int64_t)perm[sc] : sc) * d;
+                double D = 0.0;
+                if (lane == 0)
+                    for (int32_t j = 0; j < d; ++j) {
+                        const double t = (double)x[j] - (double)y[j];
+                        D = __builtin_fma(t, t, D);
+                    }
+                topk_insert_d<KM>(best, sg * __shfl(D, 0, WAVE));
+            }
+        }
+    }
+    const double kth = pick_d<KM>(best, k - below);
+    if (lane == 0) out[pi] = sg * kth;
 }
 
 // Column-block lists of the k-NN passes over slots in cell order: jlist[I *
 // T + p] (p < jcount[I]) = the column blocks J whose cells (cmask) meet
-// those row block I may need.  Pass 1 (thr null): the cells of I itself, so
-// that every row's k-th smallest upper bound comes from its own cells (an
-// upper bound of its k-th nearest distance all the same).  Pass 2: every
+// those row block I may need.  Any set of columns gives pass 1 a valid
+// bound (an upper bound of the k-th smallest, a lower bound of the
+// largest), and pass 2 must keep every block that may hold a point a row
+// of I needs; gap and far are the lower and upper bounds of the distance
+// between two cells' points (nall x nall; far +inf where the outlier cell
+// takes part, gap not positive where it says nothing), and the canonical
+// FP64 distance lies within a factor 1 -+ (d + 8) 2^-52 (shrink, 2 - shrink)
+// of the exact one.
+//   mode 0 (k-th smallest), pass 1: the cells of I itself.  Pass 2: every
 // cell whose ball may lie within sqrt(tau) of a cell of I, tau the largest
-// of its rows' pass-1 bounds (scaled by inv_scale2 to the cloud's units,
-// with a margin): a block farther than that holds no point any row of I
-// needs (the triangle inequality on the cells' balls, and the canonical
-// FP64 distance at least (1 - (d + 8) 2^-52) times the exact one), so the
-// k-th smallest over the candidates is unchanged.  A row without a finite
-// bound keeps every block.  One wave per row block.
-__global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, const unsigned long long *__restrict__ cmask,
-                                                   const double *__restrict__ gap, int32_t nall,
-                                                   const float *__restrict__ thr, double inv_scale2, double shrink,
-                                                   int32_t *__restrict__ jlist, int32_t *__restrict__ jcount) {
+// of its rows' pass-1 bounds: a block farther than that holds no point
+// within any row's k-th smallest bound.
+//   mode 1 (the largest), pass 1: for each cell a of I, every cell whose
+// far bound from a reaches the largest gap from a (the others cannot hold
+// a row's farthest point, so the bound loses little).  Pass 2: every cell
+// that may reach sqrt(tau) from a cell of I, tau the smallest of its rows'
+// pass-1 bounds: a block nearer than that holds no point at the largest
+// distance of any row.
+// thr is in panel units (inv_scale2 converts, with a margin of 2^-20); a
+// row without a finite bound, or a cell of I that the tables say nothing
+// about, keeps every block.  One wave per row block.
+__global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, int32_t mode,
+                                                   const unsigned long long *__restrict__ cmask,
+                                                   const double *__restrict__ gap, const double *__restrict__ far,
+                                                   int32_t nall, const float *__restrict__ thr, double inv_scale2,
+                                                   double shrink, int32_t *__restrict__ jlist,
+                                                   int32_t *__restrict__ jcount) {
     const int64_t I = block_linear() * 4 + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (I >= T) return;                                      // the whole wave leaves together
     const unsigned long long cI = cmask[I];
     unsigned long long nm = cI;
-    if (thr) {
-        float t = 0.0f;
+    if (!thr && mode == 1) {
+        bool keep = false;
+        unsigned long long m = cI;
+        while (m) {
+            const int ca = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            double g = lane < nall && lane != ca ? gap[(int64_t)ca * nall + lane] : -1.0;
+            for (int o = WAVE / 2; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, WAVE));
+            // every cell that may hold a point farther than the farthest
+            // cell's nearest point (all when the gaps say nothing)
+            if (lane < nall && !(g > 0.0 && far[(int64_t)ca * nall + lane] < g)) keep = true;
+        }
+        nm = __ballot(keep);
+    } else if (thr) {
+        float t = -__builtin_inff();
         for (int r = lane; r < TILE; r += WAVE) {
             const int64_t row = I * TILE + r;
             if (row < n) t = fmaxf(t, thr[row]);
         }
         for (int o = WAVE / 2; o > 0; o >>= 1) t = fmaxf(t, __shfl_xor(t, o, WAVE));
-        if (!(t < __builtin_inff())) {
+        const double tau = mode == 1 ? -(double)t * inv_scale2 * (1.0 - 0x1.0p-20)
+                                     : (double)t * inv_scale2 * (1.0 + 0x1.0p-20);
+        if (!(t < __builtin_inff()) || (mode == 1 && !(tau > 0.0))) {
             nm = ~0ull;
         } else {
-            const double tau = (double)t * inv_scale2 * (1.0 + 0x1.0p-20);
-            bool near = false;
+            const double grow = 2.0 - shrink;
+            bool keep = false;
             if (lane < nall) {
                 unsigned long long m = cI;
                 while (m) {
                     const int ca = __ffsll((long long)m) - 1;
                     m &= m - 1;
-                    const double g = gap[(int64_t)ca * nall + lane];
-                    if (!(ca != lane && g > 0.0 && g * g * shrink > tau)) near = true;
+                    if (mode == 1) {
+                        const double f = far[(int64_t)ca * nall + lane];
+                        if (!(f * f * grow < tau)) keep = true;
+                    } else {
+                        const double g = gap[(int64_t)ca * nall + lane];
+                        if (!(ca != lane && g > 0.0 && g * g * shrink > tau)) keep = true;
+                    }
                 }
             }
-            nm = __ballot(near);
+            nm = __ballot(keep);
         }
     }
     int cnt = 0;
@@ -1160,18 +1303,22 @@ hipError_t launch_knn_merge(const float *part, int32_t C, int32_t T, int64_t n, 
 hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, const int32_t *cand,
                             const int32_t *ccnt, int32_t cmax, int32_t mode, const uint32_t *perm, double *out,
                             hipStream_t s) {
-    k_knn_final<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, perm,
-                                                                       out);
+    if (n <= 0) return hipSuccess;
+    if (k <= 8)
+        k_knn_final<8><<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, perm, out);
+    else
+        k_knn_final<KNN_KMAX><<<grid_2d((n + 3) / 4), dim3(256), 0, s>>>(X, d, n, k, cand, ccnt, cmax, mode, perm,
+                                                                          out);
     return hipGetLastError();
 }
 
-hipError_t launch_knn_lists(int32_t T, int64_t n, const unsigned long long *cmask, const double *gap, int32_t nall,
-                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
-                            hipStream_t s) {
+hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask, const double *gap,
+                            const double *far, int32_t nall, const float *thr, double inv_scale2, double shrink,
+                            int32_t *jlist, int32_t *jcount, hipStream_t s) {
     if (T <= 0) return hipSuccess;
-    if (nall < 1 || nall > CELL_MAX) return hipErrorInvalidValue;
-    k_knn_lists<<<grid_2d(((int64_t)T + 3) / 4), dim3(256), 0, s>>>(T, n, cmask, gap, nall, thr, inv_scale2, shrink,
-                                                                      jlist, jcount);
+    if (nall < 1 || nall > CELL_MAX || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+    k_knn_lists<<<grid_2d(((int64_t)T + 3) / 4), dim3(256), 0, s>>>(T, n, mode, cmask, gap, far, nall, thr,
+                                                                      inv_scale2, shrink, jlist, jcount);
     return hipGetLastError();
 }
 

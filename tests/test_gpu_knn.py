@@ -64,11 +64,15 @@ def test_background_outliers(ctx, k):
     run(ctx, X, k, synth.PREC_FP16)
 
 
-def test_duplicates_grow_candidate_lists(ctx):
-    base = np.random.default_rng(4).normal(size=(30, 16)).astype(np.float32)
-    X = np.repeat(base, 100, axis=0)                               # 99 exact copies of every point
-    st = run(ctx, X, 5, synth.PREC_BF16)
-    assert st["tile_launches"] > 1, st
+@pytest.mark.parametrize("copies,k", [(100, 5), (1100, 5), (1100, 16)])
+def test_duplicates(ctx, copies, k):
+    """Exact copies: every candidate ties.  With 1099 copies of every point a
+    row has more candidates than the first lists hold (1024), and pass 2 runs
+    again with longer ones."""
+    base = np.random.default_rng(4).normal(size=(3000 // copies, 16)).astype(np.float32)
+    X = np.repeat(base, copies, axis=0)
+    st = run(ctx, X, k, synth.PREC_BF16)
+    assert st["tile_launches"] == (2 if copies > 1024 else 1), st
 
 
 def test_errors(ctx):
@@ -107,6 +111,26 @@ def test_cloud_lens_mapper(ctx, kind, k, prec):
     assert np.array_equal(g.edges, ref.edges)
     assert np.array_equal(g.edge_weights, ref.edge_weights)
     assert g.n_nodes > 1
+
+
+@pytest.mark.parametrize("which", ["mix_d256", "grid_d128_background"])
+def test_eccentricity_screened(ctx, which):
+    """The eccentricity lens on clustered clouds, where its passes take only
+    the blocks the cells leave (the farthest cells' blocks for the bound,
+    then those that may reach it; the background's cell keeps all): every
+    value is the square root of the oracle's largest distance, bit for bit."""
+    w = synth.mixture_1m_d256(scale=0.012) if which == "mix_d256" else synth.mixture_500k_d128_2d(scale=0.02)
+    X = w.X
+    params = synth.Params([synth.Axis(synth.LENS_ECCENTRICITY, 10, 0.3)], eps=w.params.eps,
+                          min_pts=w.params.min_pts, precision=synth.PREC_BF16X3)
+    print(f"[case] eccentricity {which} n={X.shape[0]} d={X.shape[1]}", flush=True)
+    cloud = ctx.cloud(X)
+    try:
+        g = cloud.run(params, debug=True)
+    finally:
+        cloud.destroy()
+    want = np.sqrt(O.ecc_d2(X))
+    assert np.array_equal(g.stages["lens"].reshape(-1).view(np.uint64), want.view(np.uint64))
 
 
 def test_knn_100k_d256_sampled(ctx):

@@ -5,8 +5,8 @@ MI355X).
 Both compute the exact k-th nearest-neighbour squared distances (the
 eps-selection module of the Use Cases section) with the same kernels; the
 no-alloc form keeps its work arrays in the library's static scratch array
-instead of the context arena.  Two calls in a row, the second smaller, must
-each equal the arena form bit for bit (the array keeps the first call's
+instead of the context arena.  Calls in a row, each smaller than the one
+before, must each equal the arena form bit for bit (the array keeps the first call's
 contents); an input too large for the array is refused before any launch.
 """
 import numpy as np
@@ -22,9 +22,14 @@ def test_noalloc_knn_matches_arena_form():
     ctx = binding.Context(arena_bytes=1 << 30)
     try:
         rng = np.random.default_rng(4242)
-        for n, d, k in ((20000, 256, 5), (3001, 64, 16)):
-            print(f"[case] noalloc knn n={n} d={d} k={k}", flush=True)
-            X, _ = synth.gaussian_mixture(rng, n, d, 12)
+        # the third: 1100 exact copies of two points, more candidates per row
+        # than the first lists hold, so pass 2 runs again in both forms
+        for n, d, k, copies in ((20000, 256, 5, 1), (3001, 64, 16, 1), (2200, 16, 5, 1100)):
+            print(f"[case] noalloc knn n={n} d={d} k={k} copies={copies}", flush=True)
+            if copies > 1:
+                X = np.repeat(rng.normal(size=(n // copies, d)).astype(np.float32), copies, axis=0)
+            else:
+                X, _ = synth.gaussian_mixture(rng, n, d, 12)
             cloud = ctx.cloud(X)
             try:
                 ref, _ = cloud.knn_d2(k)
