@@ -37,7 +37,8 @@ constexpr int CC = 32;        // columns per LDS slab
 __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X, int64_t n, int32_t d,
                                                      const float *__restrict__ landT,
                                                      const float *__restrict__ lnorm, int32_t ncell,
-                                                     const float *__restrict__ limit2, uint8_t *__restrict__ cell) {
+                                                     const float *__restrict__ limit2, uint8_t *__restrict__ cell,
+                                                     uint8_t *__restrict__ far) {
     __shared__ float tile[CB][CC + 1];
     const int64_t row0 = (int64_t)blockIdx.x * CB;
     float acc[CELL_MAX], nx = 0.f;
@@ -63,14 +64,16 @@ __global__ void __launch_bounds__(CB) k_assign_cells(const float *__restrict__ X
     }
     const int64_t my = row0 + threadIdx.x;
     if (my >= n) return;
-    int best = 0;
-    float bv = lnorm[0] - 2.f * acc[0];
+    int best = 0, worst = 0;
+    float bv = lnorm[0] - 2.f * acc[0], wv = bv;
 #pragma unroll
     for (int c = 1; c < CELL_MAX; ++c)
         if (c < ncell) {
             const float v = lnorm[c] - 2.f * acc[c];
             if (v < bv) { bv = v; best = c; }
+            if (v > wv) { wv = v; worst = c; }
         }
+    if (far) far[my] = (uint8_t)worst;                      // the farthest landmark (a hint, not a bound)
     // |x|^2 + bv is the squared distance to the landmark: beyond the cell's
     // limit the point goes to the outlier cell (id ncell)
     cell[my] = (uint8_t)(nx + bv > limit2[best] ? ncell : best);
@@ -339,11 +342,11 @@ hipError_t launch_compact_items(const TileItem *items, int64_t n, const uint8_t 
 }
 
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *landT, const float *lnorm,
-                               int32_t ncell, const float *limit2, uint8_t *cell, hipStream_t s) {
+                               int32_t ncell, const float *limit2, uint8_t *cell, uint8_t *far, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (ncell < 1 || ncell + 1 >= CELL_MAX) return hipErrorInvalidValue;
     k_assign_cells<<<dim3((unsigned)((n + CB - 1) / CB)), dim3(CB), 0, s>>>(X, n, d, landT, lnorm, ncell, limit2,
-                                                                          cell);
+                                                                          cell, far);
     return hipGetLastError();
 }
 

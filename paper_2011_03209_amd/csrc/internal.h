@@ -313,7 +313,7 @@ constexpr int CELL_LDS_FLOATS = 16384;
 // (squared distance); ncell + 1 < CELL_MAX.  landT: the landmarks
 // transposed, d x CELL_MAX (zero past ncell); lnorm[c] = |l_c|^2 (FP32).
 hipError_t launch_assign_cells(const float *X, int64_t n, int32_t d, const float *landT, const float *lnorm,
-                               int32_t ncell, const float *limit2, uint8_t *cell, hipStream_t s);
+                               int32_t ncell, const float *limit2, uint8_t *cell, uint8_t *far, hipStream_t s);
 // out[i] = squared distance from sample row i to its nearest other row.
 hipError_t launch_sample_nn2(const float *sub, int32_t m, int32_t d, float *out, hipStream_t s);
 // out[i] = items[i * n / m] with blk = i (an evenly strided sample of a tile
@@ -416,10 +416,13 @@ hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
                             hipStream_t s);
 // Column-block lists of the screened k-NN passes (k_knn_lists): cmask per row
 // block, gap and far the lower and upper bounds of the distance between two
-// cells' points (nall x nall, device), thr null for pass 1; mode as k_knn.
-hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask, const double *gap,
-                            const double *far, int32_t nall, const float *thr, double inv_scale2, double shrink,
-                            int32_t *jlist, int32_t *jcount, hipStream_t s);
+// cells' points (nall x nall, device), thr null for pass 1; mode as k_knn;
+// fmask (mode 1, pass 1; may be null) per row block the cells of its rows'
+// farthest landmarks.
+hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask,
+                            const unsigned long long *fmask, const double *gap, const double *far, int32_t nall,
+                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
+                            hipStream_t s);
 // f[i] = sqrt(f[i]) (correctly rounded FP64).
 hipError_t launch_sqrt(double *f, int64_t n, hipStream_t s);
 // items[i] = decoded tile pair i of the table (one thread per item).

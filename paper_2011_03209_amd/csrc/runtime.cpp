@@ -289,14 +289,15 @@ struct mapper_cloud {
     int32_t d = 0;
     float maxabs = 0.f;
     uint8_t *cell = nullptr;           // landmark cell of each point (locality order), or null
+    uint8_t *farcell = nullptr;        // per point: its farthest landmark's cell (the eccentricity's first pass)
     float *ogap = nullptr;             // per point of the outlier cell: distance bound to every landmark cell
     uint16_t *okey = nullptr;          // per point: cell << 8 | rank of its outlier gap (the slot order key)
     uint32_t *korder = nullptr;        // the points in okey order (stable): slots of the screened k-NN
     int32_t cell_bits = 0;             // bits of okey in the binning key
     int32_t ncell = 0;
     std::vector<double> cell_gap;      // ncell x ncell: lower bound of the distance between two cells' points
-    std::vector<double> cell_far;      // ncell x ncell: upper bound of it (+inf where the outlier cell takes part)
                                        // before eps (landmark distance - both radii), FP64
+    std::vector<double> cell_far;      // ncell x ncell: upper bound of it (+inf where the outlier cell takes part)
     std::atomic<int> inflight{0};
     mutable double med_norm2 = -1.0;   // median squared row norm (autotuner key; under tune_mu)
 };
@@ -666,7 +667,7 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     ka.part = mem.get<float>((uint64_t)C * T * TILE * 4 * KNN_KMAX);
     float *thr = mem.get<float>(n);
     ka.thr = thr;
-    unsigned long long *cmask = nullptr;
+    unsigned long long *cmask = nullptr, *fmask = nullptr;
     double *dgap = nullptr;
     int32_t *jlist = nullptr, *jcount = nullptr;
     const double shrink = 1.0 - ((double)d + 8.0) * 0x1.0p-52;
@@ -693,13 +694,18 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
         HIPCHK(hipMemsetAsync(near0, 0, CELL_MAX * 8, s));
         HIPCHK(launch_tile_cells(slots, eo, rbo, 1, T, cloud->cell, nullptr, nall - 1, shrink, 0.0, near0, cmask,
                                  nmask, s));
+        if (mode == 1 && cloud->farcell) {              // the cells of the rows' farthest landmarks
+            fmask = mem.get<unsigned long long>(T);
+            HIPCHK(launch_tile_cells(slots, eo, rbo, 1, T, cloud->farcell, nullptr, nall - 1, shrink, 0.0, near0,
+                                     fmask, nmask, s));
+        }
         dgap = mem.get<double>(2 * (uint64_t)nall * nall);      // the gap table, then the far table
         h2d(dgap, cloud->cell_gap.data(), (int64_t)nall * nall, s);
         h2d(dgap + (size_t)nall * nall, cloud->cell_far.data(), (int64_t)nall * nall, s);
         jlist = mem.get<int32_t>((uint64_t)T * T);
         jcount = mem.get<int32_t>(T);
-        HIPCHK(launch_knn_lists(T, n, mode, cmask, dgap, dgap + (size_t)nall * nall, nall, nullptr, 0.0, shrink, jlist,
-                                jcount, s));
+        HIPCHK(launch_knn_lists(T, n, mode, cmask, fmask, dgap, dgap + (size_t)nall * nall, nall, nullptr, 0.0,
+                                shrink, jlist, jcount, s));
         ka.jlist = jlist;
         ka.jcount = jcount;
         tiles1 = list_sum();
@@ -710,8 +716,8 @@ void knn_device(mapper_context *ctx, const mapper_cloud *cloud, int32_t k, int32
     HIPCHK(launch_knn_merge(ka.part, C, T, n, k, thr, s));
     int64_t tiles2 = (int64_t)T * T;
     if (screen) {
-        HIPCHK(launch_knn_lists(T, n, mode, cmask, dgap, dgap + (size_t)nall * nall, nall, thr, 1.0 / (scale * scale),
-                                shrink, jlist, jcount, s));
+        HIPCHK(launch_knn_lists(T, n, mode, cmask, nullptr, dgap, dgap + (size_t)nall * nall, nall, thr,
+                                1.0 / (scale * scale), shrink, jlist, jcount, s));
     }
     ev.mark();
     if (screen) tiles2 = list_sum();
@@ -872,10 +878,12 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     }
     std::memcpy(land.data() + (size_t)nc * d, limit2.data(), (size_t)nc * 4);
     uint8_t *cell = (uint8_t *)ctx->arena.alloc((uint64_t)n);
+    uint8_t *farc = (uint8_t *)ctx->arena.alloc((uint64_t)n);
     float *dl = (float *)ctx->arena.alloc((uint64_t)land.size() * 4);
     unsigned long long *r2 = (unsigned long long *)ctx->arena.alloc((uint64_t)CELL_MAX * 8);
-    if (!cell || !dl || !r2) {                                  // no room: keep point order
+    if (!cell || !farc || !dl || !r2) {                         // no room: keep point order
         ctx->arena.release(cell);
+        ctx->arena.release(farc);
         ctx->arena.release(dl);
         ctx->arena.release(r2);
         return;
@@ -884,7 +892,7 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     std::vector<unsigned long long> r2h((size_t)CELL_MAX, 0);
     try {
         HIPCHK(hipMemcpyAsync(dl, land.data(), land.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_assign_cells(c->X, n, d, dlt, dln, nc, dlim, cell, s));
+        HIPCHK(launch_assign_cells(c->X, n, d, dlt, dln, nc, dlim, cell, farc, s));
         HIPCHK(hipMemsetAsync(r2, 0, (size_t)CELL_MAX * 8, s));
         HIPCHK(launch_cell_radius(c->X, n, d, dl, nc, cell, r2, s));
         HIPCHK(hipMemcpyAsync(r2h.data(), r2, (size_t)CELL_MAX * 8, hipMemcpyDeviceToHost, s));
@@ -892,6 +900,7 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
     } catch (DevError &) {
         (void)hipStreamSynchronize(s);
         ctx->arena.release(cell);
+        ctx->arena.release(farc);
         ctx->arena.release(dl);
         ctx->arena.release(r2);
         throw;
@@ -919,6 +928,7 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
             (void)hipStreamSynchronize(s);
             ctx->arena.release(ogap);
             ctx->arena.release(cell);
+            ctx->arena.release(farc);
             ctx->arena.release(dl);
             ctx->arena.release(r2);
             throw;
@@ -980,16 +990,19 @@ void build_cells(mapper_context *ctx, mapper_cloud *c, hipStream_t s) {
             ctx->arena.release(okey);
             ctx->arena.release(ogap);
             ctx->arena.release(cell);
+            ctx->arena.release(farc);
             throw;
         }
     }
     if (!okey) {                                                // no room: keep point order
         ctx->arena.release(ogap);
         ctx->arena.release(cell);
+        ctx->arena.release(farc);
         return;
     }
     c->ncell = nall;
     c->cell = cell;
+    c->farcell = farc;
     c->ogap = ogap;
     c->okey = okey;
     c->korder = korder;
@@ -1962,6 +1975,7 @@ mapper_status mapper_cloud_destroy(mapper_cloud *c) {
     if (!c) return fail(MAPPER_EINVAL, "null cloud");
     if (c->inflight.load() > 0) return fail(MAPPER_EBUSY, "cloud has requests in flight");
     c->ctx->arena.release(c->cell);
+    c->ctx->arena.release(c->farcell);
     c->ctx->arena.release(c->ogap);
     c->ctx->arena.release(c->okey);
     c->ctx->arena.release(c->korder);

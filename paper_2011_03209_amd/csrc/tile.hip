@@ -1071,17 +1071,21 @@ __global__ void __launch_bounds__(256) k_knn_final(const float *X, int32_t d, in
 // cell whose ball may lie within sqrt(tau) of a cell of I, tau the largest
 // of its rows' pass-1 bounds: a block farther than that holds no point
 // within any row's k-th smallest bound.
-//   mode 1 (the largest), pass 1: for each cell a of I, every cell whose
+//   mode 1 (the largest), pass 1: the cells of the farthest landmarks of
+// I's rows (fmask; a row's farthest point usually lies there, so the bound
+// loses little), or without fmask, for each cell a of I every cell whose
 // far bound from a reaches the largest gap from a (the others cannot hold
-// a row's farthest point, so the bound loses little).  Pass 2: every cell
+// a row's farthest point).  Pass 2: every cell
 // that may reach sqrt(tau) from a cell of I, tau the smallest of its rows'
 // pass-1 bounds: a block nearer than that holds no point at the largest
 // distance of any row.
-// thr is in panel units (inv_scale2 converts, with a margin of 2^-20); a
-// row without a finite bound, or a cell of I that the tables say nothing
-// about, keeps every block.  One wave per row block.
+// Pass 1 also takes blocks I - 1 .. I + 1.  thr is in panel units
+// (inv_scale2 converts, with a margin of 2^-20); a row without a finite
+// bound, or a cell of I that the tables say nothing about, keeps every
+// block.  One wave per row block.
 __global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, int32_t mode,
                                                    const unsigned long long *__restrict__ cmask,
+                                                   const unsigned long long *__restrict__ fmask,
                                                    const double *__restrict__ gap, const double *__restrict__ far,
                                                    int32_t nall, const float *__restrict__ thr, double inv_scale2,
                                                    double shrink, int32_t *__restrict__ jlist,
@@ -1091,7 +1095,9 @@ __global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, int32_t
     if (I >= T) return;                                      // the whole wave leaves together
     const unsigned long long cI = cmask[I];
     unsigned long long nm = cI;
-    if (!thr && mode == 1) {
+    if (!thr && mode == 1 && fmask) {
+        nm = fmask[I];
+    } else if (!thr && mode == 1) {
         bool keep = false;
         unsigned long long m = cI;
         while (m) {
@@ -1139,7 +1145,10 @@ __global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, int32_t
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
     for (int J0 = 0; J0 < T; J0 += WAVE) {
         const int J = J0 + lane;
-        const bool keep = J < T && (nm & cmask[J]) != 0;
+        // pass 1 also takes the neighbouring blocks I - 1 .. I + 1: with
+        // them every row sees at least 128 others, so each pass-1 bound is
+        // finite even where a row's own cells hold fewer than k points
+        const bool keep = J < T && ((nm & cmask[J]) != 0 || (!thr && J >= I - 1 && J <= I + 1));
         const uint64_t b = __ballot(keep);
         if (keep) jlist[I * T + cnt + __popcll(b & below)] = J;
         cnt += __popcll(b);
@@ -1312,12 +1321,13 @@ hipError_t launch_knn_final(const float *X, int32_t d, int64_t n, int32_t k, con
     return hipGetLastError();
 }
 
-hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask, const double *gap,
-                            const double *far, int32_t nall, const float *thr, double inv_scale2, double shrink,
-                            int32_t *jlist, int32_t *jcount, hipStream_t s) {
+hipError_t launch_knn_lists(int32_t T, int64_t n, int32_t mode, const unsigned long long *cmask,
+                            const unsigned long long *fmask, const double *gap, const double *far, int32_t nall,
+                            const float *thr, double inv_scale2, double shrink, int32_t *jlist, int32_t *jcount,
+                            hipStream_t s) {
     if (T <= 0) return hipSuccess;
     if (nall < 1 || nall > CELL_MAX || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
-    k_knn_lists<<<grid_2d(((int64_t)T + 3) / 4), dim3(256), 0, s>>>(T, n, mode, cmask, gap, far, nall, thr,
+    k_knn_lists<<<grid_2d(((int64_t)T + 3) / 4), dim3(256), 0, s>>>(T, n, mode, cmask, fmask, gap, far, nall, thr,
                                                                       inv_scale2, shrink, jlist, jcount);
     return hipGetLastError();
 }

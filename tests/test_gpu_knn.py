@@ -64,6 +64,22 @@ def test_background_outliers(ctx, k):
     run(ctx, X, k, synth.PREC_FP16)
 
 
+def test_isolated_last_block(ctx):
+    """Three isolated points (the outlier cell) end the slot order alone in
+    the last row block, whose own cells hold fewer than k others: pass 1
+    also takes the neighbouring blocks, so their bounds stay finite and no
+    row takes every column as a candidate."""
+    rng = np.random.default_rng(31)
+    centers = rng.normal(scale=20.0, size=(10, 16))
+    X = (centers[rng.integers(0, 10, 1280)] + rng.normal(size=(1280, 16))).astype(np.float32)
+    far = (rng.normal(size=(3, 16)) * 1000.0).astype(np.float32)
+    X = np.concatenate([X, far])                                   # 1283 = 10 x 128 + 3
+    st = run(ctx, X, 5, synth.PREC_FP16)
+    assert st["tiles"] < 2 * 11 * 11, st                          # the screened passes ran
+    assert st["tile_launches"] == 1, st
+    assert st["band_pairs"] < 100 * X.shape[0], st
+
+
 @pytest.mark.parametrize("copies,k", [(100, 5), (1100, 5), (1100, 16)])
 def test_duplicates(ctx, copies, k):
     """Exact copies: every candidate ties.  With 1099 copies of every point a
