@@ -89,10 +89,31 @@ __global__ void __launch_bounds__(SB) k_scan_down(const T *in, int64_t n, const 
     }
 }
 
+// The whole scan in one block (n <= ST): one launch instead of three.
+template <typename T>
+__global__ void __launch_bounds__(SB) k_scan_small(const T *in, int64_t n, int64_t *out) {
+    const int64_t base = (int64_t)threadIdx.x * SI;
+    int64_t v[SI], s = 0;
+#pragma unroll
+    for (int k = 0; k < SI; ++k) { v[k] = ld_item(in, base + k, n); s += v[k]; }
+    int64_t tot;
+    int64_t ex = block_exclusive(s, &tot);
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
 template <typename T>
 hipError_t scan_impl(const T *in, int64_t *out, int64_t n, void *temp, hipStream_t s) {
     int64_t *part = (int64_t *)temp;
     const int64_t nb = (n + ST - 1) / ST;
+    if (nb <= 1) {
+        k_scan_small<T><<<1, SB, 0, s>>>(in, n, out);
+        return hipGetLastError();
+    }
     if (nb > 0) {
         k_scan_reduce<T><<<dim3((unsigned)nb), dim3(SB), 0, s>>>(in, n, part);
     }
@@ -178,6 +199,79 @@ __global__ void __launch_bounds__(SB) k_radix_scatter(const uint64_t *keys, cons
     }
 }
 
+// The whole sort in one block (n <= ST): every pass ranks the items as
+// k_radix_scatter does, with the digit offsets from the block's own counts,
+// and scatters them into LDS; the sorted pairs are written back in place.
+// One launch instead of five per pass.
+__global__ void __launch_bounds__(SB) k_radix_small(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits) {
+    __shared__ int32_t wcount[SB / WAVE][256];
+    __shared__ int32_t doff[256];
+    __shared__ uint64_t sk[ST];
+    __shared__ uint32_t sv[ST];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int64_t base = (int64_t)w * (SI * WAVE);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t i = threadIdx.x; i < n; i += SB) {
+        sk[i] = keys[i];
+        sv[i] = vals[i];
+    }
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        for (int k = threadIdx.x; k < (SB / WAVE) * 256; k += SB) (&wcount[0][0])[k] = 0;
+        __syncthreads();                                     // the items (loaded or scattered) are in LDS
+        int rank[SI], dig[SI];
+        uint64_t key[SI];
+        uint32_t val[SI];
+#pragma unroll
+        for (int r = 0; r < SI; ++r) {
+            const int64_t i = base + (int64_t)r * WAVE + lane;
+            const bool valid = i < n;
+            key[r] = valid ? sk[i] : 0;
+            val[r] = valid ? sv[i] : 0;
+            const int dg = (int)((key[r] >> shift) & 255u);
+            dig[r] = dg;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = __ballot((dg >> b) & 1);
+                peers &= ((dg >> b) & 1) ? bb : ~bb;
+            }
+            int before = 0;
+            if (valid) before = wcount[w][dg];
+            rank[r] = before + __popcll(peers & lt);
+            if (valid && (peers & lt) == 0) wcount[w][dg] = before + __popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        int32_t tot = 0;
+        {
+            const int dg = threadIdx.x;                      // 256 threads, one digit each
+#pragma unroll
+            for (int k = 0; k < SB / WAVE; ++k) {
+                const int32_t c = wcount[k][dg];
+                wcount[k][dg] = tot;
+                tot += c;
+            }
+        }
+        const int64_t ex = block_exclusive(tot, nullptr);    // (synchronizes the block)
+        doff[threadIdx.x] = (int32_t)ex;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < SI; ++r) {
+            const int64_t i = base + (int64_t)r * WAVE + lane;
+            if (i < n) {
+                const int pos = doff[dig[r]] + wcount[w][dig[r]] + rank[r];
+                sk[pos] = key[r];
+                sv[pos] = val[r];
+            }
+        }
+        __syncthreads();                                     // every scatter done before wcount is cleared
+    }
+    for (int64_t i = threadIdx.x; i < n; i += SB) {
+        keys[i] = sk[i];
+        vals[i] = sv[i];
+    }
+}
+
 __global__ void k_lower_bounds(const uint64_t *keys, int64_t n, int64_t nv, int64_t *out) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v > nv) return;
@@ -224,6 +318,10 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
     *result_in_alt = false;
     if (n <= 1 || key_bits <= 0) return hipSuccess;
     const int64_t nb = (n + ST - 1) / ST;
+    if (nb == 1) {                                           // in place, one launch
+        k_radix_small<<<1, SB, 0, s>>>(keys, vals, n, key_bits);
+        return hipGetLastError();
+    }
     const int64_t nc = 256 * nb;
     char *t = (char *)temp;
     int32_t *counts = (int32_t *)t;
