@@ -1190,7 +1190,7 @@ __global__ void __launch_bounds__(256) k_band_collect(const TileItem *__restrict
         if (lane >= o) incl += y;
     }
     const int total = __shfl(incl, WAVE - 1, WAVE);
-    const int seg = (int)(t % nseg);
+    const int seg = (int)((t >> 5) % nseg);
     unsigned long long b = 0;
     if (lane == 0) b = atomicAdd(&band_n[seg], (unsigned long long)total);
     const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)b);
