@@ -165,6 +165,10 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
     const bool vec = (a.d & 3) == 0;                       // rows start 16-byte aligned
     char *row = (char *)a.panel + s * panel_row_stride(a.prec, a.dp);
     double nx = 0, hh = 0, ll = 0, xt = 0, rr = 0;
+    // the power-of-two scale in FP32 when it is a normal float: the product
+    // is then the same correctly rounded value as through FP64
+    const bool fsc = a.scale >= 0x1.0p-126 && a.scale <= 0x1.0p127;
+    const float scf = (float)a.scale;
     for (int j0 = 4 * sub; j0 < a.dp; j0 += 4 * PK_LANES) {   // dp is a multiple of 32
         float v[4];
         if (vec && j0 + 4 <= a.d) {
@@ -177,8 +181,8 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
         float xs[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            xs[q] = (float)((double)v[q] * a.scale);        // exact power-of-two scaling
-            nx += (double)xs[q] * (double)xs[q];
+            xs[q] = fsc ? v[q] * scf : (float)((double)v[q] * a.scale);   // power-of-two scaling
+            nx = __builtin_fma((double)xs[q], (double)xs[q], nx);        // the square is exact
         }
         if (a.prec == P_FP32) {
             if (live) *(float4 *)(row + (int64_t)j0 * 4) = make_float4(xs[0], xs[1], xs[2], xs[3]);
@@ -194,10 +198,11 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs a) {
                 lo = (double)(bf ? bf16_round(rem, &lb[q]) : fp16_round(rem, &lb[q]));
             }
             const double hd = (double)h, r = (double)xs[q] - hd - lo;   // exact in FP64
-            hh += hd * hd;
-            ll += lo * lo;
-            xt += (hd + lo) * (hd + lo);
-            rr += r * r;
+            const double hl = hd + lo;                       // exact; every square below is too
+            hh = __builtin_fma(hd, hd, hh);
+            ll = __builtin_fma(lo, lo, ll);
+            xt = __builtin_fma(hl, hl, xt);
+            rr = __builtin_fma(r, r, rr);
         }
         // split rows interleave 16 hi and 16 lo values per group of 16 coordinates
         const int64_t at = split ? (int64_t)(j0 >> 4) * 32 + (j0 & 15) : j0;

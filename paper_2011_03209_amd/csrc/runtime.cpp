@@ -1311,8 +1311,9 @@ Phase run_pipeline(mapper_context *ctx, const mapper_cloud *cloud, const mapper_
     }
     const int dp = panel_dp(prec, d);
     const uint64_t stride = (uint64_t)panel_row_stride(prec, dp);
-    // band list: nseg segments, a tile's pairs going to segment blockIdx %
-    // nseg; grown and the tiles redone if a segment overflows
+    // band list: nseg segments (the tile pair form: 32 consecutive tile
+    // pairs to a segment; the macro form: workgroup index mod nseg); grown
+    // and collected again (macro: tiled again) if a segment overflows
     const int nseg = 8 * ((2 * ctx->cus + 7) / 8);          // two per CU, a multiple of the 8 XCDs
     int64_t band_cap = std::min<int64_t>(std::max<int64_t>(1 << 20, pairs / 256), 1ll << 28) / nseg;
     band_cap = std::max<int64_t>(band_cap, 1024);

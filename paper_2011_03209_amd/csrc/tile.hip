@@ -1162,8 +1162,9 @@ __global__ void __launch_bounds__(256) k_knn_lists(int32_t T, int64_t n, int32_t
 // wn * 32 + l % 32; bit 31 - v for value v of accumulator block 0, bit
 // 15 - v for block 1, on the rows of the accumulator layout.  A tile pair
 // with any band bit reserves its records with one atomic on its segment
-// (tile pair index mod nseg) and every lane writes its own; past band_cap
-// they are only counted.
+// (segment (t / 32) mod nseg for tile pair t: 32 consecutive tile pairs
+// share one, so their records and rows stay together for the recheck) and
+// every lane writes its own; past band_cap they are only counted.
 __global__ void __launch_bounds__(256) k_band_collect(const TileItem *__restrict__ items, int64_t n_items,
                                                       const uint32_t *__restrict__ bandmask, int32_t n_levels,
                                                       uint64_t level_words, BandPair *__restrict__ band,
