@@ -43,23 +43,38 @@ __global__ void __launch_bounds__(LB) k_lens_rows(const float *__restrict__ X, i
     const int64_t row0 = (int64_t)blockIdx.x * LB;
     const int64_t my = row0 + threadIdx.x;
     double acc = 0.0;
+    // full slabs of rows with 16-byte alignment: 8 threads cover a slab's 128
+    // bytes of a row, and the next slab's loads are issued before this one's
+    // sums (they land while the chains run)
+    constexpr int NQ = LB * LC / 4 / 256;
+    const bool vec = (d & 3) == 0;
+    float4 pre[NQ];
+    auto load_slab = [&](int32_t c0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int idx = q * 256 + threadIdx.x;
+            const int r = idx / (LC / 4), j = 4 * (idx % (LC / 4));
+            const int64_t gr = row0 + r;
+            pre[q] = gr < n ? *(const float4 *)(X + gr * d + c0 + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (vec && d >= LC) load_slab(0);
     for (int32_t c0 = 0; c0 < d; c0 += LC) {
         const int cw = (d - c0) < LC ? (d - c0) : LC;
-        if ((d & 3) == 0 && cw == LC) {
-            // 16-byte loads: 8 threads cover the slab's 128 bytes of a row
-            for (int q = 0; q < LB * LC / 4 / 256; ++q) {
+        if (vec && cw == LC) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
                 const int idx = q * 256 + threadIdx.x;
                 const int r = idx / (LC / 4), j = 4 * (idx % (LC / 4));
-                const int64_t gr = row0 + r;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (gr < n) v = *(const float4 *)(X + gr * d + c0 + j);
-                tile[r][j] = v.x;
-                tile[r][j + 1] = v.y;
-                tile[r][j + 2] = v.z;
-                tile[r][j + 3] = v.w;
+                tile[r][j] = pre[q].x;
+                tile[r][j + 1] = pre[q].y;
+                tile[r][j + 2] = pre[q].z;
+                tile[r][j + 3] = pre[q].w;
             }
+            if (c0 + 2 * LC <= d) load_slab(c0 + LC);
         } else {
             // coalesced load: 32 consecutive floats of a row per 32 threads
+#pragma unroll 4
             for (int q = 0; q < LB * LC / 256; ++q) {
                 const int idx = q * 256 + threadIdx.x;
                 const int r = idx / LC, j = idx % LC;
@@ -72,17 +87,20 @@ __global__ void __launch_bounds__(LB) k_lens_rows(const float *__restrict__ X, i
         if (kind == 3 && threadIdx.x < LC) vdir[threadIdx.x] = threadIdx.x < cw ? (double)dir[c0 + threadIdx.x] : 0.0;
         __syncthreads();
         if (my < n) {
-            if (kind == 1) {            // L2: sum of exact squares, in order
+            if (kind == 1) {            // L2: sum of exact squares, in order (the fma adds the exact square)
+#pragma unroll 4
                 for (int j = 0; j < cw; ++j) {
                     const double x = (double)tile[threadIdx.x][j];
-                    acc = acc + x * x;
+                    acc = __builtin_fma(x, x, acc);
                 }
             } else if (kind == 3) {     // projection: sum of exact products, in order
+#pragma unroll 4
                 for (int j = 0; j < cw; ++j) {
                     const double x = (double)tile[threadIdx.x][j];
-                    acc = acc + x * vdir[j];
+                    acc = __builtin_fma(x, vdir[j], acc);
                 }
             } else {                    // L-infinity
+#pragma unroll 4
                 for (int j = 0; j < cw; ++j) {
                     const double x = fabs((double)tile[threadIdx.x][j]);
                     acc = x > acc ? x : acc;
