@@ -478,6 +478,22 @@ def test_band_list_regrows(ctx):
     same_graph(g, oracle_graph(w.X, params))
 
 
+@pytest.mark.parametrize("n_pairs", [1023, 1024, 1025, 2047, 2048, 2049])
+def test_sort_and_scan_sizes(ctx, n_pairs):
+    """Well-separated pairs of points in one interval, minPts 2: every pair is
+    a node, so the root sort sees n_pairs keys and the membership sorts and
+    scans 2 n_pairs, on both sides of 2048, the largest count that one
+    workgroup sorts or scans alone."""
+    rng = np.random.default_rng(n_pairs)
+    centers = rng.permutation(np.arange(4 * n_pairs))[:n_pairs, None] * np.ones((1, 8)) * 10.0
+    centers[:, 1:] += rng.normal(scale=0.01, size=(n_pairs, 7))
+    X = np.concatenate([centers + 0.1, centers - 0.1]).astype(np.float32)
+    params = synth.Params([synth.Axis(synth.LENS_COLUMN, 1, 0.0, column=0)], eps=1.0, min_pts=2,
+                          precision=synth.PREC_BF16X3)
+    g, ref = run_and_compare(ctx, X, params)
+    assert g.n_nodes == n_pairs
+
+
 @pytest.mark.parametrize("case", ["mix1d", "grid2d_one_axis", "ties", "fewer_points_than_intervals"])
 def test_balanced_cover(ctx, case):
     """The balanced cover (intervals holding equal numbers of points): the
