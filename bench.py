@@ -191,8 +191,8 @@ def main():
                          "size, used to scale FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design note, not a run)"}))
+        print(json.dumps({"error": "the bench measures one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is designed, not run)"}))
         sys.exit(2)
     if args.serve:
         from paper_2011_03209_amd import serve
