@@ -235,9 +235,12 @@ mapper_status mapper_run_sweep(mapper_context *ctx, const mapper_cloud *cloud, c
  * counted with multiplicity; D is the FP64 chain of the eps tiles (x_j - y_j
  * in FP64, fma in coordinate order), so the result is exact and does not
  * depend on `precision` (a MAPPER_PREC_*, AUTO = FP16), which only sets
- * the matrix-core screening pass.  1 <= k <= min(16, n - 1).  stats may be
- * NULL; ms_tiles is the two screening passes, ms_recheck the FP64 step,
- * band_pairs the candidate pairs it evaluated. */
+ * the matrix-core screening pass.  On a cloud with cells (see
+ * MAPPER_FLAG_NO_SCREEN) each pass takes only the 128-row column blocks the
+ * cells' distance bounds leave; the result is the same.  1 <= k <= min(16,
+ * n - 1).  stats may be NULL; ms_tiles is the two screening passes, tiles
+ * the block pairs they took, ms_recheck the FP64 step, band_pairs the
+ * candidate pairs it evaluated. */
 mapper_status mapper_knn_d2(mapper_context *ctx, const mapper_cloud *cloud, int32_t k,
                             int32_t precision, double *out_d2, mapper_run_stats *stats);
 
