@@ -64,6 +64,16 @@ def test_background_outliers(ctx, k):
     run(ctx, X, k, synth.PREC_FP16)
 
 
+@pytest.mark.parametrize("k", [1, 7, 16])
+def test_clusters_on_a_line(ctx, k):
+    """Separated clusters in 8 dimensions: the screened passes take few
+    blocks and the values are the oracle's."""
+    X = clusters_on_a_line()
+    st = run(ctx, X, k, synth.PREC_BF16X3)
+    T = (X.shape[0] + 127) // 128
+    assert st["tiles"] < T * T, st
+
+
 def test_isolated_last_block(ctx):
     """Three isolated points (the outlier cell) end the slot order alone in
     the last row block, whose own cells hold fewer than k others: pass 1
@@ -129,16 +139,30 @@ def test_cloud_lens_mapper(ctx, kind, k, prec):
     assert g.n_nodes > 1
 
 
-@pytest.mark.parametrize("which", ["mix_d256", "grid_d128_background"])
+def clusters_on_a_line(n_clusters=20, per=300, d=8, seed=77):
+    """Well-separated clusters along a line: a row's farthest points lie in
+    the clusters at the far end, so the largest-distance pass 2 drops the
+    blocks of the clusters near it."""
+    rng = np.random.default_rng(seed)
+    centers = np.zeros((n_clusters, d))
+    centers[:, 0] = 100.0 * np.arange(n_clusters)
+    X = centers[np.repeat(np.arange(n_clusters), per)] + rng.normal(size=(n_clusters * per, d))
+    return X[rng.permutation(X.shape[0])].astype(np.float32)
+
+
+@pytest.mark.parametrize("which", ["mix_d256", "grid_d128_background", "line_d8"])
 def test_eccentricity_screened(ctx, which):
     """The eccentricity lens on clustered clouds, where its passes take only
     the blocks the cells leave (the farthest cells' blocks for the bound,
     then those that may reach it; the background's cell keeps all): every
     value is the square root of the oracle's largest distance, bit for bit."""
-    w = synth.mixture_1m_d256(scale=0.012) if which == "mix_d256" else synth.mixture_500k_d128_2d(scale=0.02)
-    X = w.X
-    params = synth.Params([synth.Axis(synth.LENS_ECCENTRICITY, 10, 0.3)], eps=w.params.eps,
-                          min_pts=w.params.min_pts, precision=synth.PREC_BF16X3)
+    if which == "line_d8":
+        X, eps, min_pts = clusters_on_a_line(), 3.0, 5
+    else:
+        w = synth.mixture_1m_d256(scale=0.012) if which == "mix_d256" else synth.mixture_500k_d128_2d(scale=0.02)
+        X, eps, min_pts = w.X, w.params.eps, w.params.min_pts
+    params = synth.Params([synth.Axis(synth.LENS_ECCENTRICITY, 10, 0.3)], eps=eps, min_pts=min_pts,
+                          precision=synth.PREC_BF16X3)
     print(f"[case] eccentricity {which} n={X.shape[0]} d={X.shape[1]}", flush=True)
     cloud = ctx.cloud(X)
     try:
