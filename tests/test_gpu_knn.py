@@ -41,8 +41,10 @@ def test_precisions(ctx, prec):
 
 @pytest.mark.parametrize("n,d,k,prec", [(300, 3, 1, synth.PREC_FP32), (129, 40, 16, synth.PREC_BF16X3),
                                         (2500, 40, 7, synth.PREC_FP16), (5000, 256, 16, synth.PREC_BF16X3),
-                                        (2, 5, 1, synth.PREC_FP16X3)])
+                                        (2, 5, 1, synth.PREC_FP16X3), (1500, 1024, 3, synth.PREC_FP16),
+                                        (1500, 2100, 3, synth.PREC_BF16X3)])
 def test_shapes(ctx, n, d, k, prec):
+    # d = 1024: cells of at most 16 landmarks; d = 2100: no cells (every block)
     X = np.random.default_rng(n + d).normal(size=(n, d)).astype(np.float32)
     run(ctx, X, k, prec)
 
