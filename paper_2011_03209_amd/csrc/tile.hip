@@ -751,8 +751,9 @@ __global__ void k_build_macro_items(TileTable mt, TileTable tt, MacroItem *items
 // ------------------------------------------------------------------- k-NN
 // k-th nearest-neighbour squared distances over the whole cloud (the
 // eps-selection module of the CIFAR-10 use case plots their distribution).
-// Same Gram tiles and certified error bound as the eps tiles, over the full
-// T x T grid of 128-row blocks: with hU_s >= |x_s|^2/2 + e_s and
+// Same Gram tiles and certified error bound as the eps tiles, over the
+// T x T grid of 128-row blocks (on a cloud with cells, over the column
+// blocks k_knn_lists leaves each row block): with hU_s >= |x_s|^2/2 + e_s and
 // hL_s <= |x_s|^2/2 - e_s (the packing thresholds at eps = 0),
 //   L_ij = 2 (hL_i + hL_j - g) <= D_ij <= U_ij = 2 (hU_i + hU_j - g),
 // each evaluated in FP32 with a relative margin 2^-22 (|S| + |g|) that covers
@@ -764,7 +765,7 @@ __global__ void k_build_macro_items(TileTable mt, TileTable tt, MacroItem *items
 // negated values: -L in pass 1 (its smallest is -max L), -U in pass 2, -D
 // in the final step, k = 1.
 //
-// A workgroup owns row block I and a chunk of column blocks.  After each
+// A workgroup owns row block I and a chunk of its column blocks.  After each
 // tile's products the bounds go to LDS (the stage buffers, free by then),
 // row r at rotation r so the row scans below are free of bank conflicts;
 // thread t then scans row t % 128, columns 32 (t / 128) .. + 31.
